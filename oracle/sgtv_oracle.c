@@ -1,0 +1,407 @@
+/*
+ * FP64 CPU oracle for spectrally grouped TV reconstruction with ADMM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file defines what the GPU library must
+ * compute; it is called by the tests, by the package's smoke check and by the
+ * benchmark's CPU-baseline leg, and by nothing on the product path.  It shares
+ * no code, header or table with the GPU library.
+ *
+ * Everything is plain IEEE double arithmetic, loops in fixed index order,
+ * serial, built without fast-math.  Conventions:
+ *
+ *   voxel j = s*Q + q, spatial bin s = iy*nx + ix          (Section II, J = S x Q)
+ *   direction p: 0 = +x, 1 = -x, 2 = +y, 3 = -y            (four spatial neighbours)
+ *   (D f)[s][p][q] = w[s][p][q] * (f[s][q] - f[nb_p(s)][q]), a neighbour outside
+ *   the grid contributes the value zero (Dirichlet, Section III after Eq. 3).
+ *   Arrays indexed by (s, p, q) are stored [s][p][q], q fastest.
+ *   w == NULL means all weights are one.
+ *
+ * Groups: grouping 0 is the paper's spectral group (one group per spatial bin,
+ * over all q and p, Eq. 2); grouping 1 is standard isotropic TV (one group per
+ * (s, q) over p, the comparison regulariser of Section II).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NDIR 4
+
+/* neighbour of spatial bin s in direction p, or -1 when it lies outside */
+static int64_t neighbour(int ny, int nx, int64_t s, int p)
+{
+    int64_t iy = s / nx, ix = s % nx;
+    switch (p) {
+    case 0: return ix + 1 < nx ? s + 1 : -1;
+    case 1: return ix - 1 >= 0 ? s - 1 : -1;
+    case 2: return iy + 1 < ny ? s + nx : -1;
+    default: return iy - 1 >= 0 ? s - nx : -1;
+    }
+}
+
+static double weight(const double *w, int Q, int64_t s, int p, int q)
+{
+    return w ? w[(s * NDIR + p) * Q + q] : 1.0;
+}
+
+/* Eq. 1 mean: p = A f + r, A in CSR. */
+void or_forward(int64_t I, const int64_t *rowptr, const int32_t *col, const double *val,
+                const double *f, const double *r, double *p)
+{
+    for (int64_t i = 0; i < I; ++i) {
+        double acc = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            acc += val[k] * f[col[k]];
+        p[i] = acc + (r ? r[i] : 0.0);
+    }
+}
+
+/* e = A^T t, accumulated row by row in CSR order. */
+void or_back(int64_t I, int64_t J, const int64_t *rowptr, const int32_t *col,
+             const double *val, const double *t, double *e)
+{
+    for (int64_t j = 0; j < J; ++j)
+        e[j] = 0.0;
+    for (int64_t i = 0; i < I; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            e[col[k]] += val[k] * t[i];
+}
+
+/* g = w .* (G f), the stacked finite differences of Eq. 3. */
+void or_diff(int ny, int nx, int Q, const double *w, const double *f, double *g)
+{
+    int64_t S = (int64_t)ny * nx;
+    for (int64_t s = 0; s < S; ++s)
+        for (int p = 0; p < NDIR; ++p) {
+            int64_t nb = neighbour(ny, nx, s, p);
+            for (int q = 0; q < Q; ++q) {
+                double other = nb >= 0 ? f[nb * Q + q] : 0.0;
+                g[(s * NDIR + p) * Q + q] = weight(w, Q, s, p, q) * (f[s * Q + q] - other);
+            }
+        }
+}
+
+/* out = (w .* G)^T t: each difference row adds +w*t to its own voxel and -w*t
+ * to its in-grid neighbour. */
+void or_diff_adj(int ny, int nx, int Q, const double *w, const double *t, double *out)
+{
+    int64_t S = (int64_t)ny * nx;
+    for (int64_t j = 0; j < S * Q; ++j)
+        out[j] = 0.0;
+    for (int64_t s = 0; s < S; ++s)
+        for (int p = 0; p < NDIR; ++p) {
+            int64_t nb = neighbour(ny, nx, s, p);
+            for (int q = 0; q < Q; ++q) {
+                double v = weight(w, Q, s, p, q) * t[(s * NDIR + p) * Q + q];
+                out[s * Q + q] += v;
+                if (nb >= 0)
+                    out[nb * Q + q] -= v;
+            }
+        }
+}
+
+/* De Pierro curvature of the quadratic penalty (Section III, image update):
+ * every difference row rho spreads over its voxels with weights
+ * |D_rho,j| / ||D_rho||_1, which yields H_j = lam * sum_rho |D_rho,j| ||D_rho||_1. */
+void or_curv(int ny, int nx, int Q, const double *w, double lam, double *H)
+{
+    int64_t S = (int64_t)ny * nx;
+    for (int64_t j = 0; j < S * Q; ++j)
+        H[j] = 0.0;
+    for (int64_t s = 0; s < S; ++s)
+        for (int p = 0; p < NDIR; ++p) {
+            int64_t nb = neighbour(ny, nx, s, p);
+            for (int q = 0; q < Q; ++q) {
+                double a = fabs(weight(w, Q, s, p, q));
+                double l1 = nb >= 0 ? 2.0 * a : a;
+                H[s * Q + q] += a * l1;
+                if (nb >= 0)
+                    H[nb * Q + q] += a * l1;
+            }
+        }
+    for (int64_t j = 0; j < S * Q; ++j)
+        H[j] *= lam;
+}
+
+/* Nonnegative root of H t^2 + B t - C = 0 (C >= 0, H > 0), the stationary
+ * point of the separable surrogate of one hyper-voxel.  The branch choice
+ * avoids cancellation.  H == 0 (no penalty curvature) reduces to t = C / B. */
+double or_root(double H, double B, double C)
+{
+    if (H == 0.0)
+        return B > 0.0 ? C / B : 0.0;
+    double disc = sqrt(B * B + 4.0 * H * C);
+    if (B <= 0.0)
+        return (-B + disc) / (2.0 * H);
+    return 2.0 * C / (B + disc);
+}
+
+/* Proximal map of thr * ||.||_2 on one group (Eq. 5): block soft-threshold.
+ * Ties (norm == thr) and empty groups give zero. */
+static void shrink_group(int n, const double *v, int64_t stride, double thr, double *d)
+{
+    double ss = 0.0;
+    for (int k = 0; k < n; ++k)
+        ss += v[k * stride] * v[k * stride];
+    double nrm = sqrt(ss);
+    double scale = nrm > thr ? 1.0 - thr / nrm : 0.0;
+    for (int k = 0; k < n; ++k)
+        d[k * stride] = scale * v[k * stride];
+}
+
+/* d = prox of (beta/lam) R applied to v, v and d laid out [s][p][q]. */
+void or_shrink(int ny, int nx, int Q, int grouping, double thr, const double *v, double *d)
+{
+    int64_t S = (int64_t)ny * nx;
+    if (grouping == 0) {
+        for (int64_t s = 0; s < S; ++s)
+            shrink_group(NDIR * Q, v + s * NDIR * Q, 1, thr, d + s * NDIR * Q);
+    } else {
+        for (int64_t s = 0; s < S; ++s)
+            for (int q = 0; q < Q; ++q)
+                shrink_group(NDIR, v + s * NDIR * Q + q, Q, thr, d + s * NDIR * Q + q);
+    }
+}
+
+/* R applied to a stacked difference vector g: sum of group 2-norms (Eq. 2). */
+double or_group_norm_sum(int ny, int nx, int Q, int grouping, const double *g)
+{
+    int64_t S = (int64_t)ny * nx;
+    double tot = 0.0;
+    for (int64_t s = 0; s < S; ++s) {
+        if (grouping == 0) {
+            double ss = 0.0;
+            for (int k = 0; k < NDIR * Q; ++k)
+                ss += g[s * NDIR * Q + k] * g[s * NDIR * Q + k];
+            tot += sqrt(ss);
+        } else {
+            for (int q = 0; q < Q; ++q) {
+                double ss = 0.0;
+                for (int p = 0; p < NDIR; ++p) {
+                    double v = g[(s * NDIR + p) * Q + q];
+                    ss += v * v;
+                }
+                tot += sqrt(ss);
+            }
+        }
+    }
+    return tot;
+}
+
+/* Negative Poisson log-likelihood of Eq. 1 written as an I-divergence:
+ * sum_i p_i - y_i + y_i log(y_i / p_i), with 0 log 0 = 0.  It differs from
+ * the plain negative log-likelihood by a constant of the data only. */
+double or_data_term(int64_t I, const double *p, const double *y)
+{
+    double tot = 0.0;
+    for (int64_t i = 0; i < I; ++i) {
+        double t = p[i] - y[i];
+        if (y[i] > 0.0)
+            t += y[i] * log(y[i] / p[i]);
+        tot += t;
+    }
+    return tot;
+}
+
+typedef struct {
+    int64_t I;
+    int ny, nx, Q;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *y, *r;
+    const double *w;
+    double beta, lam;
+    int grouping;
+} or_problem;
+
+static int64_t n_vox(const or_problem *P) { return (int64_t)P->ny * P->nx * P->Q; }
+
+/* objective of Eq. 3 evaluated at d = w.*Gf: data term + beta * R(w.*Gf) */
+void or_objective(const or_problem *P, const double *f, double out[3])
+{
+    int64_t J = n_vox(P);
+    double *p = malloc(sizeof(double) * (P->I > 0 ? P->I : 1));
+    double *g = malloc(sizeof(double) * (J * NDIR > 0 ? J * NDIR : 1));
+    or_forward(P->I, P->rowptr, P->col, P->val, f, P->r, p);
+    double data = or_data_term(P->I, p, P->y);
+    or_diff(P->ny, P->nx, P->Q, P->w, f, g);
+    double tv = or_group_norm_sum(P->ny, P->nx, P->Q, P->grouping, g);
+    out[0] = data + P->beta * tv;
+    out[1] = data;
+    out[2] = tv;
+    free(p);
+    free(g);
+}
+
+/* Image update of Eq. 4, one pass of optimisation transfer from g:
+ *   EM surrogate of L at g (sensitivity s = A^T 1, back-projected ratio e),
+ *   De Pierro surrogate of (lam/2)||D f - z||^2 at g (gradient gam, curvature H),
+ *   every hyper-voxel then solves its own 1-D problem in closed form. */
+void or_image_sweep(const or_problem *P, const double *sens, const double *H, const double *z,
+                    double *g)
+{
+    int64_t J = n_vox(P), I = P->I;
+    double *p = malloc(sizeof(double) * (I > 0 ? I : 1));
+    double *e = malloc(sizeof(double) * (J > 0 ? J : 1));
+    double *t = malloc(sizeof(double) * (J * NDIR > 0 ? J * NDIR : 1));
+    double *gam = malloc(sizeof(double) * (J > 0 ? J : 1));
+    or_forward(I, P->rowptr, P->col, P->val, g, P->r, p);
+    for (int64_t i = 0; i < I; ++i)
+        p[i] = P->y[i] / p[i];
+    or_back(I, J, P->rowptr, P->col, P->val, p, e);
+    or_diff(P->ny, P->nx, P->Q, P->w, g, t);
+    for (int64_t k = 0; k < J * NDIR; ++k)
+        t[k] -= z[k];
+    or_diff_adj(P->ny, P->nx, P->Q, P->w, t, gam);
+    for (int64_t j = 0; j < J; ++j) {
+        double B = sens[j] + P->lam * gam[j] - H[j] * g[j];
+        double C = g[j] * e[j];
+        g[j] = or_root(H[j], B, C);
+    }
+    free(p);
+    free(e);
+    free(t);
+    free(gam);
+}
+
+/* Sensitivity s = A^T 1. */
+void or_sensitivity(const or_problem *P, double *sens)
+{
+    int64_t J = n_vox(P);
+    double *ones = malloc(sizeof(double) * (P->I > 0 ? P->I : 1));
+    for (int64_t i = 0; i < P->I; ++i)
+        ones[i] = 1.0;
+    or_back(P->I, J, P->rowptr, P->col, P->val, ones, sens);
+    free(ones);
+}
+
+/* Uniform start kappa*1 matching total counts: kappa = sum(y) / sum(s). */
+double or_plain_init(const or_problem *P)
+{
+    int64_t J = n_vox(P);
+    double *sens = malloc(sizeof(double) * (J > 0 ? J : 1));
+    or_sensitivity(P, sens);
+    double sy = 0.0, ss = 0.0;
+    for (int64_t i = 0; i < P->I; ++i)
+        sy += P->y[i];
+    for (int64_t j = 0; j < J; ++j)
+        ss += sens[j];
+    free(sens);
+    return ss > 0.0 ? sy / ss : 0.0;
+}
+
+/*
+ * ADMM / split Bregman of Eqs. 4-6 for n_iter iterations, state (f, d, c) in
+ * place.  Each image update runs `sweeps` passes of optimisation transfer
+ * with z = d^k - c^k held fixed.  After iteration k+1 the row
+ * report[5k..5k+4] holds the objective of f^{k+1}, its data and TV parts,
+ * the primal residual ||w.*Gf - d|| and the dual residual lam ||D^T(d^{k+1}-d^k)||.
+ */
+int or_admm(const or_problem *P, int n_iter, int sweeps, double *f, double *d, double *c,
+            double *report)
+{
+    int64_t J = n_vox(P), JN = J * NDIR;
+    double *sens = malloc(sizeof(double) * (J > 0 ? J : 1));
+    double *H = malloc(sizeof(double) * (J > 0 ? J : 1));
+    double *z = malloc(sizeof(double) * (JN > 0 ? JN : 1));
+    double *v = malloc(sizeof(double) * (JN > 0 ? JN : 1));
+    double *dn = malloc(sizeof(double) * (JN > 0 ? JN : 1));
+    double *tmp = malloc(sizeof(double) * (J > 0 ? J : 1));
+    if (!sens || !H || !z || !v || !dn || !tmp)
+        return -1;
+    or_sensitivity(P, sens);
+    or_curv(P->ny, P->nx, P->Q, P->w, P->lam, H);
+    for (int k = 0; k < n_iter; ++k) {
+        for (int64_t m = 0; m < JN; ++m)
+            z[m] = d[m] - c[m];
+        for (int sw = 0; sw < sweeps; ++sw)
+            or_image_sweep(P, sens, H, z, f);
+        or_diff(P->ny, P->nx, P->Q, P->w, f, v);
+        for (int64_t m = 0; m < JN; ++m)
+            v[m] += c[m];
+        or_shrink(P->ny, P->nx, P->Q, P->grouping, P->beta / P->lam, v, dn);
+        double rp = 0.0, rd = 0.0;
+        for (int64_t m = 0; m < JN; ++m) {
+            double cn = v[m] - dn[m];          /* c^k + Df^{k+1} - d^{k+1}   (Eq. 6) */
+            double prim = cn - c[m];           /* = Df^{k+1} - d^{k+1}            */
+            rp += prim * prim;
+            c[m] = cn;
+            z[m] = dn[m] - d[m];               /* reuse z for d^{k+1} - d^k       */
+            d[m] = dn[m];
+        }
+        or_diff_adj(P->ny, P->nx, P->Q, P->w, z, tmp);
+        for (int64_t j = 0; j < J; ++j)
+            rd += tmp[j] * tmp[j];
+        if (report) {
+            double obj[3];
+            or_objective(P, f, obj);
+            report[5 * k + 0] = obj[0];
+            report[5 * k + 1] = obj[1];
+            report[5 * k + 2] = obj[2];
+            report[5 * k + 3] = sqrt(rp);
+            report[5 * k + 4] = P->lam * sqrt(rd);
+        }
+    }
+    free(sens);
+    free(H);
+    free(z);
+    free(v);
+    free(dn);
+    free(tmp);
+    return 0;
+}
+
+/* Flat-argument entry points for ctypes. */
+static or_problem make_problem(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
+                               const int32_t *col, const double *val, const double *y,
+                               const double *r, const double *w, double beta, double lam,
+                               int grouping)
+{
+    or_problem P;
+    P.I = I; P.ny = ny; P.nx = nx; P.Q = Q;
+    P.rowptr = rowptr; P.col = col; P.val = val;
+    P.y = y; P.r = r; P.w = w;
+    P.beta = beta; P.lam = lam; P.grouping = grouping;
+    return P;
+}
+
+int or_admm_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr, const int32_t *col,
+                 const double *val, const double *y, const double *r, const double *w,
+                 double beta, double lam, int grouping, int n_iter, int sweeps,
+                 double *f, double *d, double *c, double *report)
+{
+    or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, r, w, beta, lam, grouping);
+    return or_admm(&P, n_iter, sweeps, f, d, c, report);
+}
+
+void or_objective_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
+                       const int32_t *col, const double *val, const double *y, const double *r,
+                       const double *w, double beta, int grouping, const double *f, double *out)
+{
+    or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, r, w, beta, 1.0, grouping);
+    or_objective(&P, f, out);
+}
+
+void or_image_sweep_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
+                         const int32_t *col, const double *val, const double *y,
+                         const double *r, const double *w, double lam, const double *z,
+                         double *g)
+{
+    or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, r, w, 0.0, lam, 0);
+    int64_t J = n_vox(&P);
+    double *sens = malloc(sizeof(double) * (J > 0 ? J : 1));
+    double *H = malloc(sizeof(double) * (J > 0 ? J : 1));
+    or_sensitivity(&P, sens);
+    or_curv(ny, nx, Q, w, lam, H);
+    or_image_sweep(&P, sens, H, z, g);
+    free(sens);
+    free(H);
+}
+
+double or_plain_init_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
+                          const int32_t *col, const double *val, const double *y)
+{
+    or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, NULL, NULL, 0.0, 1.0, 0);
+    return or_plain_init(&P);
+}
