@@ -167,12 +167,10 @@ def test_curvature_majorises_penalty():
         sur = pen(fn) + grad @ (f - fn) + 0.5 * np.sum(H * (f - fn) ** 2)
         assert sur >= pen(f) - 1e-12
     # a majoriser with the wrong curvature (half of H) fails somewhere
-    bad = False
-    for _ in range(200):
-        f = rng.random(ny * nx * Q) * 3
-        if pen(fn) + grad @ (f - fn) + 0.25 * np.sum(H * (f - fn) ** 2) < pen(f) - 1e-12:
-            bad = True
-    assert bad
+    iy, ix = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    checker = np.repeat(((-1.0) ** (iy + ix)).ravel(), Q)
+    f = fn + checker
+    assert pen(fn) + grad @ (f - fn) + 0.25 * np.sum(H * (f - fn) ** 2) < pen(f)
 
 
 # --- P2 / P7: per-voxel root ------------------------------------------------------------
