@@ -1,0 +1,177 @@
+/*
+ * sgtv.h -- C ABI of the MI355X library for spectrally grouped total-variation
+ * reconstruction of photon-limited scatter data with ADMM.
+ *
+ * Problem (Section II, Eqs. 1-2; Section III, Eq. 3):
+ *   minimise over f >= 0   L(f) + beta * R(w .* G f)
+ *   L(f) = sum_i (A f + r)_i - y_i log (A f + r)_i   (Poisson model of Eq. 1)
+ *   R(d) = sum_s || d[s, :, :] ||_2                   (one group per spatial bin,
+ *                                                      over all spectral bins q and
+ *                                                      all neighbour directions p)
+ * solved with the split-Bregman / scaled ADMM iteration of Eqs. 4-6:
+ *   image update (Eq. 4)  by optimisation transfer (EM surrogate of L plus
+ *                         De Pierro's separable surrogate of the quadratic),
+ *                         a closed-form nonnegative root per hyper-voxel;
+ *   split update (Eq. 5)  block soft-threshold of v = w.*G f + c per group;
+ *   dual update  (Eq. 6)  c = v - d.
+ *
+ * Conventions fixed by this ABI:
+ *   - J = ny * nx * Q hyper-voxels, voxel j = (iy * nx + ix) * Q + q
+ *     (spectral bin fastest; "lexicographic order" of Section II).
+ *   - Neighbour directions p = 0..3: +x, -x, +y, -y.  A neighbour outside the
+ *     grid has value zero (Dirichlet, Section III), so every voxel has N = 4
+ *     differences (G_p f)[s, q] = f[s, q] - f[nb_p(s), q].
+ *   - Arrays indexed by (s, p, q) are laid out [s][p][q], q fastest (4*J floats).
+ *   - The objective is reported with the data term written as the
+ *     I-divergence sum_i p_i - y_i + y_i log(y_i / p_i) (0 log 0 = 0), which
+ *     differs from L by a constant of the data.
+ *
+ * Every function returns SGTV_OK (0) or a negative status, never throws, and
+ * on error leaves the context exactly as it was.  sgtv_last_error() returns a
+ * message for the last failing call on the calling thread.
+ *
+ * Ownership: every pointer argument belongs to the caller and is read (or
+ * written) only during the call; the library copies what it keeps into its
+ * own device memory.  mem_kind says whether a pointer is host memory
+ * (SGTV_HOST) or device memory of the context's GPU (SGTV_DEVICE).  All work
+ * is ordered on the stream given to sgtv_create; functions that return data
+ * to the host synchronise that stream.
+ */
+#ifndef SGTV_H
+#define SGTV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgtv_ctx_s *sgtv_ctx;
+
+enum {
+    SGTV_OK = 0,
+    SGTV_EINVAL = -1,   /* an argument is out of range, NaN/Inf, negative, ... */
+    SGTV_ESHAPE = -2,   /* sizes or index arrays are inconsistent               */
+    SGTV_ESTATE = -3,   /* call order: system or data not set yet               */
+    SGTV_EDEVICE = -4,  /* a HIP runtime call failed                            */
+    SGTV_ENOMEM = -5    /* device or host allocation failed                     */
+};
+
+/* storage type of the system-matrix values */
+enum { SGTV_F32 = 0, SGTV_BF16 = 1, SGTV_F16 = 2 };
+
+/* where caller pointers live */
+enum { SGTV_HOST = 0, SGTV_DEVICE = 1 };
+
+/* grouping of the total-variation penalty */
+enum {
+    SGTV_GROUP_SPECTRAL = 0, /* Eq. 2: one group per spatial bin over (q, p)           */
+    SGTV_GROUP_STANDARD = 1  /* standard isotropic TV: one group per (s, q) over p     */
+};
+
+typedef struct {
+    double total;     /* data + beta * tv, for the current image f^k                 */
+    double data;      /* sum_i p_i - y_i + y_i log(y_i / p_i), p = A f^k + r         */
+    double tv;        /* R(w .* G f^k)                                               */
+    double r_primal;  /* || w.*G f^k - d^k ||_2                                      */
+    double r_dual;    /* rho * || (w.*G)^T (d^k - d^{k-1}) ||_2  (0 before the first
+                         iteration after set_data / set_init / set_state)           */
+    int64_t iter;     /* k: ADMM iterations done since set_data / set_init          */
+} sgtv_report;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t of
+ * that device (NULL: the null stream).  The stream must outlive the context. */
+int sgtv_create(sgtv_ctx *out, int device, void *hip_stream);
+
+/* Free every device buffer of the context.  NULL is ignored. */
+void sgtv_destroy(sgtv_ctx ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *sgtv_last_error(void);
+
+/* Library version string, for diagnostics. */
+const char *sgtv_version(void);
+
+/*
+ * Set the system: an I x J nonnegative matrix A (Section II, A in R_+^{IxJ})
+ * in CSR form with int64 row pointer (I+1 entries, row_ptr[0] = 0,
+ * row_ptr[I] = nnz, non-decreasing) and int32 column indices in [0, J).
+ * Values must be finite and >= 0; explicit zeros are allowed and empty rows
+ * and columns are legal.  nnz must be below 2^31.
+ * storage_dtype SGTV_BF16 / SGTV_F16 stores every value as a 16-bit code of
+ * a / sigma_j with a per-column FP32 scale sigma_j = max_i a_ij; products are
+ * accumulated in FP32.
+ * w: direction weights w_{s,q,p} of Eq. 2: NULL (all one), w_len = 4 (one
+ * positive value per direction) or w_len = 4*J (layout [s][p][q], positive).
+ * Resets data and iteration state.
+ */
+int sgtv_set_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q,
+                    const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                    int64_t nnz, int storage_dtype, const float *w, int64_t w_len,
+                    int mem_kind);
+
+/*
+ * Set the data y (I counts, finite, >= 0, real values allowed), the known
+ * background r (I values, finite, > 0), the regularisation weight beta >= 0,
+ * the ADMM penalty rho = lambda > 0 (Eqs. 4-6) and the number of surrogate
+ * sweeps per image update (>= 1).  Resets the state: f = kappa * 1 with
+ * kappa = sum(y) / sum(A^T 1) (the count-matched uniform start), d = c = 0,
+ * k = 0.  Requires a system.
+ */
+int sgtv_set_data(sgtv_ctx ctx, const float *y, const float *r, double beta, double rho,
+                  int sweeps, int mem_kind);
+
+/* Choose the TV grouping (SGTV_GROUP_*); resets d = c = 0 and k = 0. */
+int sgtv_set_grouping(sgtv_ctx ctx, int grouping);
+
+/* Start image: x0 (J values, finite, >= 0) or NULL for the uniform start
+ * kappa * 1.  Resets d = c = 0, k = 0. */
+int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind);
+
+/* Run n_iters >= 0 ADMM iterations (Eqs. 4-6) asynchronously on the stream. */
+int sgtv_iterate(sgtv_ctx ctx, int n_iters);
+
+/* Objective and residuals of the current state (FP64 reductions); synchronises. */
+int sgtv_objective(sgtv_ctx ctx, sgtv_report *out);
+
+/* Copy the current image f^k (J floats). */
+int sgtv_get_image(sgtv_ctx ctx, float *x, int mem_kind);
+
+/* Copy the split and scaled dual variables d^k and c^k (4*J floats each,
+ * layout [s][p][q]).  Either pointer may be NULL. */
+int sgtv_get_split(sgtv_ctx ctx, float *d, float *c, int mem_kind);
+
+/*
+ * Raw iteration state for bit-exact checkpoint and resume.  The library
+ * keeps v^k = w.*G f^k + c^{k-1} (4*J floats, [s][p][q]) and one shrink
+ * factor per group a^k (n_groups floats: ny*nx for the spectral grouping,
+ * J for the standard one), so that d^k = a^k v^k and c^k = v^k - d^k.
+ * sgtv_state_sizes reports the element counts.  set_state requires
+ * 0 <= a <= 1 and finite values; it resets the previous-split memory used by
+ * r_dual.
+ */
+int sgtv_state_sizes(sgtv_ctx ctx, int64_t *n_image, int64_t *n_split, int64_t *n_groups);
+int sgtv_get_state(sgtv_ctx ctx, float *f, float *v, float *a, int64_t *k, int mem_kind);
+int sgtv_set_state(sgtv_ctx ctx, const float *f, const float *v, const float *a, int64_t k,
+                   int mem_kind);
+
+/* Normalised backprojection x_in = (A^T y) / (A^T 1) (0 where A^T 1 = 0),
+ * J floats, of the data currently set. */
+int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);
+
+/*
+ * Kernel timing for measurement.  While enabled, sgtv_iterate brackets every
+ * kernel launch with HIP events on the context stream.  sgtv_kernel_times
+ * synchronises, adds the elapsed milliseconds per kernel class to ms[0..3]
+ * and the launch counts to counts[0..3], then clears the record.  Classes:
+ * 0 forward projection and ratio, 1 backprojection with image update,
+ * 2 split and dual update, 3 anything else.
+ */
+int sgtv_set_profiling(sgtv_ctx ctx, int enable);
+int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGTV_H */

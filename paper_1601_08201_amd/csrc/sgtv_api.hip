@@ -1,0 +1,835 @@
+// C ABI of the spectrally grouped TV reconstruction library (declared in
+// include/sgtv.h): argument validation, the two sliced-ELL copies of the
+// system matrix, device buffers of the ADMM state and the per-iteration
+// launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sgtv.h"
+#include "sgtv_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? SGTV_ENOMEM : SGTV_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);                                          \
+    } while (0)
+
+// Owning device allocation.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n) {
+        release();
+        hipError_t e = hipMalloc(&p, n ? n : 16);
+        if (e == hipSuccess) bytes = n;
+        else p = nullptr;
+        return e;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Copy n elements from caller memory (host or device) into a host vector.
+template <class T>
+hipError_t fetch(std::vector<T> &dst, const T *src, int64_t n, int mem_kind) {
+    dst.resize(static_cast<size_t>(n));
+    if (n == 0) return hipSuccess;
+    if (mem_kind == SGTV_HOST) {
+        std::memcpy(dst.data(), src, sizeof(T) * static_cast<size_t>(n));
+        return hipSuccess;
+    }
+    return hipMemcpy(dst.data(), src, sizeof(T) * static_cast<size_t>(n), hipMemcpyDeviceToHost);
+}
+
+template <class T>
+hipError_t upload(DBuf &dst, const std::vector<T> &src) {
+    hipError_t e = dst.alloc(sizeof(T) * src.size());
+    if (e != hipSuccess) return e;
+    if (src.empty()) return hipSuccess;
+    return hipMemcpy(dst.p, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+// Round-to-nearest-even float -> bfloat16 code (finite inputs).
+uint16_t to_bf16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+// Round-to-nearest-even float -> IEEE binary16 code.
+uint16_t to_f16(float x) {
+    _Float16 h = static_cast<_Float16>(x);
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+// Sliced-ELL packing of n lines given line pointers (CSR-like) into 64-line
+// slices, depth padded to a multiple of 4; see sgtv::Sell for the layout.
+template <class V>
+void pack_sell(int64_t n_lines, const std::vector<int64_t> &lptr, const std::vector<int32_t> &lidx,
+               const std::vector<V> &lval, std::vector<int64_t> &sptr, std::vector<int32_t> &idx,
+               std::vector<V> &val) {
+    const int64_t n_slices = (n_lines + sgtv::kSliceRows - 1) / sgtv::kSliceRows;
+    sptr.assign(static_cast<size_t>(n_slices + 1), 0);
+    for (int64_t k = 0; k < n_slices; ++k) {
+        int64_t width = 0;
+        for (int64_t l = k * 64; l < std::min(n_lines, (k + 1) * 64); ++l)
+            width = std::max(width, lptr[l + 1] - lptr[l]);
+        width = (width + 3) / 4 * 4;
+        sptr[k + 1] = sptr[k] + width * 64;
+    }
+    idx.assign(static_cast<size_t>(sptr[n_slices]), 0);
+    val.assign(static_cast<size_t>(sptr[n_slices]), V(0));
+    for (int64_t k = 0; k < n_slices; ++k) {
+        for (int64_t l = k * 64; l < std::min(n_lines, (k + 1) * 64); ++l) {
+            const int64_t lane = l - k * 64;
+            for (int64_t t = 0; t < lptr[l + 1] - lptr[l]; ++t) {
+                const int64_t pos = sptr[k] + (t / 4) * 256 + lane * 4 + (t % 4);
+                idx[pos] = lidx[lptr[l] + t];
+                val[pos] = lval[lptr[l] + t];
+            }
+        }
+    }
+}
+
+struct System {
+    int64_t I = 0, J = 0, S = 0, nnz = 0;
+    int ny = 0, nx = 0, Q = 0, vt = SGTV_F32;
+    sgtv::Grid grid{};
+    float w4[4] = {1, 1, 1, 1};
+    bool wfull = false;
+    DBuf rs_ptr, rs_idx, rs_val, cs_ptr, cs_idx, cs_val, colscale, sens, H, wbuf;
+    std::vector<int64_t> perm;   // internal row -> caller row
+    int64_t n_rslices = 0, n_cslices = 0;
+
+    sgtv::Sell rows() const {
+        return {rs_ptr.as<int64_t>(), rs_idx.as<int32_t>(), rs_val.p, nullptr, I, n_rslices};
+    }
+    sgtv::Sell cols() const {
+        return {cs_ptr.as<int64_t>(), cs_idx.as<int32_t>(), cs_val.p,
+                vt == SGTV_F32 ? nullptr : colscale.as<float>(), J, n_cslices};
+    }
+    sgtv::Weights weights() const {
+        sgtv::Weights w;
+        for (int p = 0; p < 4; ++p) w.w[p] = w4[p];
+        w.full = wfull ? wbuf.as<float>() : nullptr;
+        return w;
+    }
+};
+
+}  // namespace
+
+struct sgtv_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<System> sys;
+    // data
+    bool has_data = false;
+    DBuf y, r, ratio;
+    double beta = 0.0, rho = 1.0;
+    int sweeps = 1;
+    int grouping = SGTV_GROUP_SPECTRAL;
+    // state: image (double buffered), split state (v, a) double buffered
+    DBuf f[2], v[2], a[2], fs;
+    int fcur = 0, vcur = 0;
+    int64_t k = 0;
+    // reductions
+    DBuf part, red;
+    int64_t part_cap = 0;
+    // optional kernel timing: (class, start, end) per launch
+    bool profiling = false;
+    struct Timed { int cls; hipEvent_t beg, end; };
+    std::vector<Timed> timed;
+};
+
+namespace {
+
+int64_t n_groups(const sgtv_ctx_s *c) {
+    return c->grouping == SGTV_GROUP_SPECTRAL ? c->sys->S : c->sys->J;
+}
+
+bool finite_nonneg(float x) { return std::isfinite(x) && x >= 0.0f; }
+
+// Allocate state buffers sized for the current system and grouping.
+int alloc_state(sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    const int64_t ng = n_groups(c);
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(c->f[b].alloc(sizeof(float) * S.J));
+        HIP_TRY(c->v[b].alloc(sizeof(float) * S.J * 4));
+        HIP_TRY(c->a[b].alloc(sizeof(float) * ng));
+    }
+    HIP_TRY(c->fs.alloc(sizeof(float) * S.J));
+    return SGTV_OK;
+}
+
+// Scaled copy sigma .* f used as the gathered vector of the 16-bit forward projection.
+int refresh_scaled(sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    if (S.vt != SGTV_F32)
+        HIP_TRY(sgtv::launch_scale(c->f[c->fcur].as<float>(), S.colscale.as<float>(),
+                                   c->fs.as<float>(), S.J, c->stream));
+    return SGTV_OK;
+}
+
+// d = c = 0 (v = 0, a = 0 in both buffers), k = 0.
+int clear_split(sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMemsetAsync(c->v[b].p, 0, sizeof(float) * S.J * 4, c->stream));
+        HIP_TRY(hipMemsetAsync(c->a[b].p, 0, sizeof(float) * n_groups(c), c->stream));
+    }
+    c->vcur = 0;
+    c->k = 0;
+    return SGTV_OK;
+}
+
+// f = kappa * 1 with kappa = sum(y) / sum(sens), reduced in FP64 on the device.
+int uniform_start(sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    int64_t nb = 0;
+    double *red = c->red.as<double>();
+    HIP_TRY(sgtv::launch_sum_f32(c->y.as<float>(), S.I, c->part.as<double>(), c->stream, &nb));
+    HIP_TRY(sgtv::launch_reduce(c->part.as<double>(), nb, 1, red + 4, c->stream));
+    HIP_TRY(sgtv::launch_sum_f32(S.sens.as<float>(), S.J, c->part.as<double>(), c->stream, &nb));
+    HIP_TRY(sgtv::launch_reduce(c->part.as<double>(), nb, 1, red + 5, c->stream));
+    c->fcur = 0;
+    HIP_TRY(sgtv::launch_fill_ratio(red + 4, red + 5, c->f[0].as<float>(), S.J, c->stream));
+    return SGTV_OK;
+}
+
+int check_ready(sgtv_ctx_s *c) {
+    if (!c) return fail(SGTV_EINVAL, "null context");
+    if (!c->sys) return fail(SGTV_ESTATE, "no system set (call sgtv_set_system first)");
+    if (!c->has_data) return fail(SGTV_ESTATE, "no data set (call sgtv_set_data first)");
+    return SGTV_OK;
+}
+
+int check_mem_kind(int mk) {
+    if (mk != SGTV_HOST && mk != SGTV_DEVICE) return fail(SGTV_EINVAL, "mem_kind must be SGTV_HOST or SGTV_DEVICE");
+    return SGTV_OK;
+}
+
+hipMemcpyKind to_caller(int mk) { return mk == SGTV_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice; }
+hipMemcpyKind from_caller(int mk) { return mk == SGTV_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice; }
+
+// Upload a validated float array of n values from caller memory into dst.
+int stage_floats(DBuf &dst, const float *src, int64_t n, int mk, hipStream_t st,
+                 bool (*ok)(float), const char *what) {
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<float> h;
+    HIP_TRY(fetch(h, src, n, mk));
+    for (int64_t i = 0; i < n; ++i)
+        if (!ok(h[i])) return fail(SGTV_EINVAL, std::string(what) + " has an invalid value at index " + std::to_string(i));
+    HIP_TRY(dst.alloc(sizeof(float) * n));
+    HIP_TRY(hipMemcpyAsync(dst.p, h.data(), sizeof(float) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SGTV_OK;
+}
+
+int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t ny, int32_t nx,
+                 int32_t Q, const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                 int64_t nnz, int vt, const float *w, int64_t w_len, int mk) {
+    auto S = std::make_unique<System>();
+    S->I = I; S->ny = ny; S->nx = nx; S->Q = Q; S->vt = vt; S->nnz = nnz;
+    S->S = static_cast<int64_t>(ny) * nx;
+    S->J = S->S * Q;
+    S->grid = sgtv::Grid{ny, nx, Q, S->S, S->J};
+    const int64_t J = S->J;
+
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<float> av;
+    HIP_TRY(fetch(rp, row_ptr, I + 1, mk));
+    HIP_TRY(fetch(ci, col_idx, nnz, mk));
+    HIP_TRY(fetch(av, val, nnz, mk));
+    if (rp[0] != 0 || rp[I] != nnz) return fail(SGTV_ESHAPE, "row_ptr[0] must be 0 and row_ptr[I] must equal nnz");
+    for (int64_t i = 0; i < I; ++i)
+        if (rp[i + 1] < rp[i]) return fail(SGTV_ESHAPE, "row_ptr decreases at row " + std::to_string(i));
+    for (int64_t k = 0; k < nnz; ++k) {
+        if (ci[k] < 0 || ci[k] >= J) return fail(SGTV_ESHAPE, "column index out of range at entry " + std::to_string(k));
+        if (!finite_nonneg(av[k])) return fail(SGTV_EINVAL, "matrix value not finite and nonnegative at entry " + std::to_string(k));
+    }
+    // weights
+    std::vector<float> wf;
+    if (w) {
+        HIP_TRY(fetch(wf, w, w_len, mk));
+        for (int64_t k = 0; k < w_len; ++k)
+            if (!(std::isfinite(wf[k]) && wf[k] > 0.0f)) return fail(SGTV_EINVAL, "weights must be finite and positive");
+        if (w_len == 4) {
+            for (int p = 0; p < 4; ++p) S->w4[p] = wf[p];
+        } else {
+            S->wfull = true;
+        }
+    }
+    // De Pierro curvature without the penalty factor: H0 = |D|^T |D| 1 (the
+    // kernels use rho * H0)
+    std::vector<double> Hd(static_cast<size_t>(J), 0.0);
+    for (int64_t s = 0; s < S->S; ++s) {
+        const int iy = static_cast<int>(s / nx), ix = static_cast<int>(s % nx);
+        for (int p = 0; p < 4; ++p) {
+            int64_t nb = -1;
+            if (p == 0 && ix + 1 < nx) nb = s + 1;
+            if (p == 1 && ix > 0) nb = s - 1;
+            if (p == 2 && iy + 1 < ny) nb = s + nx;
+            if (p == 3 && iy > 0) nb = s - nx;
+            for (int q = 0; q < Q; ++q) {
+                const double wt = S->wfull ? wf[(s * 4 + p) * Q + q] : S->w4[p];
+                const double l1 = nb >= 0 ? 2.0 * wt : wt;
+                Hd[s * Q + q] += wt * l1;
+                if (nb >= 0) Hd[nb * Q + q] += wt * l1;
+            }
+        }
+    }
+    std::vector<float> Hf(Hd.begin(), Hd.end());
+
+    // internal row order: rows sorted by decreasing length (stable), so that
+    // the 64 rows of a slice have nearly equal lengths
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < I; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i]);
+    std::vector<int64_t> cnt(static_cast<size_t>(maxlen + 2), 0);
+    for (int64_t i = 0; i < I; ++i) cnt[maxlen - (rp[i + 1] - rp[i])]++;
+    std::vector<int64_t> start(static_cast<size_t>(maxlen + 2), 0);
+    for (int64_t b = 1; b <= maxlen + 1; ++b) start[b] = start[b - 1] + cnt[b - 1];
+    S->perm.assign(static_cast<size_t>(I), 0);
+    for (int64_t i = 0; i < I; ++i) S->perm[start[maxlen - (rp[i + 1] - rp[i])]++] = i;
+
+    // column scales and 16-bit codes
+    std::vector<float> sigma;
+    std::vector<uint16_t> codes;
+    if (vt != SGTV_F32) {
+        sigma.assign(static_cast<size_t>(J), 0.0f);
+        for (int64_t k = 0; k < nnz; ++k) sigma[ci[k]] = std::max(sigma[ci[k]], av[k]);
+        codes.resize(static_cast<size_t>(nnz));
+        for (int64_t k = 0; k < nnz; ++k) {
+            const float sj = sigma[ci[k]];
+            const float t = sj > 0.0f ? av[k] / sj : 0.0f;
+            codes[k] = vt == SGTV_BF16 ? to_bf16(t) : to_f16(t);
+        }
+        for (int64_t j = 0; j < J; ++j)
+            if (sigma[j] == 0.0f) sigma[j] = 1.0f;   // empty / all-zero column: any scale
+    }
+
+    // rows in internal order
+    std::vector<int64_t> lp(static_cast<size_t>(I + 1), 0);
+    for (int64_t i = 0; i < I; ++i) {
+        const int64_t o = S->perm[i];
+        lp[i + 1] = lp[i] + (rp[o + 1] - rp[o]);
+    }
+    std::vector<int32_t> lidx(static_cast<size_t>(nnz));
+    std::vector<int64_t> lsrc(static_cast<size_t>(nnz));   // position in caller CSR
+    for (int64_t i = 0; i < I; ++i) {
+        const int64_t o = S->perm[i];
+        for (int64_t t = 0; t < rp[o + 1] - rp[o]; ++t) {
+            lidx[lp[i] + t] = ci[rp[o] + t];
+            lsrc[lp[i] + t] = rp[o] + t;
+        }
+    }
+    // columns: counting sort of the internal-order rows, rows ascending within a column
+    std::vector<int64_t> cp(static_cast<size_t>(J + 1), 0);
+    for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
+    for (int64_t j = 0; j < J; ++j) cp[j + 1] += cp[j];
+    std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
+    std::vector<int32_t> cidx(static_cast<size_t>(nnz));
+    std::vector<int64_t> csrc(static_cast<size_t>(nnz));
+    for (int64_t i = 0; i < I; ++i)
+        for (int64_t k = lp[i]; k < lp[i + 1]; ++k) {
+            const int64_t pos = cur[lidx[k]]++;
+            cidx[pos] = static_cast<int32_t>(i);
+            csrc[pos] = lsrc[k];
+        }
+
+    std::vector<int64_t> rsp, csp;
+    std::vector<int32_t> rsi, csi;
+    if (vt == SGTV_F32) {
+        std::vector<float> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
+        for (int64_t k = 0; k < nnz; ++k) { lv[k] = av[lsrc[k]]; cv[k] = av[csrc[k]]; }
+        std::vector<float> rsv, csv;
+        pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
+        pack_sell(J, cp, cidx, cv, csp, csi, csv);
+        HIP_TRY(upload(S->rs_val, rsv));
+        HIP_TRY(upload(S->cs_val, csv));
+    } else {
+        std::vector<uint16_t> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
+        for (int64_t k = 0; k < nnz; ++k) { lv[k] = codes[lsrc[k]]; cv[k] = codes[csrc[k]]; }
+        std::vector<uint16_t> rsv, csv;
+        pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
+        pack_sell(J, cp, cidx, cv, csp, csi, csv);
+        HIP_TRY(upload(S->rs_val, rsv));
+        HIP_TRY(upload(S->cs_val, csv));
+        HIP_TRY(upload(S->colscale, sigma));
+    }
+    if (rsp.back() >= (int64_t(1) << 31) || csp.back() >= (int64_t(1) << 31))
+        return fail(SGTV_ESHAPE, "padded matrix exceeds 2^31 entries");
+    S->n_rslices = static_cast<int64_t>(rsp.size()) - 1;
+    S->n_cslices = static_cast<int64_t>(csp.size()) - 1;
+    HIP_TRY(upload(S->rs_ptr, rsp));
+    HIP_TRY(upload(S->rs_idx, rsi));
+    HIP_TRY(upload(S->cs_ptr, csp));
+    HIP_TRY(upload(S->cs_idx, csi));
+    HIP_TRY(upload(S->H, Hf));
+    if (S->wfull) HIP_TRY(upload(S->wbuf, wf));
+
+    // sensitivity s = A^T 1 with the stored (possibly quantised) values
+    std::vector<float> ones(static_cast<size_t>(I), 1.0f);
+    DBuf d_ones;
+    HIP_TRY(upload(d_ones, ones));
+    HIP_TRY(S->sens.alloc(sizeof(float) * J));
+    HIP_TRY(sgtv::launch_back(S->cols(), vt, d_ones.as<float>(), S->sens.as<float>(), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out = std::move(S);
+    return SGTV_OK;
+}
+
+int ensure_partials(sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    const int64_t n1 = (S.n_rslices + 3) / 4;
+    int sl = 0;
+    while ((1 << sl) < S.Q && sl < 6) ++sl;
+    const int64_t n2 = (S.S + (256 >> sl) - 1) / (256 >> sl);
+    const int64_t need = std::max<int64_t>({n1, 3 * n2, 4096, 16});
+    if (need > c->part_cap) {
+        HIP_TRY(c->part.alloc(sizeof(double) * need));
+        c->part_cap = need;
+    }
+    if (!c->red.p) HIP_TRY(c->red.alloc(sizeof(double) * 16));
+    return SGTV_OK;
+}
+
+// Event bracket around one launch while profiling is on.
+struct TimedLaunch {
+    sgtv_ctx_s *c;
+    int cls;
+    hipEvent_t beg = nullptr;
+    TimedLaunch(sgtv_ctx_s *ctx, int k) : c(ctx), cls(k) {
+        if (c->profiling && hipEventCreate(&beg) == hipSuccess) (void)hipEventRecord(beg, c->stream);
+    }
+    ~TimedLaunch() {
+        if (!beg) return;
+        hipEvent_t end = nullptr;
+        if (hipEventCreate(&end) == hipSuccess && hipEventRecord(end, c->stream) == hipSuccess)
+            c->timed.push_back({cls, beg, end});
+        else
+            (void)hipEventDestroy(beg);
+    }
+};
+
+// One ADMM iteration (Eqs. 4-6) as a launch sequence on the context stream.
+int step(sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    const sgtv::Weights w = S.weights();
+    const float lam = static_cast<float>(c->rho);
+    for (int sw = 0; sw < c->sweeps; ++sw) {
+        const float *x = S.vt == SGTV_F32 ? c->f[c->fcur].as<float>() : c->fs.as<float>();
+        {
+            TimedLaunch t(c, 0);
+            HIP_TRY(sgtv::launch_forward_ratio(S.rows(), S.vt, x, c->y.as<float>(), c->r.as<float>(),
+                                               c->ratio.as<float>(), nullptr, false, c->stream, nullptr));
+        }
+        TimedLaunch t(c, 1);
+        HIP_TRY(sgtv::launch_back_update(S.cols(), S.vt, c->ratio.as<float>(), c->f[c->fcur].as<float>(),
+                                         c->f[c->fcur ^ 1].as<float>(), c->fs.as<float>(),
+                                         c->v[c->vcur].as<float>(), c->a[c->vcur].as<float>(),
+                                         S.sens.as<float>(), c->sys->H.as<float>(), S.grid, w,
+                                         c->grouping, lam, c->stream));
+        c->fcur ^= 1;
+    }
+    TimedLaunch t(c, 2);
+    HIP_TRY(sgtv::launch_split_update(c->f[c->fcur].as<float>(), c->v[c->vcur].as<float>(),
+                                      c->a[c->vcur].as<float>(), c->v[c->vcur ^ 1].as<float>(),
+                                      c->a[c->vcur ^ 1].as<float>(), S.grid, w, c->grouping,
+                                      static_cast<float>(c->beta / c->rho), c->stream));
+    c->vcur ^= 1;
+    c->k += 1;
+    return SGTV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sgtv_last_error(void) { return g_err.c_str(); }
+
+const char *sgtv_version(void) { return "sgtv 0.1 (gfx950, sliced-ELL FP32/BF16/FP16)"; }
+
+int sgtv_create(sgtv_ctx *out, int device, void *hip_stream) {
+    if (!out) return fail(SGTV_EINVAL, "out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(SGTV_EINVAL, "device index out of range");
+    try {
+        auto c = new sgtv_ctx_s();
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        *out = c;
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+void sgtv_destroy(sgtv_ctx ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto &t : ctx->timed) {
+        (void)hipEventDestroy(t.beg);
+        (void)hipEventDestroy(t.end);
+    }
+    delete ctx;
+}
+
+int sgtv_set_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q,
+                    const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                    int64_t nnz, int storage_dtype, const float *w, int64_t w_len, int mem_kind) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (I < 1 || ny < 1 || nx < 1 || Q < 1) return fail(SGTV_ESHAPE, "I, ny, nx and Q must be >= 1");
+    if (nnz < 0 || nnz >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "nnz must be in [0, 2^31)");
+    const int64_t J = static_cast<int64_t>(ny) * nx * Q;
+    if (J >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "J = ny*nx*Q must be below 2^31");
+    if (I >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "I must be below 2^31");
+    if (storage_dtype != SGTV_F32 && storage_dtype != SGTV_BF16 && storage_dtype != SGTV_F16)
+        return fail(SGTV_EINVAL, "unknown storage dtype");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !val))) return fail(SGTV_EINVAL, "NULL matrix array");
+    if (w && w_len != 4 && w_len != 4 * J) return fail(SGTV_ESHAPE, "w_len must be 4 or 4*J");
+    if (!w && w_len != 0) return fail(SGTV_ESHAPE, "w is NULL but w_len is not 0");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    try {
+        std::unique_ptr<System> S;
+        if (int e = build_system(ctx, S, I, ny, nx, Q, row_ptr, col_idx, val, nnz, storage_dtype, w,
+                                 w_len, mem_kind))
+            return e;
+        // commit
+        ctx->sys = std::move(S);
+        ctx->has_data = false;
+        ctx->y.release(); ctx->r.release(); ctx->ratio.release();
+        for (int b = 0; b < 2; ++b) { ctx->f[b].release(); ctx->v[b].release(); ctx->a[b].release(); }
+        ctx->fs.release();
+        ctx->part_cap = 0;
+        ctx->part.release();
+        if (int e = ensure_partials(ctx)) return e;
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+int sgtv_set_data(sgtv_ctx ctx, const float *y, const float *r, double beta, double rho,
+                  int sweeps, int mem_kind) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (!ctx->sys) return fail(SGTV_ESTATE, "no system set (call sgtv_set_system first)");
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (!y || !r) return fail(SGTV_EINVAL, "NULL y or r");
+    if (!(std::isfinite(beta) && beta >= 0.0)) return fail(SGTV_EINVAL, "beta must be finite and >= 0");
+    if (!(std::isfinite(rho) && rho > 0.0)) return fail(SGTV_EINVAL, "rho must be finite and > 0");
+    if (sweeps < 1) return fail(SGTV_EINVAL, "sweeps must be >= 1");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    try {
+        const System &S = *ctx->sys;
+        std::vector<float> hy, hr;
+        HIP_TRY(fetch(hy, y, S.I, mem_kind));
+        HIP_TRY(fetch(hr, r, S.I, mem_kind));
+        for (int64_t i = 0; i < S.I; ++i) {
+            if (!finite_nonneg(hy[i])) return fail(SGTV_EINVAL, "y has a negative or non-finite value at " + std::to_string(i));
+            if (!(std::isfinite(hr[i]) && hr[i] > 0.0f)) return fail(SGTV_EINVAL, "r must be finite and > 0 (index " + std::to_string(i) + ")");
+        }
+        std::vector<float> py(static_cast<size_t>(S.I)), pr(static_cast<size_t>(S.I));
+        for (int64_t i = 0; i < S.I; ++i) { py[i] = hy[S.perm[i]]; pr[i] = hr[S.perm[i]]; }
+        DBuf dy, dr, dratio;
+        HIP_TRY(upload(dy, py));
+        HIP_TRY(upload(dr, pr));
+        HIP_TRY(dratio.alloc(sizeof(float) * S.I));
+        ctx->y = std::move(dy);
+        ctx->r = std::move(dr);
+        ctx->ratio = std::move(dratio);
+        ctx->beta = beta;
+        ctx->rho = rho;
+        ctx->sweeps = sweeps;
+        if (!ctx->f[0].p || ctx->a[0].bytes != sizeof(float) * n_groups(ctx)) {
+            if (int e = alloc_state(ctx)) return e;
+        }
+        ctx->has_data = true;
+        if (int e = uniform_start(ctx)) return e;
+        if (int e = refresh_scaled(ctx)) return e;
+        if (int e = clear_split(ctx)) return e;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+int sgtv_set_grouping(sgtv_ctx ctx, int grouping) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (grouping != SGTV_GROUP_SPECTRAL && grouping != SGTV_GROUP_STANDARD)
+        return fail(SGTV_EINVAL, "unknown grouping");
+    if (grouping == ctx->grouping) {
+        if (ctx->sys && ctx->has_data) {
+            DeviceGuard g(ctx->device);
+            return clear_split(ctx);
+        }
+        return SGTV_OK;
+    }
+    DeviceGuard g(ctx->device);
+    const int old = ctx->grouping;
+    ctx->grouping = grouping;
+    if (ctx->sys && ctx->has_data) {
+        // keep f, resize (v, a) storage for the new group count
+        DBuf keep_f;
+        HIP_TRY(keep_f.alloc(sizeof(float) * ctx->sys->J));
+        HIP_TRY(hipMemcpyAsync(keep_f.p, ctx->f[ctx->fcur].p, sizeof(float) * ctx->sys->J,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        if (int e = alloc_state(ctx)) { ctx->grouping = old; return e; }
+        HIP_TRY(hipMemcpyAsync(ctx->f[0].p, keep_f.p, sizeof(float) * ctx->sys->J,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->fcur = 0;
+        if (int e = refresh_scaled(ctx)) return e;
+        if (int e = clear_split(ctx)) return e;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    return SGTV_OK;
+}
+
+int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    DeviceGuard g(ctx->device);
+    try {
+        const System &S = *ctx->sys;
+        if (x0) {
+            DBuf staged;
+            if (int e = stage_floats(staged, x0, S.J, mem_kind, ctx->stream, finite_nonneg, "x0"))
+                return e;
+            HIP_TRY(hipMemcpyAsync(ctx->f[0].p, staged.p, sizeof(float) * S.J,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+            ctx->fcur = 0;
+        } else {
+            if (int e = uniform_start(ctx)) return e;
+        }
+        if (int e = refresh_scaled(ctx)) return e;
+        if (int e = clear_split(ctx)) return e;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+int sgtv_iterate(sgtv_ctx ctx, int n_iters) {
+    if (int e = check_ready(ctx)) return e;
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    DeviceGuard g(ctx->device);
+    for (int it = 0; it < n_iters; ++it)
+        if (int e = step(ctx)) return e;
+    return SGTV_OK;
+}
+
+int sgtv_objective(sgtv_ctx ctx, sgtv_report *out) {
+    if (int e = check_ready(ctx)) return e;
+    if (!out) return fail(SGTV_EINVAL, "out is NULL");
+    DeviceGuard g(ctx->device);
+    const System &S = *ctx->sys;
+    double *part = ctx->part.as<double>();
+    double *red = ctx->red.as<double>();
+    int64_t n1 = 0, n2 = 0;
+    const float *x = S.vt == SGTV_F32 ? ctx->f[ctx->fcur].as<float>() : ctx->fs.as<float>();
+    HIP_TRY(sgtv::launch_forward_ratio(S.rows(), S.vt, x, ctx->y.as<float>(), ctx->r.as<float>(),
+                                       ctx->ratio.as<float>(), part, true, ctx->stream, &n1));
+    HIP_TRY(sgtv::launch_reduce(part, n1, 1, red, ctx->stream));
+    HIP_TRY(sgtv::launch_report(ctx->f[ctx->fcur].as<float>(), ctx->v[ctx->vcur].as<float>(),
+                                ctx->a[ctx->vcur].as<float>(), ctx->v[ctx->vcur ^ 1].as<float>(),
+                                ctx->a[ctx->vcur ^ 1].as<float>(), S.grid, S.weights(),
+                                ctx->grouping, part, ctx->stream, &n2));
+    HIP_TRY(sgtv::launch_reduce(part, n2, 3, red + 1, ctx->stream));
+    double h[4];
+    HIP_TRY(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    out->data = h[0];
+    out->tv = h[1];
+    out->total = h[0] + ctx->beta * h[1];
+    out->r_primal = std::sqrt(h[2]);
+    out->r_dual = ctx->rho * std::sqrt(h[3]);
+    out->iter = ctx->k;
+    return SGTV_OK;
+}
+
+int sgtv_get_image(sgtv_ctx ctx, float *x, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (!x) return fail(SGTV_EINVAL, "x is NULL");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(hipMemcpyAsync(x, ctx->f[ctx->fcur].p, sizeof(float) * ctx->sys->J, to_caller(mem_kind),
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SGTV_OK;
+}
+
+int sgtv_get_split(sgtv_ctx ctx, float *d, float *c, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    DeviceGuard g(ctx->device);
+    const System &S = *ctx->sys;
+    DBuf td, tc;
+    HIP_TRY(td.alloc(sizeof(float) * S.J * 4));
+    HIP_TRY(tc.alloc(sizeof(float) * S.J * 4));
+    HIP_TRY(sgtv::launch_split_from_state(ctx->v[ctx->vcur].as<float>(), ctx->a[ctx->vcur].as<float>(),
+                                          td.as<float>(), tc.as<float>(), S.grid, ctx->grouping,
+                                          ctx->stream));
+    if (d) HIP_TRY(hipMemcpyAsync(d, td.p, sizeof(float) * S.J * 4, to_caller(mem_kind), ctx->stream));
+    if (c) HIP_TRY(hipMemcpyAsync(c, tc.p, sizeof(float) * S.J * 4, to_caller(mem_kind), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SGTV_OK;
+}
+
+int sgtv_state_sizes(sgtv_ctx ctx, int64_t *n_image, int64_t *n_split, int64_t *n_gr) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (!ctx->sys) return fail(SGTV_ESTATE, "no system set");
+    if (n_image) *n_image = ctx->sys->J;
+    if (n_split) *n_split = ctx->sys->J * 4;
+    if (n_gr) *n_gr = n_groups(ctx);
+    return SGTV_OK;
+}
+
+int sgtv_get_state(sgtv_ctx ctx, float *f, float *v, float *a, int64_t *k, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    DeviceGuard g(ctx->device);
+    const System &S = *ctx->sys;
+    if (f) HIP_TRY(hipMemcpyAsync(f, ctx->f[ctx->fcur].p, sizeof(float) * S.J, to_caller(mem_kind), ctx->stream));
+    if (v) HIP_TRY(hipMemcpyAsync(v, ctx->v[ctx->vcur].p, sizeof(float) * S.J * 4, to_caller(mem_kind), ctx->stream));
+    if (a) HIP_TRY(hipMemcpyAsync(a, ctx->a[ctx->vcur].p, sizeof(float) * n_groups(ctx), to_caller(mem_kind), ctx->stream));
+    if (k) *k = ctx->k;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SGTV_OK;
+}
+
+static bool finite_any(float x) { return std::isfinite(x); }
+static bool unit_interval(float x) { return std::isfinite(x) && x >= 0.0f && x <= 1.0f; }
+
+int sgtv_set_state(sgtv_ctx ctx, const float *f, const float *v, const float *a, int64_t k,
+                   int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (!f || !v || !a) return fail(SGTV_EINVAL, "f, v and a are required");
+    if (k < 0) return fail(SGTV_EINVAL, "k must be >= 0");
+    DeviceGuard g(ctx->device);
+    try {
+        const System &S = *ctx->sys;
+        DBuf sf, sv, sa;
+        if (int e = stage_floats(sf, f, S.J, mem_kind, ctx->stream, finite_nonneg, "f")) return e;
+        if (int e = stage_floats(sv, v, S.J * 4, mem_kind, ctx->stream, finite_any, "v")) return e;
+        if (int e = stage_floats(sa, a, n_groups(ctx), mem_kind, ctx->stream, unit_interval, "a")) return e;
+        ctx->fcur = 0;
+        ctx->vcur = 0;
+        HIP_TRY(hipMemcpyAsync(ctx->f[0].p, sf.p, sizeof(float) * S.J, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int b = 0; b < 2; ++b) {
+            HIP_TRY(hipMemcpyAsync(ctx->v[b].p, sv.p, sizeof(float) * S.J * 4, hipMemcpyDeviceToDevice, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(ctx->a[b].p, sa.p, sizeof(float) * n_groups(ctx), hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        ctx->k = k;
+        if (int e = refresh_scaled(ctx)) return e;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (!x) return fail(SGTV_EINVAL, "x is NULL");
+    DeviceGuard g(ctx->device);
+    const System &S = *ctx->sys;
+    DBuf e, out;
+    HIP_TRY(e.alloc(sizeof(float) * S.J));
+    HIP_TRY(out.alloc(sizeof(float) * S.J));
+    HIP_TRY(sgtv::launch_back(S.cols(), S.vt, ctx->y.as<float>(), e.as<float>(), ctx->stream));
+    HIP_TRY(sgtv::launch_div_safe(e.as<float>(), S.sens.as<float>(), out.as<float>(), S.J, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(x, out.p, sizeof(float) * S.J, to_caller(mem_kind), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SGTV_OK;
+}
+
+int sgtv_set_profiling(sgtv_ctx ctx, int enable) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    ctx->profiling = enable != 0;
+    return SGTV_OK;
+}
+
+int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (!ms || !counts) return fail(SGTV_EINVAL, "ms and counts are required");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    int status = SGTV_OK;
+    for (auto &t : ctx->timed) {
+        float el = 0.0f;
+        hipError_t e = hipEventElapsedTime(&el, t.beg, t.end);
+        if (e != hipSuccess && status == SGTV_OK) status = hip_fail(e, "hipEventElapsedTime");
+        if (e == hipSuccess && t.cls >= 0 && t.cls < 4) {
+            ms[t.cls] += el;
+            counts[t.cls] += 1;
+        }
+        (void)hipEventDestroy(t.beg);
+        (void)hipEventDestroy(t.end);
+    }
+    ctx->timed.clear();
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Internal interface between the C-ABI host code and the CDNA4 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgtv {
+
+constexpr int kWave = 64;          // wavefront width on gfx950
+constexpr int kBlock = 256;        // threads per block for every streaming kernel
+constexpr int kSliceRows = 64;     // lines (rows or columns) per sliced-ELL slice
+constexpr int kDepth = 4;          // entries per lane per 16-byte index load
+
+// Hyperspectral grid: J = S * Q voxels, voxel j = s * Q + q, s = iy * nx + ix.
+struct Grid {
+    int ny, nx, Q;
+    int64_t S, J;
+};
+
+// Direction weights: constants per direction, or a full [s][p][q] array.
+struct Weights {
+    float w[4];
+    const float *full;   // nullptr: use w[p]
+};
+
+// Sliced-ELL matrix in device memory (slices of 64 lines, depth padded to 4).
+// Entry t of line l of slice k sits at sptr[k] + (t / 4) * 256 + (l % 64) * 4 + t % 4.
+struct Sell {
+    const int64_t *sptr;   // n_slices + 1 element offsets
+    const int32_t *idx;    // gathered index per entry (padding: 0)
+    const void *val;       // float / bf16 / fp16 codes (padding: 0)
+    const float *scale;    // per-column scale for 16-bit values, nullptr for FP32
+    int64_t n_lines, n_slices;
+};
+
+// Launchers (all asynchronous on `st`).
+hipError_t launch_forward_ratio(const Sell &A, int vt, const float *x, const float *y,
+                                const float *r, float *ratio, double *partials, bool objective,
+                                hipStream_t st, int64_t *n_partials);
+hipError_t launch_back(const Sell &At, int vt, const float *t, float *e, hipStream_t st);
+hipError_t launch_back_update(const Sell &At, int vt, const float *ratio, const float *g,
+                              float *g_next, float *gs_next, const float *v, const float *a,
+                              const float *sens, const float *H, const Grid &grid,
+                              const Weights &w, int grouping, float lam, hipStream_t st);
+hipError_t launch_split_update(const float *f, const float *v_old, const float *a_old,
+                               float *v_new, float *a_new, const Grid &grid, const Weights &w,
+                               int grouping, float thr, hipStream_t st);
+hipError_t launch_report(const float *f, const float *v, const float *a, const float *v_prev,
+                         const float *a_prev, const Grid &grid, const Weights &w, int grouping,
+                         double *partials, hipStream_t st, int64_t *n_blocks);
+hipError_t launch_reduce(const double *partials, int64_t n, int n_quant, double *out,
+                         hipStream_t st);
+hipError_t launch_sum_f32(const float *a, int64_t n, double *partials, hipStream_t st,
+                          int64_t *n_blocks);
+hipError_t launch_fill_ratio(const double *num, const double *den, float *out, int64_t n,
+                             hipStream_t st);
+hipError_t launch_scale(const float *x, const float *s, float *out, int64_t n, hipStream_t st);
+hipError_t launch_split_from_state(const float *v, const float *a, float *d, float *c,
+                                   const Grid &grid, int grouping, hipStream_t st);
+hipError_t launch_div_safe(const float *num, const float *den, float *out, int64_t n,
+                           hipStream_t st);
+hipError_t launch_check_range(const float *x, int64_t n, float lo, int strict_lo, float hi,
+                              int *flag, hipStream_t st);
+
+}  // namespace sgtv

@@ -1,0 +1,312 @@
+"""Python binding of libsgtv.so (ctypes): argument marshalling only.
+
+The functions below carry the names of the C entry points declared in
+include/sgtv.h and forward their arguments unchanged; every step of the
+reconstruction runs in the library's HIP kernels.  NumPy arrays are passed as
+host memory, torch CUDA tensors as device memory (PyTorch provides device
+memory and streams, nothing else).  If the library has not been built the
+first call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB_PATH
+
+SGTV_OK, SGTV_EINVAL, SGTV_ESHAPE, SGTV_ESTATE, SGTV_EDEVICE, SGTV_ENOMEM = 0, -1, -2, -3, -4, -5
+SGTV_F32, SGTV_BF16, SGTV_F16 = 0, 1, 2
+SGTV_HOST, SGTV_DEVICE = 0, 1
+SGTV_GROUP_SPECTRAL, SGTV_GROUP_STANDARD = 0, 1
+
+STORAGE = {"f32": SGTV_F32, "bf16": SGTV_BF16, "f16": SGTV_F16}
+
+
+class SgtvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sgtv error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("total", ctypes.c_double), ("data", ctypes.c_double), ("tv", ctypes.c_double),
+                ("r_primal", ctypes.c_double), ("r_dual", ctypes.c_double), ("iter", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+def lib():
+    """Load libsgtv.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsgtv.so is not built: run python -m paper_1601_08201_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "sgtv_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+            "sgtv_destroy": (None, [_P]),
+            "sgtv_last_error": (ctypes.c_char_p, []),
+            "sgtv_version": (ctypes.c_char_p, []),
+            "sgtv_set_system": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _I, _P, _I64, _I]),
+            "sgtv_set_data": (_I, [_P, _P, _P, _D, _D, _I, _I]),
+            "sgtv_set_grouping": (_I, [_P, _I]),
+            "sgtv_set_init": (_I, [_P, _P, _I]),
+            "sgtv_iterate": (_I, [_P, _I]),
+            "sgtv_objective": (_I, [_P, ctypes.POINTER(Report)]),
+            "sgtv_get_image": (_I, [_P, _P, _I]),
+            "sgtv_get_split": (_I, [_P, _P, _P, _I]),
+            "sgtv_state_sizes": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+            "sgtv_get_state": (_I, [_P, _P, _P, _P, ctypes.POINTER(_I64), _I]),
+            "sgtv_set_state": (_I, [_P, _P, _P, _P, _I64, _I]),
+            "sgtv_backprojection": (_I, [_P, _P, _I]),
+            "sgtv_set_profiling": (_I, [_P, _I]),
+            "sgtv_kernel_times": (_I, [_P, _P, _P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != SGTV_OK:
+        raise SgtvError(code, lib().sgtv_last_error().decode(errors="replace"))
+
+
+def _is_torch_cuda(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _arg(a, dtype):
+    """(pointer, mem_kind, keepalive) for a NumPy array or torch CUDA tensor."""
+    if a is None:
+        return None, SGTV_HOST, None
+    if _is_torch_cuda(a):
+        import torch
+        tdt = {np.float32: torch.float32, np.int32: torch.int32, np.int64: torch.int64}[dtype]
+        if a.dtype != tdt or not a.is_contiguous():
+            a = a.to(tdt).contiguous()
+        return ctypes.c_void_p(a.data_ptr()), SGTV_DEVICE, a
+    arr = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+    return arr.ctypes.data_as(ctypes.c_void_p), SGTV_HOST, arr
+
+
+def _kind(*items):
+    kinds = {k for (_, k, keep) in items if keep is not None}
+    if len(kinds) > 1:
+        raise ValueError("mix of host arrays and device tensors in one call")
+    return kinds.pop() if kinds else SGTV_HOST
+
+
+# ---- thin wrappers with the C names ---------------------------------------------------
+
+def sgtv_create(device=0, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().sgtv_create(ctypes.byref(h), int(device), stream))
+    return h
+
+
+def sgtv_destroy(ctx):
+    lib().sgtv_destroy(ctx)
+
+
+def sgtv_last_error():
+    return lib().sgtv_last_error().decode(errors="replace")
+
+
+def sgtv_version():
+    return lib().sgtv_version().decode()
+
+
+def sgtv_set_system(ctx, I, ny, nx, Q, row_ptr, col_idx, val, storage="f32", w=None):
+    a = _arg(row_ptr, np.int64)
+    b = _arg(col_idx, np.int32)
+    c = _arg(val, np.float32)
+    wa = _arg(w, np.float32)
+    mk = _kind(a, b, c, wa)
+    nnz = int(b[2].shape[0]) if b[2] is not None else 0
+    wlen = 0 if w is None else int(np.prod(wa[2].shape))
+    _check(lib().sgtv_set_system(ctx, int(I), int(ny), int(nx), int(Q), a[0], b[0], c[0], nnz,
+                                 STORAGE.get(storage, storage), wa[0], wlen, mk))
+
+
+def sgtv_set_data(ctx, y, r, beta, rho, sweeps=1):
+    a, b = _arg(y, np.float32), _arg(r, np.float32)
+    _check(lib().sgtv_set_data(ctx, a[0], b[0], float(beta), float(rho), int(sweeps), _kind(a, b)))
+
+
+def sgtv_set_grouping(ctx, grouping):
+    _check(lib().sgtv_set_grouping(ctx, int(grouping)))
+
+
+def sgtv_set_init(ctx, x0=None):
+    a = _arg(x0, np.float32)
+    _check(lib().sgtv_set_init(ctx, a[0], _kind(a)))
+
+
+def sgtv_iterate(ctx, n_iters):
+    _check(lib().sgtv_iterate(ctx, int(n_iters)))
+
+
+def sgtv_objective(ctx):
+    rep = Report()
+    _check(lib().sgtv_objective(ctx, ctypes.byref(rep)))
+    return rep.as_dict()
+
+
+def sgtv_state_sizes(ctx):
+    a, b, c = _I64(), _I64(), _I64()
+    _check(lib().sgtv_state_sizes(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def _out(n, like=None):
+    if like is not None:
+        return like
+    return np.empty(n, np.float32)
+
+
+def _out_arg(out):
+    if _is_torch_cuda(out):
+        return ctypes.c_void_p(out.data_ptr()), SGTV_DEVICE
+    return out.ctypes.data_as(ctypes.c_void_p), SGTV_HOST
+
+
+def sgtv_get_image(ctx, out=None):
+    n_img, _, _ = sgtv_state_sizes(ctx)
+    out = _out(n_img, out)
+    p, mk = _out_arg(out)
+    _check(lib().sgtv_get_image(ctx, p, mk))
+    return out
+
+
+def sgtv_get_split(ctx):
+    _, n_split, _ = sgtv_state_sizes(ctx)
+    d, c = np.empty(n_split, np.float32), np.empty(n_split, np.float32)
+    _check(lib().sgtv_get_split(ctx, d.ctypes.data_as(_P), c.ctypes.data_as(_P), SGTV_HOST))
+    return d, c
+
+
+def sgtv_get_state(ctx):
+    n_img, n_split, n_gr = sgtv_state_sizes(ctx)
+    f, v, a = np.empty(n_img, np.float32), np.empty(n_split, np.float32), np.empty(n_gr, np.float32)
+    k = _I64()
+    _check(lib().sgtv_get_state(ctx, f.ctypes.data_as(_P), v.ctypes.data_as(_P), a.ctypes.data_as(_P),
+                                ctypes.byref(k), SGTV_HOST))
+    return f, v, a, k.value
+
+
+def sgtv_set_state(ctx, f, v, a, k):
+    fa, va, aa = _arg(f, np.float32), _arg(v, np.float32), _arg(a, np.float32)
+    _check(lib().sgtv_set_state(ctx, fa[0], va[0], aa[0], int(k), _kind(fa, va, aa)))
+
+
+def sgtv_backprojection(ctx, out=None):
+    n_img, _, _ = sgtv_state_sizes(ctx)
+    out = _out(n_img, out)
+    p, mk = _out_arg(out)
+    _check(lib().sgtv_backprojection(ctx, p, mk))
+    return out
+
+
+def sgtv_set_profiling(ctx, enable):
+    _check(lib().sgtv_set_profiling(ctx, int(bool(enable))))
+
+
+KERNEL_CLASSES = ("forward_ratio", "back_update", "split_update", "other")
+
+
+def sgtv_kernel_times(ctx):
+    """{class: (total_ms, launches)} accumulated since the last call."""
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    _check(lib().sgtv_kernel_times(ctx, ctypes.cast(ms, _P), ctypes.cast(cnt, _P)))
+    return {KERNEL_CLASSES[i]: (ms[i], cnt[i]) for i in range(4)}
+
+
+class Reconstructor:
+    """Owning handle around one library context (one scan)."""
+
+    def __init__(self, device=0, stream=None):
+        self._ctx = sgtv_create(device, stream)
+
+    def close(self):
+        if self._ctx is not None:
+            sgtv_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def set_system(self, I, ny, nx, Q, row_ptr, col_idx, val, storage="f32", w=None):
+        sgtv_set_system(self._ctx, I, ny, nx, Q, row_ptr, col_idx, val, storage, w)
+        return self
+
+    def set_problem(self, prob, storage="f32", w=None, sweeps=None):
+        """Convenience: set system and data of a datagen.Problem."""
+        self.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val,
+                        storage=storage, w=w)
+        self.set_data(prob.y, prob.r, prob.beta, prob.rho, prob.sweeps if sweeps is None else sweeps)
+        return self
+
+    def set_data(self, y, r, beta, rho, sweeps=1):
+        sgtv_set_data(self._ctx, y, r, beta, rho, sweeps)
+        return self
+
+    def set_grouping(self, grouping):
+        sgtv_set_grouping(self._ctx, grouping)
+        return self
+
+    def set_init(self, x0=None):
+        sgtv_set_init(self._ctx, x0)
+        return self
+
+    def iterate(self, n):
+        sgtv_iterate(self._ctx, n)
+        return self
+
+    def objective(self):
+        return sgtv_objective(self._ctx)
+
+    def image(self, out=None):
+        return sgtv_get_image(self._ctx, out)
+
+    def split(self):
+        return sgtv_get_split(self._ctx)
+
+    def state(self):
+        return sgtv_get_state(self._ctx)
+
+    def set_state(self, f, v, a, k):
+        sgtv_set_state(self._ctx, f, v, a, k)
+        return self
+
+    def backprojection(self, out=None):
+        return sgtv_backprojection(self._ctx, out)
+
+    def set_profiling(self, enable=True):
+        sgtv_set_profiling(self._ctx, enable)
+        return self
+
+    def kernel_times(self):
+        return sgtv_kernel_times(self._ctx)

@@ -1,0 +1,254 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Tolerances: image relative L2 <= 1e-5 after a fixed iteration count on the
+FP32 path (the acceptance bound of the method's GPU port); objective and data
+terms compared to relative 1e-6; split variables d, c to relative L2 1e-4
+(they are differences of nearly equal numbers in voxels where the group is
+almost shrunk to zero).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_08201_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1601_08201_amd import sgtv
+    sgtv.lib()
+    return sgtv
+
+
+def run_gpu(sg, prob, n, storage="f32", w=None, grouping=0, sweeps=None, x0=None):
+    R = sg.Reconstructor()
+    R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val, storage=storage, w=w)
+    if grouping:
+        R.set_grouping(grouping)
+    R.set_data(prob.y, prob.r, prob.beta, prob.rho, prob.sweeps if sweeps is None else sweeps)
+    if x0 is not None:
+        R.set_init(x0)
+    R.iterate(n)
+    return R
+
+
+def check_against_oracle(sg, prob, n, w=None, grouping=0, sweeps=None, x0=None, tol=IMG_TOL):
+    R = run_gpu(sg, prob, n, w=w, grouping=grouping, sweeps=sweeps, x0=x0)
+    f_g = R.image()
+    d_g, c_g = R.split()
+    rep = R.objective()
+    f_o, d_o, c_o, rep_o = oracle.admm(prob, n, f0=x0, w=w, grouping=grouping,
+                                       sweeps=prob.sweeps if sweeps is None else sweeps)
+    print("case", prob.ny, prob.nx, prob.Q, prob.I, "iters", n, "rel_l2", rel_l2(f_g, f_o), flush=True)
+    assert np.all(f_g >= 0)
+    assert rel_l2(f_g, f_o) <= tol
+    assert rel_l2(d_g, d_o) <= 1e-4 or np.linalg.norm(d_g - d_o) <= 1e-5
+    assert rel_l2(c_g, c_o) <= 1e-4
+    obj_o = oracle.objective(prob, f_o, w=w, grouping=grouping)
+    assert rep["total"] == pytest.approx(obj_o[0], rel=1e-6)
+    assert rep["data"] == pytest.approx(obj_o[1], rel=1e-6, abs=1e-6)
+    assert rep["tv"] == pytest.approx(obj_o[2], rel=1e-5)
+    if n > 0:
+        assert rep["r_primal"] == pytest.approx(rep_o[-1, 3], rel=1e-3, abs=1e-6)
+        assert rep["r_dual"] == pytest.approx(rep_o[-1, 4], rel=1e-3, abs=1e-6)
+    assert rep["iter"] == n
+    R.close()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_small_workload_50_iterations(sg, seed):
+    prob = datagen.make_problem("small", seed)
+    check_against_oracle(sg, prob, 50)
+
+
+@pytest.mark.parametrize("Q", [1, 7, 33, 64, 129])
+def test_spectral_sizes(sg, Q):
+    prob = datagen.make_problem(dict(ny=5, nx=6, Q=Q, I=max(64, 3 * 30 * Q // 2), nnz_per_col=8,
+                                     rects=3, beta=0.2, rho=1.0), seed=100 + Q)
+    check_against_oracle(sg, prob, 20)
+
+
+def test_non_square_grid_and_ragged_tails(sg):
+    prob = datagen.make_problem(dict(ny=3, nx=11, Q=5, I=301, nnz_per_col=7, rects=3, beta=0.1),
+                                seed=7)
+    check_against_oracle(sg, prob, 30)
+
+
+def test_empty_rows_and_columns(sg):
+    prob = datagen.make_problem(dict(ny=4, nx=4, Q=8, I=200, nnz_per_col=6, rects=2, beta=0.1), seed=9)
+    A = prob.csr().tolil()
+    A[5, :] = 0
+    A[17, :] = 0
+    A[:, 3] = 0
+    A[:, 64] = 0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    prob.rowptr, prob.col, prob.val = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float32)
+    check_against_oracle(sg, prob, 25)
+
+
+def test_rows_with_many_entries(sg):
+    prob = datagen.make_problem(dict(ny=4, nx=4, Q=16, I=40, nnz_per_col=12, rects=2, beta=0.1), seed=12)
+    check_against_oracle(sg, prob, 25)
+
+
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_surrogate_sweeps(sg, sweeps):
+    prob = datagen.make_problem("small", 3)
+    check_against_oracle(sg, prob, 15, sweeps=sweeps)
+
+
+def test_standard_tv_grouping(sg):
+    prob = datagen.make_problem("small", 4)
+    check_against_oracle(sg, prob, 30, grouping=1)
+
+
+def test_direction_weights(sg):
+    prob = datagen.make_problem(dict(ny=6, nx=5, Q=9, I=300, nnz_per_col=8, rects=3, beta=0.15), seed=21)
+    check_against_oracle(sg, prob, 20, w=np.array([1.0, 1.0, 0.3, 0.3], np.float32))
+    wfull = np.random.default_rng(3).uniform(0.5, 1.5, prob.J * 4).astype(np.float32)
+    check_against_oracle(sg, prob, 20, w=wfull)
+
+
+def test_explicit_start_image(sg):
+    prob = datagen.make_problem("small", 5)
+    x0 = np.random.default_rng(1).uniform(0, 3, prob.J).astype(np.float32)
+    check_against_oracle(sg, prob, 20, x0=x0)
+
+
+def test_split_calls_equal_one_call_bitwise(sg):
+    prob = datagen.make_problem("small", 6)
+    a = run_gpu(sg, prob, 50)
+    b = run_gpu(sg, prob, 25)
+    b.iterate(25)
+    np.testing.assert_array_equal(a.image(), b.image())
+    for x, y in zip(a.state()[:3], b.state()[:3]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_checkpoint_resume_bitwise(sg):
+    prob = datagen.make_problem("small", 7)
+    a = run_gpu(sg, prob, 40)
+    b = run_gpu(sg, prob, 15)
+    f, v, al, k = b.state()
+    c = run_gpu(sg, prob, 0)
+    c.set_state(f, v, al, k)
+    c.iterate(25)
+    np.testing.assert_array_equal(a.image(), c.image())
+    assert c.objective()["iter"] == 40
+
+
+def test_run_twice_bitwise(sg):
+    prob = datagen.make_problem("small", 8)
+    a = run_gpu(sg, prob, 30).image()
+    b = run_gpu(sg, prob, 30).image()
+    np.testing.assert_array_equal(a, b)
+
+
+def test_device_tensors_in_and_out(sg):
+    import torch
+    prob = datagen.make_problem("small", 2)
+    R = sg.Reconstructor(stream=torch.cuda.current_stream().cuda_stream)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    R.set_system(prob.I, prob.ny, prob.nx, prob.Q, dev(prob.rowptr), dev(prob.col), dev(prob.val))
+    R.set_data(dev(prob.y), dev(prob.r), prob.beta, prob.rho, 1)
+    R.iterate(10)
+    out = torch.empty(prob.J, dtype=torch.float32, device="cuda")
+    R.image(out)
+    torch.cuda.synchronize()
+    ref = run_gpu(sg, prob, 10).image()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+
+
+def test_zero_counts_stay_zero(sg):
+    prob = datagen.make_problem("small", 1)
+    prob.y = np.zeros_like(prob.y)
+    R = run_gpu(sg, prob, 10)
+    assert np.all(R.image() == 0)
+    rep = R.objective()
+    assert rep["total"] == pytest.approx(float(np.sum(prob.r.astype(np.float64))), rel=1e-6)
+
+
+def test_backprojection_normalised(sg):
+    prob = datagen.make_problem("small", 0)
+    R = run_gpu(sg, prob, 0)
+    x = R.backprojection()
+    e = oracle.back(prob.rowptr, prob.col, prob.val, prob.y, prob.J)
+    s = oracle.back(prob.rowptr, prob.col, prob.val, np.ones(prob.I), prob.J)
+    ref = np.where(s > 0, e / np.where(s > 0, s, 1), 0)
+    assert rel_l2(x, ref) <= 1e-6
+
+
+def test_invalid_inputs_leave_state_unchanged(sg):
+    prob = datagen.make_problem("small", 0)
+    R = run_gpu(sg, prob, 5)
+    before = R.state()
+    bad_col = prob.col.copy()
+    bad_col[3] = prob.J
+    with pytest.raises(sg.SgtvError) as ei:
+        R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, bad_col, prob.val)
+    assert ei.value.code == sg.SGTV_ESHAPE
+    bad_val = prob.val.copy()
+    bad_val[0] = -1.0
+    with pytest.raises(sg.SgtvError) as ei:
+        R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, bad_val)
+    assert ei.value.code == sg.SGTV_EINVAL
+    bad_val[0] = np.nan
+    with pytest.raises(sg.SgtvError):
+        R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, bad_val)
+    y = prob.y.copy()
+    y[2] = np.inf
+    with pytest.raises(sg.SgtvError):
+        R.set_data(y, prob.r, prob.beta, prob.rho)
+    with pytest.raises(sg.SgtvError):
+        R.set_data(prob.y, np.zeros_like(prob.r), prob.beta, prob.rho)
+    with pytest.raises(sg.SgtvError):
+        R.set_data(prob.y, prob.r, -1.0, prob.rho)
+    with pytest.raises(sg.SgtvError):
+        R.set_data(prob.y, prob.r, prob.beta, 0.0)
+    x0 = np.ones(prob.J, np.float32)
+    x0[1] = -0.5
+    with pytest.raises(sg.SgtvError):
+        R.set_init(x0)
+    after = R.state()
+    for a, b in zip(before[:3], after[:3]):
+        np.testing.assert_array_equal(a, b)
+    assert before[3] == after[3]
+    R2 = sg.Reconstructor()
+    with pytest.raises(sg.SgtvError) as ei:
+        R2.iterate(1)
+    assert ei.value.code == sg.SGTV_ESTATE
+
+
+def test_paper_scale_first_iterations_and_properties(sg):
+    """128x128x128 scan, 1,048,576 measurements, 64 entries per column: full-size parity
+    after 2 iterations, then 200 iterations stay finite, nonnegative and lower the objective."""
+    prob = datagen.make_problem("paper", 1)
+    print("paper-scale problem generated", flush=True)
+    R = run_gpu(sg, prob, 2)
+    f_g = R.image()
+    f_o, _, _, rep_o = oracle.admm(prob, 2, report=False)
+    err = rel_l2(f_g, f_o)
+    print("paper-scale rel_l2 after 2 iterations", err, flush=True)
+    assert err <= IMG_TOL
+    first = R.objective()["total"]
+    R.iterate(198)
+    rep = R.objective()
+    f = R.image()
+    assert np.all(np.isfinite(f)) and np.all(f >= 0)
+    assert rep["total"] < first
+    assert rep["iter"] == 200
