@@ -28,16 +28,27 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(prob, value_bytes):
-    """Bytes each kernel must move per launch (every array touched once)."""
+def algorithmic_bytes(prob, value_bytes, fmt):
+    """Bytes each kernel must move per launch: every array it needs, touched once.
+
+    Tiled format: forward = A (values + indices), x, p out; ratio = p, y, r,
+    ratio out; back = A, ratio, e out; image update = e, g, v, a, sens, H,
+    g out; split = f, v, a in and v, a out.  The sliced-ELL kernels fuse the
+    ratio into the forward pass and the image update into the back pass.
+    """
     I, J, nnz = prob.I, prob.J, prob.nnz
     S = prob.ny * prob.nx
     a = nnz * (value_bytes + 4)
-    fwd = a + 4 * (I + 1) + 4 * J + 4 * I + 4 * I + 4 * I          # A, ptr, x, y, r, ratio
-    back = a + 4 * (J + 1) + 4 * I + 4 * J + 16 * J + 4 * S + 4 * J + 4 * J + 4 * J
-    #      A, ptr, ratio, g, v, a, sens, H, g_next
-    split = 4 * J + 16 * J + 4 * S + 16 * J + 4 * S                  # f, v_old, a_old, v_new, a_new
-    return {"forward_ratio": fwd, "back_update": back, "split_update": split}
+    out = {"split_update": 4 * J + 16 * J + 4 * S + 16 * J + 4 * S}
+    if fmt == "tiled":
+        out["forward"] = a + 4 * J + 4 * I
+        out["ratio"] = 16 * I
+        out["back"] = a + 4 * I + 4 * J
+        out["image_update"] = 4 * J + 4 * J + 16 * J + 4 * S + 4 * J + 4 * J + 4 * J
+    else:
+        out["forward"] = a + 4 * (I + 1) + 4 * J + 12 * I
+        out["back"] = a + 4 * (J + 1) + 4 * I + 32 * J + 4 * S
+    return out
 
 
 def cpu_baseline(prob, iters):
@@ -69,7 +80,10 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--config", default="paper")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--format", default="tiled", choices=["tiled", "sell"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -94,6 +108,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     R = sgtv.Reconstructor(device=0, stream=stream.cuda_stream)
+    R.set_schedule(format=0 if args.format == "tiled" else 1)
     t0 = time.time()
     R.set_problem(prob, storage=args.storage)
     log("system and data set in %.1fs" % (time.time() - t0))
@@ -119,7 +134,7 @@ def main():
     times = R.kernel_times()
     R.set_profiling(False)
     vb = {"f32": 4, "bf16": 2, "f16": 2}[args.storage]
-    alg = algorithmic_bytes(prob, vb)
+    alg = algorithmic_bytes(prob, vb, args.format)
     kern = {}
     for name, (tot, cnt) in times.items():
         if cnt and name in alg:
@@ -129,6 +144,14 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_us"])
     achieved = kern[dom]["gbs"]
     log("kernels: " + json.dumps(kern))
+    log("schedule: " + json.dumps(R.schedule()))
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
     iter_bytes = sum(alg.values())
 
     cpu = None
@@ -153,9 +176,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16": "bf16-values/f32-accum", "f16": "f16-values/f32-accum"}[args.storage],
         "data": "synthetic (seeded phantom, random coded-mask system matrix, Poisson counts)",
-        "config": {"workload": "%s scan %dx%dx%d, I=%d, %d nnz/col, nnz=%d, beta=%g, rho=%g, %s values"
+        "config": {"workload": "%s scan %dx%dx%d, I=%d, %d nnz/col, nnz=%d, beta=%g, rho=%g, %s values, %s format"
                                % (args.config, prob.ny, prob.nx, prob.Q, prob.I, prob.nnz // prob.J,
-                                  prob.nnz, prob.beta, prob.rho, args.storage),
+                                  prob.nnz, prob.beta, prob.rho, args.storage, args.format),
                    "global_batch": 1, "parallelism": "single GPU"},
         "iteration_alg_GBs": iter_bytes * 1e3 / ms_per_step / 1e9,
         "kernels": kern,

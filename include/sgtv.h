@@ -160,12 +160,43 @@ int sgtv_set_state(sgtv_ctx ctx, const float *f, const float *v, const float *a,
 int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);
 
 /*
+ * Launch schedule of the two sparse products A f and A^T t.  Takes effect at
+ * the next sgtv_set_system; zero fields are chosen automatically.
+ *   format SGTV_FORMAT_TILED: LDS-tiled products.  A workgroup of `waves`
+ *     wavefronts owns waves * rows_per_wave output rows with their sums in
+ *     LDS, stages `block_cols` entries of the gathered vector at a time into
+ *     LDS, and the column blocks are split into `slabs` groups whose partial
+ *     sums are added afterwards (each slab is pinned to one XCD).
+ *   format SGTV_FORMAT_SELL: sliced ELL, one lane per output row, gathers
+ *     straight from memory (no other field applies).
+ * Limits: waves in [1, 16]; rows_per_wave in [1, 32767]; block_cols a
+ * multiple of 4 in [4, 65536]; slabs in [1, 16]; the LDS of one workgroup,
+ * 4 * (waves * (rows_per_wave + 1) rounded up to 4 + block_cols) bytes, at
+ * most 163840.  Violations give SGTV_EINVAL at set_schedule (field ranges) or
+ * set_system (LDS size).
+ */
+enum { SGTV_FORMAT_TILED = 0, SGTV_FORMAT_SELL = 1 };
+typedef struct {
+    int32_t format;
+    int32_t waves;
+    int32_t fwd_rows_per_wave, fwd_block_cols, fwd_slabs;
+    int32_t back_rows_per_wave, back_block_cols, back_slabs;
+} sgtv_schedule;
+
+int sgtv_set_schedule(sgtv_ctx ctx, const sgtv_schedule *s);
+/* The schedule in use for the current system (automatic choices resolved),
+ * or the requested one if no system is set. */
+int sgtv_get_schedule(sgtv_ctx ctx, sgtv_schedule *s);
+
+/*
  * Kernel timing for measurement.  While enabled, sgtv_iterate brackets every
  * kernel launch with HIP events on the context stream.  sgtv_kernel_times
- * synchronises, adds the elapsed milliseconds per kernel class to ms[0..3]
- * and the launch counts to counts[0..3], then clears the record.  Classes:
- * 0 forward projection and ratio, 1 backprojection with image update,
- * 2 split and dual update, 3 anything else.
+ * synchronises, adds the elapsed milliseconds per kernel class to ms[0..4]
+ * and the launch counts to counts[0..4], then clears the record.  Classes:
+ * 0 forward projection A f (sliced ELL: fused with the ratio), 1
+ * backprojection A^T t (sliced ELL: fused with the image update), 2 split and
+ * dual update, 3 ratio y / (A f + r) of the tiled format, 4 image update of
+ * the tiled format.
  */
 int sgtv_set_profiling(sgtv_ctx ctx, int enable);
 int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts);

@@ -140,15 +140,161 @@ void pack_sell(int64_t n_lines, const std::vector<int64_t> &lptr, const std::vec
     }
 }
 
+struct Tiled {
+    DBuf pk, val, goff;
+    sgtv::TileMap map{};
+};
+
+// Parameters of one tiled product, after automatic choices.
+struct TileParams {
+    int rw, waves, cb, ns;
+};
+
+int64_t next_pow2(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Automatic schedule: column blocks of up to 16K entries, slabs so that one
+// slab of the gathered vector is at most 1 MiB (an XCD's L2 keeps it), and
+// rows per wave so that the grid has about 512 workgroups.
+TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int cb, int ns) {
+    TileParams t;
+    t.waves = waves > 0 ? waves : 16;
+    t.cb = cb > 0 ? cb : static_cast<int>(std::min<int64_t>(16384, std::max<int64_t>(4, next_pow2(n_cols))));
+    const int64_t ncb = (n_cols + t.cb - 1) / t.cb;
+    if (ns > 0) {
+        t.ns = ns;
+    } else {
+        int64_t want = next_pow2((n_cols * 4 + (1 << 20) - 1) >> 20);
+        t.ns = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({want, 8, ncb})));
+    }
+    if (t.ns > ncb) t.ns = static_cast<int>(std::max<int64_t>(1, ncb));
+    if (rw > 0) {
+        t.rw = rw;
+    } else {
+        int r = 1024;
+        while (r > 64 && ((n_rows + int64_t(t.waves) * r - 1) / (int64_t(t.waves) * r)) * t.ns < 512) r >>= 1;
+        t.rw = r;
+    }
+    return t;
+}
+
+size_t tile_lds_bytes(const TileParams &t) {
+    size_t a = static_cast<size_t>(t.waves) * (t.rw + 1) * 4;
+    a = (a + 15) / 16 * 16;
+    return a + static_cast<size_t>(t.cb) * 4;
+}
+
+// Host packing of one tiled product from CSR-like lines (rows of M in order,
+// column indices ascending within a row).  V is float or a 16-bit code.
+template <class V>
+int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
+                const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
+                std::vector<int32_t> &pk, std::vector<V> &pv, std::vector<int32_t> &goff,
+                sgtv::TileMap &map) {
+    const int64_t RB = static_cast<int64_t>(t.waves) * t.rw;
+    const int64_t n_rb = (n_rows + RB - 1) / RB;
+    const int64_t ncb = (n_cols + t.cb - 1) / t.cb;
+    const int ns = t.ns;
+    std::vector<int> slab_begin(ns + 1);
+    for (int k = 0; k <= ns; ++k) slab_begin[k] = static_cast<int>((k * ncb) / ns);
+    int cbs_max = 0;
+    for (int k = 0; k < ns; ++k) cbs_max = std::max(cbs_max, slab_begin[k + 1] - slab_begin[k]);
+    std::vector<int> slab_of(static_cast<size_t>(ncb));
+    for (int k = 0; k < ns; ++k)
+        for (int b = slab_begin[k]; b < slab_begin[k + 1]; ++b) slab_of[b] = k;
+    const int64_t n_lists = n_rb * ns * cbs_max * t.waves;
+    auto list_of = [&](int64_t r, int32_t c) -> int64_t {
+        const int64_t rb = r / RB, i = r - rb * RB;
+        const int64_t w = i / t.rw;
+        const int64_t cbi = c / t.cb;
+        const int slab = slab_of[cbi];
+        return ((rb * ns + slab) * cbs_max + (cbi - slab_begin[slab])) * t.waves + w;
+    };
+    std::vector<int32_t> count(static_cast<size_t>(n_lists), 0), run(static_cast<size_t>(n_lists), 0),
+        maxrun(static_cast<size_t>(n_lists), 0);
+    std::vector<int64_t> last(static_cast<size_t>(n_lists), -1);
+    for (int64_t r = 0; r < n_rows; ++r)
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+            const int64_t L = list_of(r, ci[k]);
+            count[L]++;
+            run[L] = last[L] == r ? run[L] + 1 : 1;
+            last[L] = r;
+            maxrun[L] = std::max(maxrun[L], run[L]);
+        }
+    goff.assign(static_cast<size_t>(n_lists + 1), 0);
+    int64_t total = 0;
+    std::vector<int32_t> ngr(static_cast<size_t>(n_lists));
+    for (int64_t L = 0; L < n_lists; ++L) {
+        const int64_t ng = count[L] ? std::max<int64_t>((count[L] + 63) / 64, maxrun[L]) : 0;
+        ngr[L] = static_cast<int32_t>(ng);
+        goff[L] = static_cast<int32_t>(total);
+        total += ng;
+        if (total * 64 >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "tiled matrix exceeds 2^31 stored entries");
+    }
+    goff[n_lists] = static_cast<int32_t>(total);
+    pk.assign(static_cast<size_t>(total * 64), t.rw << 16);
+    pv.assign(static_cast<size_t>(total * 64), V(0));
+    std::fill(count.begin(), count.end(), 0);   // reuse as cursor
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t rl = (r % RB) % t.rw;
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+            const int32_t c = ci[k];
+            const int64_t L = list_of(r, c);
+            const int64_t kk = count[L]++;
+            const int64_t ng = ngr[L];
+            const int64_t g = kk % ng, lane = kk / ng;
+            const int64_t nb4 = ng / 4;
+            const int64_t base = static_cast<int64_t>(goff[L]) * 64;
+            const int64_t pos = g < nb4 * 4 ? base + (g / 4) * 256 + lane * 4 + (g % 4)
+                                            : base + nb4 * 256 + (g - nb4 * 4) * 64 + lane;
+            pk[pos] = static_cast<int32_t>((rl << 16) | (c % t.cb));
+            pv[pos] = vals[k];
+        }
+    }
+    map = sgtv::TileMap{};
+    map.n_rows = n_rows;
+    map.n_cols = n_cols;
+    map.n_rb = n_rb;
+    map.rw = t.rw;
+    map.waves = t.waves;
+    map.cb = t.cb;
+    map.ns = ns;
+    map.cbs_max = cbs_max;
+    for (int k = 0; k <= ns; ++k) map.slab_begin[k] = slab_begin[k];
+    return SGTV_OK;
+}
+
+template <class V>
+int upload_tiled(Tiled &T, int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
+                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t) {
+    std::vector<int32_t> pk, goff;
+    std::vector<V> pv;
+    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, pk, pv, goff, T.map)) return e;
+    HIP_TRY(upload(T.pk, pk));
+    HIP_TRY(upload(T.val, pv));
+    HIP_TRY(upload(T.goff, goff));
+    T.map.pk = T.pk.as<int32_t>();
+    T.map.val = T.val.p;
+    T.map.goff = T.goff.as<int32_t>();
+    return SGTV_OK;
+}
+
 struct System {
     int64_t I = 0, J = 0, S = 0, nnz = 0;
     int ny = 0, nx = 0, Q = 0, vt = SGTV_F32;
+    int format = SGTV_FORMAT_TILED;
+    sgtv_schedule sched{};       // resolved schedule
     sgtv::Grid grid{};
     float w4[4] = {1, 1, 1, 1};
     bool wfull = false;
     DBuf rs_ptr, rs_idx, rs_val, cs_ptr, cs_idx, cs_val, colscale, sens, H, wbuf;
-    std::vector<int64_t> perm;   // internal row -> caller row
+    std::vector<int64_t> perm;   // internal row -> caller row (identity for tiles)
     int64_t n_rslices = 0, n_cslices = 0;
+    Tiled fwd, back;             // tiled format: A (rows = measurements), A^T (rows = voxels)
+    DBuf fpart, bpart;           // per-slab partial sums
 
     sgtv::Sell rows() const {
         return {rs_ptr.as<int64_t>(), rs_idx.as<int32_t>(), rs_val.p, nullptr, I, n_rslices};
@@ -170,6 +316,7 @@ struct System {
 struct sgtv_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    sgtv_schedule want{};        // requested schedule for the next system
     std::unique_ptr<System> sys;
     // data
     bool has_data = false;
@@ -275,6 +422,18 @@ int stage_floats(DBuf &dst, const float *src, int64_t n, int mk, hipStream_t st,
     return SGTV_OK;
 }
 
+// e = A^T t with the stored values (scaled back for 16-bit codes).
+int back_project(const System &S, const float *t, float *e, hipStream_t st) {
+    if (S.format == SGTV_FORMAT_TILED) {
+        HIP_TRY(sgtv::launch_tiled(S.back.map, S.vt, t, S.bpart.as<float>(), st));
+        HIP_TRY(sgtv::launch_back_combine(S.bpart.as<float>(), S.back.map.ns, S.J,
+                                          S.vt == SGTV_F32 ? nullptr : S.colscale.as<float>(), e, st));
+    } else {
+        HIP_TRY(sgtv::launch_back(S.cols(), S.vt, t, e, st));
+    }
+    return SGTV_OK;
+}
+
 int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t ny, int32_t nx,
                  int32_t Q, const int64_t *row_ptr, const int32_t *col_idx, const float *val,
                  int64_t nnz, int vt, const float *w, int64_t w_len, int mk) {
@@ -331,17 +490,6 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
     }
     std::vector<float> Hf(Hd.begin(), Hd.end());
 
-    // internal row order: rows sorted by decreasing length (stable), so that
-    // the 64 rows of a slice have nearly equal lengths
-    int64_t maxlen = 0;
-    for (int64_t i = 0; i < I; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i]);
-    std::vector<int64_t> cnt(static_cast<size_t>(maxlen + 2), 0);
-    for (int64_t i = 0; i < I; ++i) cnt[maxlen - (rp[i + 1] - rp[i])]++;
-    std::vector<int64_t> start(static_cast<size_t>(maxlen + 2), 0);
-    for (int64_t b = 1; b <= maxlen + 1; ++b) start[b] = start[b - 1] + cnt[b - 1];
-    S->perm.assign(static_cast<size_t>(I), 0);
-    for (int64_t i = 0; i < I; ++i) S->perm[start[maxlen - (rp[i + 1] - rp[i])]++] = i;
-
     // column scales and 16-bit codes
     std::vector<float> sigma;
     std::vector<uint16_t> codes;
@@ -356,65 +504,116 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         }
         for (int64_t j = 0; j < J; ++j)
             if (sigma[j] == 0.0f) sigma[j] = 1.0f;   // empty / all-zero column: any scale
-    }
-
-    // rows in internal order
-    std::vector<int64_t> lp(static_cast<size_t>(I + 1), 0);
-    for (int64_t i = 0; i < I; ++i) {
-        const int64_t o = S->perm[i];
-        lp[i + 1] = lp[i] + (rp[o + 1] - rp[o]);
-    }
-    std::vector<int32_t> lidx(static_cast<size_t>(nnz));
-    std::vector<int64_t> lsrc(static_cast<size_t>(nnz));   // position in caller CSR
-    for (int64_t i = 0; i < I; ++i) {
-        const int64_t o = S->perm[i];
-        for (int64_t t = 0; t < rp[o + 1] - rp[o]; ++t) {
-            lidx[lp[i] + t] = ci[rp[o] + t];
-            lsrc[lp[i] + t] = rp[o] + t;
-        }
-    }
-    // columns: counting sort of the internal-order rows, rows ascending within a column
-    std::vector<int64_t> cp(static_cast<size_t>(J + 1), 0);
-    for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
-    for (int64_t j = 0; j < J; ++j) cp[j + 1] += cp[j];
-    std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
-    std::vector<int32_t> cidx(static_cast<size_t>(nnz));
-    std::vector<int64_t> csrc(static_cast<size_t>(nnz));
-    for (int64_t i = 0; i < I; ++i)
-        for (int64_t k = lp[i]; k < lp[i + 1]; ++k) {
-            const int64_t pos = cur[lidx[k]]++;
-            cidx[pos] = static_cast<int32_t>(i);
-            csrc[pos] = lsrc[k];
-        }
-
-    std::vector<int64_t> rsp, csp;
-    std::vector<int32_t> rsi, csi;
-    if (vt == SGTV_F32) {
-        std::vector<float> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
-        for (int64_t k = 0; k < nnz; ++k) { lv[k] = av[lsrc[k]]; cv[k] = av[csrc[k]]; }
-        std::vector<float> rsv, csv;
-        pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
-        pack_sell(J, cp, cidx, cv, csp, csi, csv);
-        HIP_TRY(upload(S->rs_val, rsv));
-        HIP_TRY(upload(S->cs_val, csv));
-    } else {
-        std::vector<uint16_t> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
-        for (int64_t k = 0; k < nnz; ++k) { lv[k] = codes[lsrc[k]]; cv[k] = codes[csrc[k]]; }
-        std::vector<uint16_t> rsv, csv;
-        pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
-        pack_sell(J, cp, cidx, cv, csp, csi, csv);
-        HIP_TRY(upload(S->rs_val, rsv));
-        HIP_TRY(upload(S->cs_val, csv));
         HIP_TRY(upload(S->colscale, sigma));
     }
-    if (rsp.back() >= (int64_t(1) << 31) || csp.back() >= (int64_t(1) << 31))
-        return fail(SGTV_ESHAPE, "padded matrix exceeds 2^31 entries");
-    S->n_rslices = static_cast<int64_t>(rsp.size()) - 1;
-    S->n_cslices = static_cast<int64_t>(csp.size()) - 1;
-    HIP_TRY(upload(S->rs_ptr, rsp));
-    HIP_TRY(upload(S->rs_idx, rsi));
-    HIP_TRY(upload(S->cs_ptr, csp));
-    HIP_TRY(upload(S->cs_idx, csi));
+
+    S->format = c->want.format;
+    S->sched = c->want;
+    if (S->format == SGTV_FORMAT_TILED) {
+        const sgtv_schedule &q = c->want;
+        const TileParams tf = choose_tiles(I, J, q.waves, q.fwd_rows_per_wave, q.fwd_block_cols, q.fwd_slabs);
+        const TileParams tb = choose_tiles(J, I, q.waves, q.back_rows_per_wave, q.back_block_cols, q.back_slabs);
+        if (tile_lds_bytes(tf) > 163840 || tile_lds_bytes(tb) > 163840)
+            return fail(SGTV_EINVAL, "schedule needs more than 160 KiB of LDS per workgroup");
+        S->sched.waves = tf.waves;
+        S->sched.fwd_rows_per_wave = tf.rw; S->sched.fwd_block_cols = tf.cb; S->sched.fwd_slabs = tf.ns;
+        S->sched.back_rows_per_wave = tb.rw; S->sched.back_block_cols = tb.cb; S->sched.back_slabs = tb.ns;
+        S->perm.resize(static_cast<size_t>(I));
+        for (int64_t i = 0; i < I; ++i) S->perm[i] = i;
+        // transpose (counting sort by column; rows ascending within a column)
+        std::vector<int64_t> cp(static_cast<size_t>(J + 1), 0);
+        for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
+        for (int64_t j = 0; j < J; ++j) cp[j + 1] += cp[j];
+        std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
+        std::vector<int32_t> cidx(static_cast<size_t>(nnz));
+        std::vector<int64_t> csrc(static_cast<size_t>(nnz));
+        for (int64_t i = 0; i < I; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int64_t pos = cur[ci[k]]++;
+                cidx[pos] = static_cast<int32_t>(i);
+                csrc[pos] = k;
+            }
+        if (vt == SGTV_F32) {
+            if (int e = upload_tiled(S->fwd, I, J, rp, ci, av, tf)) return e;
+            std::vector<float> cv(static_cast<size_t>(nnz));
+            for (int64_t k = 0; k < nnz; ++k) cv[k] = av[csrc[k]];
+            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb)) return e;
+        } else {
+            if (int e = upload_tiled(S->fwd, I, J, rp, ci, codes, tf)) return e;
+            std::vector<uint16_t> cv(static_cast<size_t>(nnz));
+            for (int64_t k = 0; k < nnz; ++k) cv[k] = codes[csrc[k]];
+            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb)) return e;
+        }
+        HIP_TRY(S->fpart.alloc(sizeof(float) * I * tf.ns));
+        HIP_TRY(S->bpart.alloc(sizeof(float) * J * tb.ns));
+    } else {
+        // internal row order: rows sorted by decreasing length (stable), so that
+        // the 64 rows of a slice have nearly equal lengths
+        int64_t maxlen = 0;
+        for (int64_t i = 0; i < I; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i]);
+        std::vector<int64_t> cnt(static_cast<size_t>(maxlen + 2), 0);
+        for (int64_t i = 0; i < I; ++i) cnt[maxlen - (rp[i + 1] - rp[i])]++;
+        std::vector<int64_t> start(static_cast<size_t>(maxlen + 2), 0);
+        for (int64_t b = 1; b <= maxlen + 1; ++b) start[b] = start[b - 1] + cnt[b - 1];
+        S->perm.assign(static_cast<size_t>(I), 0);
+        for (int64_t i = 0; i < I; ++i) S->perm[start[maxlen - (rp[i + 1] - rp[i])]++] = i;
+
+        std::vector<int64_t> lp(static_cast<size_t>(I + 1), 0);
+        for (int64_t i = 0; i < I; ++i) {
+            const int64_t o = S->perm[i];
+            lp[i + 1] = lp[i] + (rp[o + 1] - rp[o]);
+        }
+        std::vector<int32_t> lidx(static_cast<size_t>(nnz));
+        std::vector<int64_t> lsrc(static_cast<size_t>(nnz));   // position in caller CSR
+        for (int64_t i = 0; i < I; ++i) {
+            const int64_t o = S->perm[i];
+            for (int64_t t = 0; t < rp[o + 1] - rp[o]; ++t) {
+                lidx[lp[i] + t] = ci[rp[o] + t];
+                lsrc[lp[i] + t] = rp[o] + t;
+            }
+        }
+        // columns: counting sort of the internal-order rows, rows ascending within a column
+        std::vector<int64_t> cp(static_cast<size_t>(J + 1), 0);
+        for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
+        for (int64_t j = 0; j < J; ++j) cp[j + 1] += cp[j];
+        std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
+        std::vector<int32_t> cidx(static_cast<size_t>(nnz));
+        std::vector<int64_t> csrc(static_cast<size_t>(nnz));
+        for (int64_t i = 0; i < I; ++i)
+            for (int64_t k = lp[i]; k < lp[i + 1]; ++k) {
+                const int64_t pos = cur[lidx[k]]++;
+                cidx[pos] = static_cast<int32_t>(i);
+                csrc[pos] = lsrc[k];
+            }
+
+        std::vector<int64_t> rsp, csp;
+        std::vector<int32_t> rsi, csi;
+        if (vt == SGTV_F32) {
+            std::vector<float> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
+            for (int64_t k = 0; k < nnz; ++k) { lv[k] = av[lsrc[k]]; cv[k] = av[csrc[k]]; }
+            std::vector<float> rsv, csv;
+            pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
+            pack_sell(J, cp, cidx, cv, csp, csi, csv);
+            HIP_TRY(upload(S->rs_val, rsv));
+            HIP_TRY(upload(S->cs_val, csv));
+        } else {
+            std::vector<uint16_t> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
+            for (int64_t k = 0; k < nnz; ++k) { lv[k] = codes[lsrc[k]]; cv[k] = codes[csrc[k]]; }
+            std::vector<uint16_t> rsv, csv;
+            pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
+            pack_sell(J, cp, cidx, cv, csp, csi, csv);
+            HIP_TRY(upload(S->rs_val, rsv));
+            HIP_TRY(upload(S->cs_val, csv));
+        }
+        if (rsp.back() >= (int64_t(1) << 31) || csp.back() >= (int64_t(1) << 31))
+            return fail(SGTV_ESHAPE, "padded matrix exceeds 2^31 entries");
+        S->n_rslices = static_cast<int64_t>(rsp.size()) - 1;
+        S->n_cslices = static_cast<int64_t>(csp.size()) - 1;
+        HIP_TRY(upload(S->rs_ptr, rsp));
+        HIP_TRY(upload(S->rs_idx, rsi));
+        HIP_TRY(upload(S->cs_ptr, csp));
+        HIP_TRY(upload(S->cs_idx, csi));
+    }
     HIP_TRY(upload(S->H, Hf));
     if (S->wfull) HIP_TRY(upload(S->wbuf, wf));
 
@@ -423,7 +622,7 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
     DBuf d_ones;
     HIP_TRY(upload(d_ones, ones));
     HIP_TRY(S->sens.alloc(sizeof(float) * J));
-    HIP_TRY(sgtv::launch_back(S->cols(), vt, d_ones.as<float>(), S->sens.as<float>(), c->stream));
+    if (int e = back_project(*S, d_ones.as<float>(), S->sens.as<float>(), c->stream)) return e;
     HIP_TRY(hipStreamSynchronize(c->stream));
     out = std::move(S);
     return SGTV_OK;
@@ -467,19 +666,46 @@ int step(sgtv_ctx_s *c) {
     const System &S = *c->sys;
     const sgtv::Weights w = S.weights();
     const float lam = static_cast<float>(c->rho);
+    const float *scale = S.vt == SGTV_F32 ? nullptr : S.colscale.as<float>();
+    float *gs_next = S.vt == SGTV_F32 ? nullptr : c->fs.as<float>();
     for (int sw = 0; sw < c->sweeps; ++sw) {
         const float *x = S.vt == SGTV_F32 ? c->f[c->fcur].as<float>() : c->fs.as<float>();
-        {
-            TimedLaunch t(c, 0);
-            HIP_TRY(sgtv::launch_forward_ratio(S.rows(), S.vt, x, c->y.as<float>(), c->r.as<float>(),
-                                               c->ratio.as<float>(), nullptr, false, c->stream, nullptr));
+        if (S.format == SGTV_FORMAT_TILED) {
+            {
+                TimedLaunch t(c, 0);
+                HIP_TRY(sgtv::launch_tiled(S.fwd.map, S.vt, x, S.fpart.as<float>(), c->stream));
+            }
+            {
+                TimedLaunch t(c, 3);
+                HIP_TRY(sgtv::launch_ratio_combine(S.fpart.as<float>(), S.fwd.map.ns, S.I, c->y.as<float>(),
+                                                   c->r.as<float>(), c->ratio.as<float>(), nullptr, false,
+                                                   c->stream, nullptr));
+            }
+            {
+                TimedLaunch t(c, 1);
+                HIP_TRY(sgtv::launch_tiled(S.back.map, S.vt, c->ratio.as<float>(), S.bpart.as<float>(), c->stream));
+            }
+            {
+                TimedLaunch t(c, 4);
+                HIP_TRY(sgtv::launch_voxel_update(S.bpart.as<float>(), S.back.map.ns, scale,
+                                                  c->f[c->fcur].as<float>(), c->f[c->fcur ^ 1].as<float>(),
+                                                  gs_next, c->v[c->vcur].as<float>(), c->a[c->vcur].as<float>(),
+                                                  S.sens.as<float>(), S.H.as<float>(), S.grid, w,
+                                                  c->grouping, lam, c->stream));
+            }
+        } else {
+            {
+                TimedLaunch t(c, 0);
+                HIP_TRY(sgtv::launch_forward_ratio(S.rows(), S.vt, x, c->y.as<float>(), c->r.as<float>(),
+                                                   c->ratio.as<float>(), nullptr, false, c->stream, nullptr));
+            }
+            TimedLaunch t(c, 1);
+            HIP_TRY(sgtv::launch_back_update(S.cols(), S.vt, c->ratio.as<float>(), c->f[c->fcur].as<float>(),
+                                             c->f[c->fcur ^ 1].as<float>(), c->fs.as<float>(),
+                                             c->v[c->vcur].as<float>(), c->a[c->vcur].as<float>(),
+                                             S.sens.as<float>(), S.H.as<float>(), S.grid, w,
+                                             c->grouping, lam, c->stream));
         }
-        TimedLaunch t(c, 1);
-        HIP_TRY(sgtv::launch_back_update(S.cols(), S.vt, c->ratio.as<float>(), c->f[c->fcur].as<float>(),
-                                         c->f[c->fcur ^ 1].as<float>(), c->fs.as<float>(),
-                                         c->v[c->vcur].as<float>(), c->a[c->vcur].as<float>(),
-                                         S.sens.as<float>(), c->sys->H.as<float>(), S.grid, w,
-                                         c->grouping, lam, c->stream));
         c->fcur ^= 1;
     }
     TimedLaunch t(c, 2);
@@ -687,8 +913,15 @@ int sgtv_objective(sgtv_ctx ctx, sgtv_report *out) {
     double *red = ctx->red.as<double>();
     int64_t n1 = 0, n2 = 0;
     const float *x = S.vt == SGTV_F32 ? ctx->f[ctx->fcur].as<float>() : ctx->fs.as<float>();
-    HIP_TRY(sgtv::launch_forward_ratio(S.rows(), S.vt, x, ctx->y.as<float>(), ctx->r.as<float>(),
-                                       ctx->ratio.as<float>(), part, true, ctx->stream, &n1));
+    if (S.format == SGTV_FORMAT_TILED) {
+        HIP_TRY(sgtv::launch_tiled(S.fwd.map, S.vt, x, S.fpart.as<float>(), ctx->stream));
+        HIP_TRY(sgtv::launch_ratio_combine(S.fpart.as<float>(), S.fwd.map.ns, S.I, ctx->y.as<float>(),
+                                           ctx->r.as<float>(), ctx->ratio.as<float>(), part, true,
+                                           ctx->stream, &n1));
+    } else {
+        HIP_TRY(sgtv::launch_forward_ratio(S.rows(), S.vt, x, ctx->y.as<float>(), ctx->r.as<float>(),
+                                           ctx->ratio.as<float>(), part, true, ctx->stream, &n1));
+    }
     HIP_TRY(sgtv::launch_reduce(part, n1, 1, red, ctx->stream));
     HIP_TRY(sgtv::launch_report(ctx->f[ctx->fcur].as<float>(), ctx->v[ctx->vcur].as<float>(),
                                 ctx->a[ctx->vcur].as<float>(), ctx->v[ctx->vcur ^ 1].as<float>(),
@@ -798,10 +1031,32 @@ int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind) {
     DBuf e, out;
     HIP_TRY(e.alloc(sizeof(float) * S.J));
     HIP_TRY(out.alloc(sizeof(float) * S.J));
-    HIP_TRY(sgtv::launch_back(S.cols(), S.vt, ctx->y.as<float>(), e.as<float>(), ctx->stream));
+    if (int st = back_project(S, ctx->y.as<float>(), e.as<float>(), ctx->stream)) return st;
     HIP_TRY(sgtv::launch_div_safe(e.as<float>(), S.sens.as<float>(), out.as<float>(), S.J, ctx->stream));
     HIP_TRY(hipMemcpyAsync(x, out.p, sizeof(float) * S.J, to_caller(mem_kind), ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SGTV_OK;
+}
+
+int sgtv_set_schedule(sgtv_ctx ctx, const sgtv_schedule *s) {
+    if (!ctx || !s) return fail(SGTV_EINVAL, "null argument");
+    if (s->format != SGTV_FORMAT_TILED && s->format != SGTV_FORMAT_SELL) return fail(SGTV_EINVAL, "unknown format");
+    if (s->waves < 0 || s->waves > 16) return fail(SGTV_EINVAL, "waves must be in [1, 16] (0: automatic)");
+    const int32_t rws[2] = {s->fwd_rows_per_wave, s->back_rows_per_wave};
+    const int32_t cbs[2] = {s->fwd_block_cols, s->back_block_cols};
+    const int32_t nss[2] = {s->fwd_slabs, s->back_slabs};
+    for (int i = 0; i < 2; ++i) {
+        if (rws[i] < 0 || rws[i] > 32767) return fail(SGTV_EINVAL, "rows_per_wave must be in [1, 32767]");
+        if (cbs[i] < 0 || cbs[i] > 65536 || (cbs[i] % 4) != 0) return fail(SGTV_EINVAL, "block_cols must be a multiple of 4 in [4, 65536]");
+        if (nss[i] < 0 || nss[i] > sgtv::kMaxSlabs) return fail(SGTV_EINVAL, "slabs must be in [1, 16]");
+    }
+    ctx->want = *s;
+    return SGTV_OK;
+}
+
+int sgtv_get_schedule(sgtv_ctx ctx, sgtv_schedule *s) {
+    if (!ctx || !s) return fail(SGTV_EINVAL, "null argument");
+    *s = ctx->sys ? ctx->sys->sched : ctx->want;
     return SGTV_OK;
 }
 
@@ -813,7 +1068,7 @@ int sgtv_set_profiling(sgtv_ctx ctx, int enable) {
 
 int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts) {
     if (!ctx) return fail(SGTV_EINVAL, "null context");
-    if (!ms || !counts) return fail(SGTV_EINVAL, "ms and counts are required");
+    if (!ms || !counts) return fail(SGTV_EINVAL, "ms and counts (5 entries each) are required");
     DeviceGuard g(ctx->device);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     int status = SGTV_OK;
@@ -821,7 +1076,7 @@ int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts) {
         float el = 0.0f;
         hipError_t e = hipEventElapsedTime(&el, t.beg, t.end);
         if (e != hipSuccess && status == SGTV_OK) status = hip_fail(e, "hipEventElapsedTime");
-        if (e == hipSuccess && t.cls >= 0 && t.cls < 4) {
+        if (e == hipSuccess && t.cls >= 0 && t.cls < 5) {
             ms[t.cls] += el;
             counts[t.cls] += 1;
         }

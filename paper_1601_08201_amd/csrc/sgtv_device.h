@@ -1,0 +1,131 @@
+// Device helpers shared by the kernels of the ADMM iteration.
+#pragma once
+
+#include "sgtv_kernels.h"
+
+namespace sgtv {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned short v4u16 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- value codes
+template <int VT> struct Code;
+template <> struct Code<0> {
+    typedef float T;
+    typedef v4f V4;
+    static __device__ __forceinline__ float dec(float a) { return a; }
+};
+template <> struct Code<1> {   // bfloat16: upper half of an FP32 word
+    typedef unsigned short T;
+    typedef v4u16 V4;
+    static __device__ __forceinline__ float dec(unsigned short a) {
+        return __uint_as_float(static_cast<unsigned>(a) << 16);
+    }
+};
+template <> struct Code<2> {   // IEEE binary16
+    typedef unsigned short T;
+    typedef v4u16 V4;
+    static __device__ __forceinline__ float dec(unsigned short a) {
+        return static_cast<float>(__builtin_bit_cast(_Float16, a));
+    }
+};
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ float seg_sum(float v, int width) {
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double seg_sum(double v, int width) {
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum of one double per thread over the block, written by thread 0.
+__device__ __forceinline__ void block_sum_store(double v, double *out) {
+    __shared__ double sh[kBlock / kWave];
+    v = wave_sum(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) s += sh[w];
+        *out = s;
+    }
+}
+
+// ---------------------------------------------------------------- geometry
+__device__ __forceinline__ int64_t neighbour(const Grid &g, int64_t s, int iy, int ix, int p) {
+    switch (p) {
+    case 0: return ix + 1 < g.nx ? s + 1 : -1;
+    case 1: return ix > 0 ? s - 1 : -1;
+    case 2: return iy + 1 < g.ny ? s + g.nx : -1;
+    default: return iy > 0 ? s - g.nx : -1;
+    }
+}
+
+__device__ __forceinline__ float weight(const Weights &w, const Grid &g, int64_t s, int p, int q) {
+    return w.full ? w.full[(s * 4 + p) * g.Q + q] : w.w[p];
+}
+
+// Nonnegative root of H t^2 + B t - C = 0, C >= 0, H > 0; branch chosen so
+// neither form subtracts nearly equal numbers.
+__device__ __forceinline__ float voxel_root(float H, float B, float C) {
+    float disc = sqrtf(fmaf(B, B, 4.0f * H * C));
+    return B <= 0.0f ? (disc - B) / (2.0f * H) : (2.0f * C) / (B + disc);
+}
+
+__device__ __forceinline__ float shrink_factor(float nrm, float thr) {
+    return nrm > thr ? 1.0f - thr / nrm : 0.0f;
+}
+
+// Image update of one hyper-voxel j = (s, q) (Section III, Eq. 4, optimisation
+// transfer): with e = (A^T ratio)_j,
+//   gamma = lam * (D^T t)_j, t = w.*G g - d + c = w.*G g + v - 2 a v   (z = d - c)
+//   B = sens_j + gamma - lam H0_j g_j,  C = g_j e
+// the new value is the nonnegative root of (lam H0_j) t^2 + B t - C.
+template <int GROUPING>
+__device__ __forceinline__ float voxel_update_value(int64_t j, float e, const float *__restrict__ g,
+                                                    const float *__restrict__ v,
+                                                    const float *__restrict__ a,
+                                                    const float *__restrict__ sens,
+                                                    const float *__restrict__ H, const Grid &grid,
+                                                    const Weights &wts, float lam) {
+    const int Q = grid.Q;
+    const int64_t s = j / Q;
+    const int q = static_cast<int>(j - s * Q);
+    const int iy = static_cast<int>(s / grid.nx), ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
+    const float gs = g[j];
+    const float as = GROUPING == 0 ? a[s] : a[j];
+    float dt = 0.0f;   // (D^T t)_j
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int64_t nb = neighbour(grid, s, iy, ix, p);
+        const float gn = nb >= 0 ? g[nb * Q + q] : 0.0f;
+        const float wp = weight(wts, grid, s, p, q);
+        const float vs = v[(s * 4 + p) * Q + q];
+        const float ds = as * vs;
+        dt = fmaf(wp, fmaf(wp, gs - gn, vs - 2.0f * ds), dt);
+        if (nb >= 0) {
+            const int pb = p ^ 1;   // direction from the neighbour back to s
+            const float wn = weight(wts, grid, nb, pb, q);
+            const float vn = v[(nb * 4 + pb) * Q + q];
+            const float an = GROUPING == 0 ? a[nb] : a[nb * Q + q];
+            const float dn = an * vn;
+            dt = fmaf(-wn, fmaf(wn, gn - gs, vn - 2.0f * dn), dt);
+        }
+    }
+    const float h = lam * H[j];
+    const float B = sens[j] + lam * dt - h * gs;
+    const float C = gs * e;
+    return voxel_root(h, B, C);
+}
+
+}  // namespace sgtv

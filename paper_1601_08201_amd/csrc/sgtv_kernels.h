@@ -33,7 +33,42 @@ struct Sell {
     int64_t n_lines, n_slices;
 };
 
+// LDS-tiled sparse product y = M x with per-slab partial outputs.
+// Rows of M are cut into row blocks of waves * rw rows (one workgroup each;
+// wave w owns rows [w*rw, (w+1)*rw) of the block and keeps their sums in
+// LDS), columns into blocks of cb columns (staged in LDS one at a time) and
+// the column blocks into ns slabs.  Workgroup b works on row block b / ns and
+// slab b % ns, so all workgroups of a slab land on the same XCD and its
+// slice of x stays in that XCD's L2.  Entries of one (row block, slab,
+// column block, wave) list are stored in groups of 64 with 64 distinct rows,
+// four groups interleaved per 16-byte load; packed index = row << 16 | col.
+constexpr int kMaxSlabs = 16;
+struct TileMap {
+    const int32_t *pk;      // packed (row in wave, column in block), padding: row = rw
+    const void *val;        // values or 16-bit codes, padding: 0
+    const int32_t *goff;    // group offset of every list, n_lists + 1 entries
+    int64_t n_rows, n_cols;
+    int64_t n_rb;           // row blocks
+    int rw, waves, cb, ns, cbs_max;
+    int slab_begin[kMaxSlabs + 1];   // first column block of each slab
+    size_t lds_bytes() const {
+        size_t a = static_cast<size_t>(waves) * (rw + 1) * 4;
+        a = (a + 15) / 16 * 16;
+        return a + static_cast<size_t>(cb) * 4;
+    }
+};
+
 // Launchers (all asynchronous on `st`).
+hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st);
+hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,
+                                const float *r, float *ratio, double *partials, bool objective,
+                                hipStream_t st, int64_t *n_partials);
+hipError_t launch_back_combine(const float *part, int ns, int64_t n, const float *scale,
+                               float *e, hipStream_t st);
+hipError_t launch_voxel_update(const float *part, int ns, const float *scale, const float *g,
+                               float *g_next, float *gs_next, const float *v, const float *a,
+                               const float *sens, const float *H, const Grid &grid,
+                               const Weights &w, int grouping, float lam, hipStream_t st);
 hipError_t launch_forward_ratio(const Sell &A, int vt, const float *x, const float *y,
                                 const float *r, float *ratio, double *partials, bool objective,
                                 hipStream_t st, int64_t *n_partials);

@@ -1,0 +1,213 @@
+// LDS-tiled sparse products for the forward projection A f and the
+// backprojection A^T t of the ADMM iteration (Section III, image update).
+//
+// Random 4-byte gathers of the projected vector are the cost of a sparse
+// product on this matrix family: served from L2 they cap the value stream far
+// below HBM speed, served from LDS they do not.  So each workgroup keeps the
+// sums of its row block in LDS, stages the gathered vector one column block
+// at a time into LDS (read coalesced from L2, where the XCD-pinned slab of
+// the vector stays resident) and streams the entries of the block with
+// nontemporal 16-byte loads.  Every row of a wave's accumulator range is hit
+// by at most one lane per instruction, so read-modify-write needs no atomics
+// and each sum has a fixed order.
+#include "sgtv_device.h"
+
+namespace sgtv {
+
+template <int VT>
+__global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restrict__ x,
+                                                float *__restrict__ part) {
+    typedef typename Code<VT>::T T;
+    typedef typename Code<VT>::V4 V4;
+    extern __shared__ float lds[];
+    const int rw1 = M.rw + 1;
+    float *acc = lds;
+    const size_t acc_floats = (static_cast<size_t>(M.waves) * rw1 + 3) / 4 * 4;
+    float *xs = lds + acc_floats;
+
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int w = tid / kWave, lane = tid & (kWave - 1);
+    const int slab = static_cast<int>(blockIdx.x % M.ns);
+    const int64_t rb = blockIdx.x / M.ns;
+    float *my = acc + w * rw1;
+
+    for (int i = tid; i < M.waves * rw1; i += nthr) acc[i] = 0.0f;
+
+    const int cb0 = M.slab_begin[slab];
+    const int ncbs = M.slab_begin[slab + 1] - cb0;
+    const int32_t *__restrict__ pk = M.pk;
+    const T *__restrict__ val = static_cast<const T *>(M.val);
+    for (int c = 0; c < ncbs; ++c) {
+        const int64_t col0 = static_cast<int64_t>(cb0 + c) * M.cb;
+        const int64_t rem = M.n_cols - col0;
+        const int ncols = rem < M.cb ? static_cast<int>(rem) : M.cb;
+        __syncthreads();   // everyone is done with the previous block
+        if ((col0 & 3) == 0) {
+            const int n4 = ncols / 4;
+            const v4f *src = reinterpret_cast<const v4f *>(x + col0);
+            v4f *dst = reinterpret_cast<v4f *>(xs);
+            for (int i = tid; i < n4; i += nthr) dst[i] = src[i];
+            for (int i = n4 * 4 + tid; i < ncols; i += nthr) xs[i] = x[col0 + i];
+        } else {
+            for (int i = tid; i < ncols; i += nthr) xs[i] = x[col0 + i];
+        }
+        __syncthreads();
+        const int64_t L = ((rb * M.ns + slab) * M.cbs_max + c) * M.waves + w;
+        const int64_t g0 = M.goff[L];
+        const int ng = M.goff[L + 1] - static_cast<int>(g0);
+        const int nb4 = ng >> 2;
+        const int64_t base = g0 * kWave;
+        const v4i *p4 = reinterpret_cast<const v4i *>(pk + base) + lane;
+        const V4 *v4 = reinterpret_cast<const V4 *>(val + base) + lane;
+        for (int b = 0; b < nb4; ++b) {
+            const v4i p = __builtin_nontemporal_load(p4 + b * kWave);
+            const V4 a = __builtin_nontemporal_load(v4 + b * kWave);
+            float t;
+            t = xs[p.x & 0xFFFF]; my[p.x >> 16] = fmaf(Code<VT>::dec(a.x), t, my[p.x >> 16]);
+            t = xs[p.y & 0xFFFF]; my[p.y >> 16] = fmaf(Code<VT>::dec(a.y), t, my[p.y >> 16]);
+            t = xs[p.z & 0xFFFF]; my[p.z >> 16] = fmaf(Code<VT>::dec(a.z), t, my[p.z >> 16]);
+            t = xs[p.w & 0xFFFF]; my[p.w >> 16] = fmaf(Code<VT>::dec(a.w), t, my[p.w >> 16]);
+        }
+        const int64_t tail = base + static_cast<int64_t>(nb4) * 4 * kWave + lane;
+        for (int g = nb4 * 4; g < ng; ++g) {
+            const int64_t e = tail + static_cast<int64_t>(g - nb4 * 4) * kWave;
+            const int p = __builtin_nontemporal_load(pk + e);
+            const T a = __builtin_nontemporal_load(val + e);
+            const float t = xs[p & 0xFFFF];
+            my[p >> 16] = fmaf(Code<VT>::dec(a), t, my[p >> 16]);
+        }
+    }
+    __syncthreads();
+    const int64_t rb_rows = static_cast<int64_t>(M.waves) * M.rw;
+    const int64_t row0 = rb * rb_rows;
+    float *out = part + static_cast<int64_t>(slab) * M.n_rows;
+    for (int64_t i = tid; i < rb_rows; i += nthr) {
+        const int64_t row = row0 + i;
+        if (row < M.n_rows) out[row] = acc[(i / M.rw) * rw1 + (i % M.rw)];
+    }
+}
+
+// ratio_i = y_i / (sum_k part[k][i] + r_i), with optional FP64 partials of
+// the I-divergence sum_i p_i - y_i + y_i log(y_i / p_i).
+template <bool OBJ>
+__global__ __launch_bounds__(kBlock) void k_ratio_combine(const float *__restrict__ part, int ns,
+                                                          int64_t n, const float *__restrict__ y,
+                                                          const float *__restrict__ r,
+                                                          float *__restrict__ ratio,
+                                                          double *__restrict__ partials) {
+    double term = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock) {
+        float acc = part[i];
+        for (int k = 1; k < ns; ++k) acc += part[static_cast<int64_t>(k) * n + i];
+        const float p = acc + r[i];
+        const float yi = y[i];
+        ratio[i] = yi / p;
+        if (OBJ) {
+            const double pd = p, yd = yi;
+            double t = pd - yd;
+            if (yd > 0.0) t += yd * log(yd / pd);
+            term += t;
+        }
+    }
+    if (OBJ) block_sum_store(term, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_back_combine(const float *__restrict__ part, int ns,
+                                                         int64_t n, const float *__restrict__ scale,
+                                                         float *__restrict__ e) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock) {
+        float acc = part[i];
+        for (int k = 1; k < ns; ++k) acc += part[static_cast<int64_t>(k) * n + i];
+        e[i] = scale ? acc * scale[i] : acc;
+    }
+}
+
+template <int GROUPING>
+__global__ __launch_bounds__(kBlock) void k_voxel_update(
+    const float *__restrict__ part, int ns, const float *__restrict__ scale,
+    const float *__restrict__ g, float *__restrict__ g_next, float *__restrict__ gs_next,
+    const float *__restrict__ v, const float *__restrict__ a, const float *__restrict__ sens,
+    const float *__restrict__ H, Grid grid, Weights wts, float lam) {
+    const int64_t n = grid.J;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; j < n;
+         j += static_cast<int64_t>(gridDim.x) * kBlock) {
+        float e = part[j];
+        for (int k = 1; k < ns; ++k) e += part[static_cast<int64_t>(k) * n + j];
+        if (scale) e *= scale[j];
+        const float gnew = voxel_update_value<GROUPING>(j, e, g, v, a, sens, H, grid, wts, lam);
+        g_next[j] = gnew;
+        if (gs_next) gs_next[j] = gnew * scale[j];
+    }
+}
+
+static unsigned stride_blocks(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return static_cast<unsigned>(b);
+}
+
+hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st) {
+    const int64_t tiles = M.n_rb * M.ns;
+    if (tiles == 0) return hipSuccess;
+    const size_t lds = M.lds_bytes();
+    const dim3 grid(static_cast<unsigned>(tiles)), block(static_cast<unsigned>(M.waves * kWave));
+    hipError_t e;
+    if (vt == 0) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tiled<0>, grid, block, lds, st, M, x, part);
+    } else if (vt == 1) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<1>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tiled<1>, grid, block, lds, st, M, x, part);
+    } else {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<2>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tiled<2>, grid, block, lds, st, M, x, part);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,
+                                const float *r, float *ratio, double *partials, bool objective,
+                                hipStream_t st, int64_t *n_partials) {
+    const unsigned nb = stride_blocks(n) > 4096 ? 4096 : stride_blocks(n);
+    if (n_partials) *n_partials = nb;
+    if (objective)
+        hipLaunchKernelGGL(k_ratio_combine<true>, dim3(nb), dim3(kBlock), 0, st, part, ns, n, y, r,
+                           ratio, partials);
+    else
+        hipLaunchKernelGGL(k_ratio_combine<false>, dim3(nb), dim3(kBlock), 0, st, part, ns, n, y,
+                           r, ratio, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_back_combine(const float *part, int ns, int64_t n, const float *scale,
+                               float *e, hipStream_t st) {
+    hipLaunchKernelGGL(k_back_combine, dim3(stride_blocks(n)), dim3(kBlock), 0, st, part, ns, n,
+                       scale, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_voxel_update(const float *part, int ns, const float *scale, const float *g,
+                               float *g_next, float *gs_next, const float *v, const float *a,
+                               const float *sens, const float *H, const Grid &grid,
+                               const Weights &w, int grouping, float lam, hipStream_t st) {
+    const unsigned nb = stride_blocks(grid.J);
+    if (grouping == 0)
+        hipLaunchKernelGGL(k_voxel_update<0>, dim3(nb), dim3(kBlock), 0, st, part, ns, scale, g,
+                           g_next, gs_next, v, a, sens, H, grid, w, lam);
+    else
+        hipLaunchKernelGGL(k_voxel_update<1>, dim3(nb), dim3(kBlock), 0, st, part, ns, scale, g,
+                           g_next, gs_next, v, a, sens, H, grid, w, lam);
+    return hipGetLastError();
+}
+
+}  // namespace sgtv

@@ -38,6 +38,18 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("fwd_rows_per_wave", ctypes.c_int32), ("fwd_block_cols", ctypes.c_int32),
+                ("fwd_slabs", ctypes.c_int32), ("back_rows_per_wave", ctypes.c_int32),
+                ("back_block_cols", ctypes.c_int32), ("back_slabs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SGTV_FORMAT_TILED, SGTV_FORMAT_SELL = 0, 1
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -71,6 +83,8 @@ def lib():
             "sgtv_set_state": (_I, [_P, _P, _P, _P, _I64, _I]),
             "sgtv_backprojection": (_I, [_P, _P, _I]),
             "sgtv_set_profiling": (_I, [_P, _I]),
+            "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
+            "sgtv_get_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_kernel_times": (_I, [_P, _P, _P]),
         }
         for name, (res, args) in sig.items():
@@ -222,19 +236,31 @@ def sgtv_backprojection(ctx, out=None):
     return out
 
 
+def sgtv_set_schedule(ctx, **fields):
+    """Schedule for the next set_system; unnamed fields are automatic (0)."""
+    sch = Schedule(**{k: int(v) for k, v in fields.items()})
+    _check(lib().sgtv_set_schedule(ctx, ctypes.byref(sch)))
+
+
+def sgtv_get_schedule(ctx):
+    sch = Schedule()
+    _check(lib().sgtv_get_schedule(ctx, ctypes.byref(sch)))
+    return sch.as_dict()
+
+
 def sgtv_set_profiling(ctx, enable):
     _check(lib().sgtv_set_profiling(ctx, int(bool(enable))))
 
 
-KERNEL_CLASSES = ("forward_ratio", "back_update", "split_update", "other")
+KERNEL_CLASSES = ("forward", "back", "split_update", "ratio", "image_update")
 
 
 def sgtv_kernel_times(ctx):
     """{class: (total_ms, launches)} accumulated since the last call."""
-    ms = (ctypes.c_double * 4)()
-    cnt = (ctypes.c_int64 * 4)()
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
     _check(lib().sgtv_kernel_times(ctx, ctypes.cast(ms, _P), ctypes.cast(cnt, _P)))
-    return {KERNEL_CLASSES[i]: (ms[i], cnt[i]) for i in range(4)}
+    return {KERNEL_CLASSES[i]: (ms[i], cnt[i]) for i in range(5)}
 
 
 class Reconstructor:
@@ -303,6 +329,13 @@ class Reconstructor:
 
     def backprojection(self, out=None):
         return sgtv_backprojection(self._ctx, out)
+
+    def set_schedule(self, **fields):
+        sgtv_set_schedule(self._ctx, **fields)
+        return self
+
+    def schedule(self):
+        return sgtv_get_schedule(self._ctx)
 
     def set_profiling(self, enable=True):
         sgtv_set_profiling(self._ctx, enable)

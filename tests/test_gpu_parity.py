@@ -33,8 +33,10 @@ def sg():
     return sgtv
 
 
-def run_gpu(sg, prob, n, storage="f32", w=None, grouping=0, sweeps=None, x0=None):
+def run_gpu(sg, prob, n, storage="f32", w=None, grouping=0, sweeps=None, x0=None, schedule=None):
     R = sg.Reconstructor()
+    if schedule:
+        R.set_schedule(**schedule)
     R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val, storage=storage, w=w)
     if grouping:
         R.set_grouping(grouping)
@@ -45,8 +47,9 @@ def run_gpu(sg, prob, n, storage="f32", w=None, grouping=0, sweeps=None, x0=None
     return R
 
 
-def check_against_oracle(sg, prob, n, w=None, grouping=0, sweeps=None, x0=None, tol=IMG_TOL):
-    R = run_gpu(sg, prob, n, w=w, grouping=grouping, sweeps=sweeps, x0=x0)
+def check_against_oracle(sg, prob, n, w=None, grouping=0, sweeps=None, x0=None, tol=IMG_TOL,
+                         schedule=None):
+    R = run_gpu(sg, prob, n, w=w, grouping=grouping, sweeps=sweeps, x0=x0, schedule=schedule)
     f_g = R.image()
     d_g, c_g = R.split()
     rep = R.objective()
@@ -79,6 +82,21 @@ def test_spectral_sizes(sg, Q):
     prob = datagen.make_problem(dict(ny=5, nx=6, Q=Q, I=max(64, 3 * 30 * Q // 2), nnz_per_col=8,
                                      rects=3, beta=0.2, rho=1.0), seed=100 + Q)
     check_against_oracle(sg, prob, 20)
+
+
+SCHEDULES = {
+    "sell": dict(format=1),
+    "tiles-small": dict(format=0, waves=4, fwd_rows_per_wave=64, fwd_block_cols=1024, fwd_slabs=3,
+                        back_rows_per_wave=32, back_block_cols=512, back_slabs=2),
+    "tiles-one-wave": dict(format=0, waves=1, fwd_rows_per_wave=100, fwd_block_cols=4092, fwd_slabs=1,
+                           back_rows_per_wave=300, back_block_cols=12, back_slabs=5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SCHEDULES))
+def test_schedules_agree_with_oracle(sg, name):
+    prob = datagen.make_problem("small", 11)
+    check_against_oracle(sg, prob, 30, schedule=SCHEDULES[name])
 
 
 def test_non_square_grid_and_ragged_tails(sg):
