@@ -72,6 +72,7 @@ def _declare(lib):
         "or_objective_flat": (None, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
         "or_image_sweep_flat": (None, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _P, _P]),
         "or_plain_init_flat": (_D, [_I64, _I, _I, _I, _P, _P, _P, _P]),
+        "or_quantise": (None, [_I64, _I64, _P, _P, _I, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -213,6 +214,22 @@ def plain_init(prob):
     y = _f64(prob.y)
     return lib.or_plain_init_flat(prob.I, prob.ny, prob.nx, prob.Q, _ptr(rp), _ptr(c), _ptr(v),
                                   _ptr(y))
+
+
+def quantise(col, val, J, kind):
+    """Per-column scaled 16-bit codes of the matrix values (kind 'bf16' or 'f16').
+
+    Returns (scale float32[J], codes uint16[nnz], dequantised float64[nnz]).
+    """
+    lib = _load()
+    k = {"bf16": 1, "f16": 2}[kind]
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float32)
+    scale = np.empty(J, np.float32)
+    codes = np.empty(col.shape[0], np.uint16)
+    deq = np.empty(col.shape[0], np.float64)
+    lib.or_quantise(col.shape[0], J, _ptr(col), _ptr(val), k, _ptr(scale), _ptr(codes), _ptr(deq))
+    return scale, codes, deq
 
 
 def admm(prob, n_iter, f0=None, d0=None, c0=None, sweeps=None, beta=None, lam=None, w=None,

@@ -405,3 +405,76 @@ double or_plain_init_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowpt
     or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, NULL, NULL, 0.0, 1.0, 0);
     return or_plain_init(&P);
 }
+
+/*
+ * Reduced-precision storage of the system matrix: every column j gets the
+ * FP32 scale sigma_j = max_i a_ij and every value the 16-bit code of the FP32
+ * quotient a_ij / sigma_j, rounded to nearest-even (bfloat16: kind 1, IEEE
+ * binary16: kind 2).  The quotient is formed in FP32 so that both sides round
+ * the same number.  deq receives sigma_j * decode(code) in FP64, the matrix
+ * the reduced-precision path effectively multiplies with.
+ */
+static uint16_t rne_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static double bf16_value(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* binary16 from the IEEE 754 definition: 1 sign, 5 exponent (bias 15),
+ * 10 fraction bits, subnormals below 2^-14; inputs here are finite, >= 0. */
+static uint16_t rne_f16(float xf)
+{
+    double x = (double)xf;           /* exact */
+    if (x == 0.0)
+        return 0;
+    int e;
+    (void)frexp(x, &e);              /* x = m 2^e, m in [0.5, 1) */
+    int E = e - 1;                   /* x = (2m) 2^E, 2m in [1, 2) */
+    if (E < -14) {                   /* subnormal: units of 2^-24 */
+        double q = x / ldexp(1.0, -24);
+        double r = nearbyint(q);     /* round half to even (default mode) */
+        return (uint16_t)r;          /* may round up into the normal range */
+    }
+    double q = ldexp(x, 10 - E);     /* in [1024, 2048) */
+    double r = nearbyint(q);
+    if (r == 2048.0) { r = 1024.0; E += 1; }
+    if (E > 15)
+        return 0x7C00;               /* overflow to infinity (not reached for a / max) */
+    return (uint16_t)(((E + 15) << 10) | ((int)r - 1024));
+}
+
+static double f16_value(uint16_t h)
+{
+    int E = (h >> 10) & 0x1F, F = h & 0x3FF;
+    if (E == 0)
+        return ldexp((double)F, -24);
+    return ldexp(1024.0 + F, E - 25);
+}
+
+void or_quantise(int64_t nnz, int64_t J, const int32_t *col, const float *val, int kind,
+                 float *scale, uint16_t *codes, double *deq)
+{
+    for (int64_t j = 0; j < J; ++j)
+        scale[j] = 0.0f;
+    for (int64_t k = 0; k < nnz; ++k)
+        if (val[k] > scale[col[k]])
+            scale[col[k]] = val[k];
+    for (int64_t k = 0; k < nnz; ++k) {
+        float s = scale[col[k]];
+        float t = s > 0.0f ? val[k] / s : 0.0f;
+        uint16_t c = kind == 1 ? rne_bf16(t) : rne_f16(t);
+        codes[k] = c;
+        deq[k] = (double)s * (kind == 1 ? bf16_value(c) : f16_value(c));
+    }
+}

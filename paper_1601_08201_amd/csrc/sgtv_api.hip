@@ -157,7 +157,8 @@ int64_t next_pow2(int64_t v) {
 }
 
 // Automatic schedule: column blocks of up to 16K entries, slabs so that one
-// slab of the gathered vector is at most 1 MiB (an XCD's L2 keeps it), and
+// slab of the gathered vector is at most 2 MiB (an XCD's 4 MiB L2 keeps it
+// next to the streamed entries), and
 // rows per wave so that the grid has about 512 workgroups.
 TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int cb, int ns) {
     TileParams t;
@@ -167,7 +168,7 @@ TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int c
     if (ns > 0) {
         t.ns = ns;
     } else {
-        int64_t want = next_pow2((n_cols * 4 + (1 << 20) - 1) >> 20);
+        int64_t want = next_pow2((n_cols * 4 + (2 << 20) - 1) >> 21);
         t.ns = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({want, 8, ncb})));
     }
     if (t.ns > ncb) t.ns = static_cast<int>(std::max<int64_t>(1, ncb));

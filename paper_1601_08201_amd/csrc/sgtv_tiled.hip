@@ -14,6 +14,11 @@
 
 namespace sgtv {
 
+// Float4 chunks of the next column block each thread holds in registers while
+// the current block is being processed (blocks larger than this are staged
+// without the register prefetch).
+constexpr int kXPrefetch = 4;
+
 template <int VT>
 __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restrict__ x,
                                                 float *__restrict__ part) {
@@ -38,36 +43,79 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restri
     const int ncbs = M.slab_begin[slab + 1] - cb0;
     const int32_t *__restrict__ pk = M.pk;
     const T *__restrict__ val = static_cast<const T *>(M.val);
-    for (int c = 0; c < ncbs; ++c) {
-        const int64_t col0 = static_cast<int64_t>(cb0 + c) * M.cb;
+    const bool reg_prefetch = M.cb <= kXPrefetch * 4 * nthr;
+    const int64_t list0 = ((rb * M.ns + slab) * M.cbs_max) * M.waves + w;
+
+    // stage column block 0
+    if (ncbs > 0) {
+        const int64_t col0 = static_cast<int64_t>(cb0) * M.cb;
         const int64_t rem = M.n_cols - col0;
         const int ncols = rem < M.cb ? static_cast<int>(rem) : M.cb;
-        __syncthreads();   // everyone is done with the previous block
-        if ((col0 & 3) == 0) {
-            const int n4 = ncols / 4;
-            const v4f *src = reinterpret_cast<const v4f *>(x + col0);
-            v4f *dst = reinterpret_cast<v4f *>(xs);
-            for (int i = tid; i < n4; i += nthr) dst[i] = src[i];
-            for (int i = n4 * 4 + tid; i < ncols; i += nthr) xs[i] = x[col0 + i];
-        } else {
-            for (int i = tid; i < ncols; i += nthr) xs[i] = x[col0 + i];
+        for (int i = tid; i < ncols; i += nthr) xs[i] = x[col0 + i];
+    }
+    __syncthreads();
+
+    // first batch of list 0
+    int64_t g0 = ncbs > 0 ? M.goff[list0] : 0;
+    int ng = ncbs > 0 ? M.goff[list0 + 1] - static_cast<int>(g0) : 0;
+    v4i pn = {0, 0, 0, 0};
+    V4 an = {};
+    if (ng >= 4) {
+        pn = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(pk + g0 * kWave) + lane);
+        an = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(val + g0 * kWave) + lane);
+    }
+    for (int c = 0; c < ncbs; ++c) {
+        // next column block: issue its loads now, store them after the barrier
+        v4f xr[kXPrefetch];
+        const bool more = c + 1 < ncbs;
+        int64_t ncol0 = 0;
+        int nncols = 0;
+        if (more) {
+            ncol0 = static_cast<int64_t>(cb0 + c + 1) * M.cb;
+            const int64_t rem = M.n_cols - ncol0;
+            nncols = rem < M.cb ? static_cast<int>(rem) : M.cb;
+            if (reg_prefetch) {
+#pragma unroll
+                for (int k = 0; k < kXPrefetch; ++k) {
+                    const int i4 = (k * nthr + tid) * 4;
+                    if (i4 + 3 < nncols) xr[k] = *reinterpret_cast<const v4f *>(x + ncol0 + i4);
+                    else {
+                        v4f t = {0.f, 0.f, 0.f, 0.f};
+                        if (i4 < nncols) t.x = x[ncol0 + i4];
+                        if (i4 + 1 < nncols) t.y = x[ncol0 + i4 + 1];
+                        if (i4 + 2 < nncols) t.z = x[ncol0 + i4 + 2];
+                        xr[k] = t;
+                    }
+                }
+            }
         }
-        __syncthreads();
-        const int64_t L = ((rb * M.ns + slab) * M.cbs_max + c) * M.waves + w;
-        const int64_t g0 = M.goff[L];
-        const int ng = M.goff[L + 1] - static_cast<int>(g0);
+        // geometry of the next list (for the prefetch across the block boundary)
+        const int64_t ng0 = more ? M.goff[list0 + (c + 1) * M.waves] : 0;
+        const int nng = more ? M.goff[list0 + (c + 1) * M.waves + 1] - static_cast<int>(ng0) : 0;
+
         const int nb4 = ng >> 2;
         const int64_t base = g0 * kWave;
         const v4i *p4 = reinterpret_cast<const v4i *>(pk + base) + lane;
         const V4 *v4 = reinterpret_cast<const V4 *>(val + base) + lane;
         for (int b = 0; b < nb4; ++b) {
-            const v4i p = __builtin_nontemporal_load(p4 + b * kWave);
-            const V4 a = __builtin_nontemporal_load(v4 + b * kWave);
+            const v4i p = pn;
+            const V4 a = an;
+            if (b + 1 < nb4) {
+                pn = __builtin_nontemporal_load(p4 + (b + 1) * kWave);
+                an = __builtin_nontemporal_load(v4 + (b + 1) * kWave);
+            } else if (nng >= 4) {
+                pn = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(pk + ng0 * kWave) + lane);
+                an = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(val + ng0 * kWave) + lane);
+            }
             float t;
             t = xs[p.x & 0xFFFF]; my[p.x >> 16] = fmaf(Code<VT>::dec(a.x), t, my[p.x >> 16]);
             t = xs[p.y & 0xFFFF]; my[p.y >> 16] = fmaf(Code<VT>::dec(a.y), t, my[p.y >> 16]);
             t = xs[p.z & 0xFFFF]; my[p.z >> 16] = fmaf(Code<VT>::dec(a.z), t, my[p.z >> 16]);
             t = xs[p.w & 0xFFFF]; my[p.w >> 16] = fmaf(Code<VT>::dec(a.w), t, my[p.w >> 16]);
+        }
+        if (nb4 == 0 && nng >= 4) {
+            pn = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(pk + ng0 * kWave) + lane);
+            an = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(val + ng0 * kWave) + lane);
         }
         const int64_t tail = base + static_cast<int64_t>(nb4) * 4 * kWave + lane;
         for (int g = nb4 * 4; g < ng; ++g) {
@@ -76,6 +124,26 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restri
             const T a = __builtin_nontemporal_load(val + e);
             const float t = xs[p & 0xFFFF];
             my[p >> 16] = fmaf(Code<VT>::dec(a), t, my[p >> 16]);
+        }
+        g0 = ng0;
+        ng = nng;
+        if (more) {
+            __syncthreads();   // every wave is done with this block
+            if (reg_prefetch) {
+#pragma unroll
+                for (int k = 0; k < kXPrefetch; ++k) {
+                    const int i4 = (k * nthr + tid) * 4;
+                    if (i4 + 3 < nncols) *reinterpret_cast<v4f *>(xs + i4) = xr[k];
+                    else {
+                        if (i4 < nncols) xs[i4] = xr[k].x;
+                        if (i4 + 1 < nncols) xs[i4 + 1] = xr[k].y;
+                        if (i4 + 2 < nncols) xs[i4 + 2] = xr[k].z;
+                    }
+                }
+            } else {
+                for (int i = tid; i < nncols; i += nthr) xs[i] = x[ncol0 + i];
+            }
+            __syncthreads();
         }
     }
     __syncthreads();
