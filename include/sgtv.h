@@ -169,6 +169,9 @@ int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);
  *     sums are added afterwards (each slab is pinned to one XCD).
  *   format SGTV_FORMAT_SELL: sliced ELL, one lane per output row, gathers
  *     straight from memory (no other field applies).
+ *   variant: inner loop of the tiled products: 1 one batch of entries in
+ *     flight per wave, 2 two batches, 3 two batches plus the next column block
+ *     read ahead into registers (0: automatic).
  * Limits: waves in [1, 16]; rows_per_wave in [1, 32767]; block_cols a
  * multiple of 4 in [4, 65536]; slabs in [1, 16]; the LDS of one workgroup,
  * 4 * (waves * (rows_per_wave + 1) rounded up to 4 + block_cols) bytes, at
@@ -181,6 +184,7 @@ typedef struct {
     int32_t waves;
     int32_t fwd_rows_per_wave, fwd_block_cols, fwd_slabs;
     int32_t back_rows_per_wave, back_block_cols, back_slabs;
+    int32_t variant;
 } sgtv_schedule;
 
 int sgtv_set_schedule(sgtv_ctx ctx, const sgtv_schedule *s);

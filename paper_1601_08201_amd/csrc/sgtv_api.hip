@@ -19,6 +19,10 @@ namespace {
 
 thread_local std::string g_err;
 
+// Spare floats after every vector that the tiled products gather from: the
+// kernels stage whole float4 groups, which may run past the last element.
+constexpr int64_t kVecPad = 32;
+
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
@@ -159,7 +163,7 @@ int64_t next_pow2(int64_t v) {
 // Automatic schedule: column blocks of up to 16K entries, slabs so that one
 // slab of the gathered vector is at most 2 MiB (an XCD's 4 MiB L2 keeps it
 // next to the streamed entries), and
-// rows per wave so that the grid has about 512 workgroups.
+// rows per wave so that the grid has at least 256 workgroups (one per CU).
 TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int cb, int ns) {
     TileParams t;
     t.waves = waves > 0 ? waves : 16;
@@ -176,7 +180,7 @@ TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int c
         t.rw = rw;
     } else {
         int r = 1024;
-        while (r > 64 && ((n_rows + int64_t(t.waves) * r - 1) / (int64_t(t.waves) * r)) * t.ns < 512) r >>= 1;
+        while (r > 64 && ((n_rows + int64_t(t.waves) * r - 1) / (int64_t(t.waves) * r)) * t.ns < 256) r >>= 1;
         t.rw = r;
     }
     return t;
@@ -236,8 +240,10 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         if (total * 64 >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "tiled matrix exceeds 2^31 stored entries");
     }
     goff[n_lists] = static_cast<int32_t>(total);
-    pk.assign(static_cast<size_t>(total * 64), t.rw << 16);
-    pv.assign(static_cast<size_t>(total * 64), V(0));
+    // one extra all-padding batch at the end: the kernel streams it in place of
+    // a batch past the end of a list
+    pk.assign(static_cast<size_t>(total * 64 + 256), t.rw << 16);
+    pv.assign(static_cast<size_t>(total * 64 + 256), V(0));
     std::fill(count.begin(), count.end(), 0);   // reuse as cursor
     for (int64_t r = 0; r < n_rows; ++r) {
         const int64_t rl = (r % RB) % t.rw;
@@ -259,11 +265,13 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     map.n_rows = n_rows;
     map.n_cols = n_cols;
     map.n_rb = n_rb;
+    map.pad = total * 64;
     map.rw = t.rw;
     map.waves = t.waves;
     map.cb = t.cb;
     map.ns = ns;
     map.cbs_max = cbs_max;
+    map.variant = 0;
     for (int k = 0; k <= ns; ++k) map.slab_begin[k] = slab_begin[k];
     return SGTV_OK;
 }
@@ -351,11 +359,11 @@ int alloc_state(sgtv_ctx_s *c) {
     const System &S = *c->sys;
     const int64_t ng = n_groups(c);
     for (int b = 0; b < 2; ++b) {
-        HIP_TRY(c->f[b].alloc(sizeof(float) * S.J));
+        HIP_TRY(c->f[b].alloc(sizeof(float) * (S.J + kVecPad)));
         HIP_TRY(c->v[b].alloc(sizeof(float) * S.J * 4));
         HIP_TRY(c->a[b].alloc(sizeof(float) * ng));
     }
-    HIP_TRY(c->fs.alloc(sizeof(float) * S.J));
+    HIP_TRY(c->fs.alloc(sizeof(float) * (S.J + kVecPad)));
     return SGTV_OK;
 }
 
@@ -519,6 +527,7 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         S->sched.waves = tf.waves;
         S->sched.fwd_rows_per_wave = tf.rw; S->sched.fwd_block_cols = tf.cb; S->sched.fwd_slabs = tf.ns;
         S->sched.back_rows_per_wave = tb.rw; S->sched.back_block_cols = tb.cb; S->sched.back_slabs = tb.ns;
+        S->sched.variant = q.variant > 0 ? q.variant : 1;
         S->perm.resize(static_cast<size_t>(I));
         for (int64_t i = 0; i < I; ++i) S->perm[i] = i;
         // transpose (counting sort by column; rows ascending within a column)
@@ -545,6 +554,8 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
             for (int64_t k = 0; k < nnz; ++k) cv[k] = codes[csrc[k]];
             if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb)) return e;
         }
+        S->fwd.map.variant = S->sched.variant - 1;
+        S->back.map.variant = S->sched.variant - 1;
         HIP_TRY(S->fpart.alloc(sizeof(float) * I * tf.ns));
         HIP_TRY(S->bpart.alloc(sizeof(float) * J * tb.ns));
     } else {
@@ -619,7 +630,7 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
     if (S->wfull) HIP_TRY(upload(S->wbuf, wf));
 
     // sensitivity s = A^T 1 with the stored (possibly quantised) values
-    std::vector<float> ones(static_cast<size_t>(I), 1.0f);
+    std::vector<float> ones(static_cast<size_t>(I + kVecPad), 1.0f);
     DBuf d_ones;
     HIP_TRY(upload(d_ones, ones));
     HIP_TRY(S->sens.alloc(sizeof(float) * J));
@@ -814,12 +825,13 @@ int sgtv_set_data(sgtv_ctx ctx, const float *y, const float *r, double beta, dou
             if (!finite_nonneg(hy[i])) return fail(SGTV_EINVAL, "y has a negative or non-finite value at " + std::to_string(i));
             if (!(std::isfinite(hr[i]) && hr[i] > 0.0f)) return fail(SGTV_EINVAL, "r must be finite and > 0 (index " + std::to_string(i) + ")");
         }
-        std::vector<float> py(static_cast<size_t>(S.I)), pr(static_cast<size_t>(S.I));
+        // vectors gathered by the tiled products carry kVecPad spare floats
+        std::vector<float> py(static_cast<size_t>(S.I + kVecPad), 0.0f), pr(static_cast<size_t>(S.I), 0.0f);
         for (int64_t i = 0; i < S.I; ++i) { py[i] = hy[S.perm[i]]; pr[i] = hr[S.perm[i]]; }
         DBuf dy, dr, dratio;
         HIP_TRY(upload(dy, py));
         HIP_TRY(upload(dr, pr));
-        HIP_TRY(dratio.alloc(sizeof(float) * S.I));
+        HIP_TRY(dratio.alloc(sizeof(float) * (S.I + kVecPad)));
         ctx->y = std::move(dy);
         ctx->r = std::move(dr);
         ctx->ratio = std::move(dratio);
@@ -1043,6 +1055,7 @@ int sgtv_set_schedule(sgtv_ctx ctx, const sgtv_schedule *s) {
     if (!ctx || !s) return fail(SGTV_EINVAL, "null argument");
     if (s->format != SGTV_FORMAT_TILED && s->format != SGTV_FORMAT_SELL) return fail(SGTV_EINVAL, "unknown format");
     if (s->waves < 0 || s->waves > 16) return fail(SGTV_EINVAL, "waves must be in [1, 16] (0: automatic)");
+    if (s->variant < 0 || s->variant > 3) return fail(SGTV_EINVAL, "variant must be in [1, 3] (0: automatic)");
     const int32_t rws[2] = {s->fwd_rows_per_wave, s->back_rows_per_wave};
     const int32_t cbs[2] = {s->fwd_block_cols, s->back_block_cols};
     const int32_t nss[2] = {s->fwd_slabs, s->back_slabs};

@@ -49,7 +49,9 @@ struct TileMap {
     const int32_t *goff;    // group offset of every list, n_lists + 1 entries
     int64_t n_rows, n_cols;
     int64_t n_rb;           // row blocks
+    int64_t pad;            // entry offset of one all-padding batch (256 entries)
     int rw, waves, cb, ns, cbs_max;
+    int variant;            // kernel variant (0 simple, 1 pipelined, 2 + block prefetch)
     int slab_begin[kMaxSlabs + 1];   // first column block of each slab
     size_t lds_bytes() const {
         size_t a = static_cast<size_t>(waves) * (rw + 1) * 4;

@@ -19,8 +19,31 @@ namespace sgtv {
 // without the register prefetch).
 constexpr int kXPrefetch = 4;
 
+// Products of one batch (4 groups of 64 entries, 4 entries per lane) into
+// the wave's LDS accumulators; rows within a group are distinct.
 template <int VT>
-__global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restrict__ x,
+__device__ __forceinline__ void tile_batch(const v4i p, const typename Code<VT>::V4 a,
+                                           const float *xs, float *my) {
+    float t;
+    t = xs[p.x & 0xFFFF]; my[p.x >> 16] = fmaf(Code<VT>::dec(a.x), t, my[p.x >> 16]);
+    t = xs[p.y & 0xFFFF]; my[p.y >> 16] = fmaf(Code<VT>::dec(a.y), t, my[p.y >> 16]);
+    t = xs[p.z & 0xFFFF]; my[p.z >> 16] = fmaf(Code<VT>::dec(a.z), t, my[p.z >> 16]);
+    t = xs[p.w & 0xFFFF]; my[p.w >> 16] = fmaf(Code<VT>::dec(a.w), t, my[p.w >> 16]);
+}
+
+// MODE 0: one batch at a time, the next column block staged after the
+//         barrier.
+// MODE 1: two batches in flight per wave (the batch past the end of a list is
+//         the all-padding batch, so the loop is straight-line and the wait
+//         counts stay exact).
+// MODE 2: MODE 1, and the next column block is read into registers (kXPrefetch
+//         float4 per thread; needs cb <= 16 * threads) after the last batch
+//         of the current block has been issued.
+template <int VT, int MODE>
+__global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__restrict__ pk,
+                                                const typename Code<VT>::T *__restrict__ val,
+                                                const int32_t *__restrict__ goff,
+                                                const float *__restrict__ x,
                                                 float *__restrict__ part) {
     typedef typename Code<VT>::T T;
     typedef typename Code<VT>::V4 V4;
@@ -32,7 +55,9 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restri
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int w = tid / kWave, lane = tid & (kWave - 1);
+    // the wave index is uniform: scalar list offsets and uniform loop bounds
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = tid & (kWave - 1);
     const int slab = static_cast<int>(blockIdx.x % M.ns);
     const int64_t rb = blockIdx.x / M.ns;
     float *my = acc + w * rw1;
@@ -41,81 +66,62 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restri
 
     const int cb0 = M.slab_begin[slab];
     const int ncbs = M.slab_begin[slab + 1] - cb0;
-    const int32_t *__restrict__ pk = M.pk;
-    const T *__restrict__ val = static_cast<const T *>(M.val);
-    const bool reg_prefetch = M.cb <= kXPrefetch * 4 * nthr;
     const int64_t list0 = ((rb * M.ns + slab) * M.cbs_max) * M.waves + w;
+    const v4i *pad4 = reinterpret_cast<const v4i *>(pk + M.pad) + lane;
+    const V4 *padv4 = reinterpret_cast<const V4 *>(val + M.pad) + lane;
 
-    // stage column block 0
+    // the gathered vector is padded to a multiple of 4 floats plus 16, so a
+    // whole float4 that starts inside it stays inside the allocation
     if (ncbs > 0) {
         const int64_t col0 = static_cast<int64_t>(cb0) * M.cb;
         const int64_t rem = M.n_cols - col0;
         const int ncols = rem < M.cb ? static_cast<int>(rem) : M.cb;
-        for (int i = tid; i < ncols; i += nthr) xs[i] = x[col0 + i];
+        for (int i4 = tid * 4; i4 < ncols; i4 += nthr * 4)
+            *reinterpret_cast<v4f *>(xs + i4) = *reinterpret_cast<const v4f *>(x + col0 + i4);
     }
     __syncthreads();
 
-    // first batch of list 0
-    int64_t g0 = ncbs > 0 ? M.goff[list0] : 0;
-    int ng = ncbs > 0 ? M.goff[list0 + 1] - static_cast<int>(g0) : 0;
-    v4i pn = {0, 0, 0, 0};
-    V4 an = {};
-    if (ng >= 4) {
-        pn = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(pk + g0 * kWave) + lane);
-        an = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(val + g0 * kWave) + lane);
-    }
     for (int c = 0; c < ncbs; ++c) {
-        // next column block: issue its loads now, store them after the barrier
-        v4f xr[kXPrefetch];
-        const bool more = c + 1 < ncbs;
-        int64_t ncol0 = 0;
-        int nncols = 0;
-        if (more) {
-            ncol0 = static_cast<int64_t>(cb0 + c + 1) * M.cb;
-            const int64_t rem = M.n_cols - ncol0;
-            nncols = rem < M.cb ? static_cast<int>(rem) : M.cb;
-            if (reg_prefetch) {
-#pragma unroll
-                for (int k = 0; k < kXPrefetch; ++k) {
-                    const int i4 = (k * nthr + tid) * 4;
-                    if (i4 + 3 < nncols) xr[k] = *reinterpret_cast<const v4f *>(x + ncol0 + i4);
-                    else {
-                        v4f t = {0.f, 0.f, 0.f, 0.f};
-                        if (i4 < nncols) t.x = x[ncol0 + i4];
-                        if (i4 + 1 < nncols) t.y = x[ncol0 + i4 + 1];
-                        if (i4 + 2 < nncols) t.z = x[ncol0 + i4 + 2];
-                        xr[k] = t;
-                    }
-                }
-            }
-        }
-        // geometry of the next list (for the prefetch across the block boundary)
-        const int64_t ng0 = more ? M.goff[list0 + (c + 1) * M.waves] : 0;
-        const int nng = more ? M.goff[list0 + (c + 1) * M.waves + 1] - static_cast<int>(ng0) : 0;
-
+        const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
+        const int g0 = goff[L];
+        const int ng = goff[L + 1] - g0;
         const int nb4 = ng >> 2;
-        const int64_t base = g0 * kWave;
+        const int64_t base = static_cast<int64_t>(g0) * kWave;
         const v4i *p4 = reinterpret_cast<const v4i *>(pk + base) + lane;
         const V4 *v4 = reinterpret_cast<const V4 *>(val + base) + lane;
-        for (int b = 0; b < nb4; ++b) {
-            const v4i p = pn;
-            const V4 a = an;
-            if (b + 1 < nb4) {
-                pn = __builtin_nontemporal_load(p4 + (b + 1) * kWave);
-                an = __builtin_nontemporal_load(v4 + (b + 1) * kWave);
-            } else if (nng >= 4) {
-                pn = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(pk + ng0 * kWave) + lane);
-                an = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(val + ng0 * kWave) + lane);
+
+        const int cn = c + 1 < ncbs ? c + 1 : c;
+        const int64_t ncol0 = static_cast<int64_t>(cb0 + cn) * M.cb;
+        const int64_t nrem = M.n_cols - ncol0;
+        const int nncols = nrem < M.cb ? static_cast<int>(nrem) : M.cb;
+        v4f xr[kXPrefetch];
+        if (MODE == 0) {
+            for (int b = 0; b < nb4; ++b) {
+                const v4i p = __builtin_nontemporal_load(p4 + b * kWave);
+                const V4 a = __builtin_nontemporal_load(v4 + b * kWave);
+                tile_batch<VT>(p, a, xs, my);
             }
-            float t;
-            t = xs[p.x & 0xFFFF]; my[p.x >> 16] = fmaf(Code<VT>::dec(a.x), t, my[p.x >> 16]);
-            t = xs[p.y & 0xFFFF]; my[p.y >> 16] = fmaf(Code<VT>::dec(a.y), t, my[p.y >> 16]);
-            t = xs[p.z & 0xFFFF]; my[p.z >> 16] = fmaf(Code<VT>::dec(a.z), t, my[p.z >> 16]);
-            t = xs[p.w & 0xFFFF]; my[p.w >> 16] = fmaf(Code<VT>::dec(a.w), t, my[p.w >> 16]);
+        } else {
+            v4i pA = __builtin_nontemporal_load(nb4 > 0 ? p4 : pad4);
+            V4 aA = __builtin_nontemporal_load(nb4 > 0 ? v4 : padv4);
+            for (int b = 0; b < nb4; b += 2) {
+                // a batch past the end of the list is the all-padding batch
+                // (row = rw, value 0): processing it changes nothing
+                const bool h1 = b + 1 < nb4, h2 = b + 2 < nb4;
+                const v4i pB = __builtin_nontemporal_load(h1 ? p4 + (b + 1) * kWave : pad4);
+                const V4 aB = __builtin_nontemporal_load(h1 ? v4 + (b + 1) * kWave : padv4);
+                tile_batch<VT>(pA, aA, xs, my);
+                pA = __builtin_nontemporal_load(h2 ? p4 + (b + 2) * kWave : pad4);
+                aA = __builtin_nontemporal_load(h2 ? v4 + (b + 2) * kWave : padv4);
+                tile_batch<VT>(pB, aB, xs, my);
+            }
         }
-        if (nb4 == 0 && nng >= 4) {
-            pn = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(pk + ng0 * kWave) + lane);
-            an = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(val + ng0 * kWave) + lane);
+        if (MODE == 2) {
+#pragma unroll
+            for (int k = 0; k < kXPrefetch; ++k) {
+                const int i4 = (k * nthr + tid) * 4;
+                xr[k] = *reinterpret_cast<const v4f *>(x + ncol0 + (i4 < nncols ? i4 : 0));
+            }
         }
         const int64_t tail = base + static_cast<int64_t>(nb4) * 4 * kWave + lane;
         for (int g = nb4 * 4; g < ng; ++g) {
@@ -125,23 +131,17 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const float *__restri
             const float t = xs[p & 0xFFFF];
             my[p >> 16] = fmaf(Code<VT>::dec(a), t, my[p >> 16]);
         }
-        g0 = ng0;
-        ng = nng;
-        if (more) {
+        if (c + 1 < ncbs) {
             __syncthreads();   // every wave is done with this block
-            if (reg_prefetch) {
+            if (MODE == 2) {
 #pragma unroll
                 for (int k = 0; k < kXPrefetch; ++k) {
                     const int i4 = (k * nthr + tid) * 4;
-                    if (i4 + 3 < nncols) *reinterpret_cast<v4f *>(xs + i4) = xr[k];
-                    else {
-                        if (i4 < nncols) xs[i4] = xr[k].x;
-                        if (i4 + 1 < nncols) xs[i4 + 1] = xr[k].y;
-                        if (i4 + 2 < nncols) xs[i4 + 2] = xr[k].z;
-                    }
+                    if (i4 < nncols) *reinterpret_cast<v4f *>(xs + i4) = xr[k];
                 }
             } else {
-                for (int i = tid; i < nncols; i += nthr) xs[i] = x[ncol0 + i];
+                for (int i4 = tid * 4; i4 < nncols; i4 += nthr * 4)
+                    *reinterpret_cast<v4f *>(xs + i4) = *reinterpret_cast<const v4f *>(x + ncol0 + i4);
             }
             __syncthreads();
         }
@@ -218,29 +218,32 @@ static unsigned stride_blocks(int64_t n) {
     return static_cast<unsigned>(b);
 }
 
-hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st) {
-    const int64_t tiles = M.n_rb * M.ns;
-    if (tiles == 0) return hipSuccess;
+template <int VT, int MODE>
+static hipError_t launch_tiled_t(const TileMap &M, const float *x, float *part, hipStream_t st) {
     const size_t lds = M.lds_bytes();
-    const dim3 grid(static_cast<unsigned>(tiles)), block(static_cast<unsigned>(M.waves * kWave));
-    hipError_t e;
-    if (vt == 0) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<0>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tiled<0>, grid, block, lds, st, M, x, part);
-    } else if (vt == 1) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<1>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tiled<1>, grid, block, lds, st, M, x, part);
-    } else {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<2>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tiled<2>, grid, block, lds, st, M, x, part);
-    }
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<VT, MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tiled<VT, MODE>), dim3(static_cast<unsigned>(M.n_rb * M.ns)),
+                       dim3(static_cast<unsigned>(M.waves * kWave)), lds, st, M, M.pk,
+                       static_cast<const typename Code<VT>::T *>(M.val), M.goff, x, part);
     return hipGetLastError();
+}
+
+template <int VT>
+static hipError_t launch_tiled_v(const TileMap &M, const float *x, float *part, hipStream_t st) {
+    const bool fits = M.cb <= kXPrefetch * 4 * M.waves * kWave;
+    if (M.variant == 1) return launch_tiled_t<VT, 1>(M, x, part, st);
+    if (M.variant == 2 && fits) return launch_tiled_t<VT, 2>(M, x, part, st);
+    return launch_tiled_t<VT, 0>(M, x, part, st);
+}
+
+hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st) {
+    if (M.n_rb * M.ns == 0) return hipSuccess;
+    if (vt == 0) return launch_tiled_v<0>(M, x, part, st);
+    if (vt == 1) return launch_tiled_v<1>(M, x, part, st);
+    return launch_tiled_v<2>(M, x, part, st);
 }
 
 hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,

@@ -42,7 +42,8 @@ class Schedule(ctypes.Structure):
     _fields_ = [("format", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("fwd_rows_per_wave", ctypes.c_int32), ("fwd_block_cols", ctypes.c_int32),
                 ("fwd_slabs", ctypes.c_int32), ("back_rows_per_wave", ctypes.c_int32),
-                ("back_block_cols", ctypes.c_int32), ("back_slabs", ctypes.c_int32)]
+                ("back_block_cols", ctypes.c_int32), ("back_slabs", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

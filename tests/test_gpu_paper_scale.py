@@ -1,0 +1,79 @@
+"""Paper-scale scan (128 x 128 x 128, 1,048,576 measurements, 134M nonzeros):
+FP32 parity after 200 iterations and the error of the 16-bit-value paths
+against the FP64 oracle on the exact FP32 matrix at iterations 50 and 200.
+
+The FP64 oracle runs 200 iterations of the full problem once (about a minute
+of host time); every GPU path is compared with that same run.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_08201_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def paper():
+    prob = datagen.make_problem("paper", 1)
+    print("paper-scale problem generated", flush=True)
+    f50, d50, c50, _ = oracle.admm(prob, 50, report=False)
+    print("oracle: 50 iterations done", flush=True)
+    f200, _, _, _ = oracle.admm(prob, 150, f0=f50, d0=d50, c0=c50, report=False)
+    print("oracle: 200 iterations done", flush=True)
+    obj = {50: oracle.objective(prob, f50)[0], 200: oracle.objective(prob, f200)[0]}
+    return prob, {50: f50, 200: f200}, obj
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1601_08201_amd import sgtv
+    sgtv.lib()
+    return sgtv
+
+
+def gpu_images(sg, prob, storage):
+    R = sg.Reconstructor()
+    R.set_problem(prob, storage=storage)
+    R.iterate(50)
+    f50 = R.image()
+    R.iterate(150)
+    f200 = R.image()
+    rep = R.objective()
+    R.close()
+    return {50: f50, 200: f200}, rep
+
+
+def test_fp32_matches_oracle_after_200_iterations(sg, paper):
+    prob, f_or, obj = paper
+    f_g, rep = gpu_images(sg, prob, "f32")
+    for k in (50, 200):
+        err = rel_l2(f_g[k], f_or[k])
+        print("fp32 iteration %d: image rel L2 %.3e" % (k, err), flush=True)
+        assert err <= 1e-5
+    assert rep["total"] == pytest.approx(obj[200], rel=1e-6)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_reduced_precision_error_against_fp64(sg, paper, storage):
+    prob, f_or, obj = paper
+    f_g, rep = gpu_images(sg, prob, storage)
+    out = {"storage": storage}
+    for k in (50, 200):
+        phi = oracle.objective(prob, f_g[k])[0]       # FP64 objective on the exact matrix
+        out[k] = dict(image_rel_l2=rel_l2(f_g[k], f_or[k]),
+                      rel_objective=abs(phi - obj[k]) / abs(obj[k]))
+    print("reduced precision vs FP64 oracle (exact FP32 matrix): " + json.dumps(out), flush=True)
+    assert np.all(np.isfinite(f_g[200])) and np.all(f_g[200] >= 0)
+    assert out[200]["rel_objective"] <= 1e-4

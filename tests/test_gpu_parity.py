@@ -270,3 +270,31 @@ def test_paper_scale_first_iterations_and_properties(sg):
     assert np.all(np.isfinite(f)) and np.all(f >= 0)
     assert rep["total"] < first
     assert rep["iter"] == 200
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_reduced_precision_matches_oracle_on_quantised_matrix(sg, storage, fmt):
+    """16-bit values with per-column scales: the GPU multiplies with
+    sigma_j * decode(code); the oracle given that same dequantised matrix must
+    agree to the FP32 tolerance."""
+    import copy
+    prob = datagen.make_problem("small", 12)
+    scale, codes, deq = oracle.quantise(prob.col, prob.val, prob.J, storage)
+    q = copy.copy(prob)
+    q.val = deq
+    R = run_gpu(sg, prob, 50, storage=storage, schedule=dict(format=fmt))
+    f_g = R.image()
+    rep = R.objective()
+    f_o, _, _, _ = oracle.admm(q, 50, report=False)
+    err = rel_l2(f_g, f_o)
+    print("storage", storage, "format", fmt, "rel_l2 vs oracle on quantised matrix", err, flush=True)
+    assert err <= IMG_TOL
+    # objective reported by the GPU is that of the quantised system
+    assert rep["total"] == pytest.approx(oracle.objective(q, f_o)[0], rel=1e-6)
+    # and against the exact matrix the image stays close
+    f_x, _, _, _ = oracle.admm(prob, 50, report=False)
+    phi_g = oracle.objective(prob, f_g)[0]
+    phi_x = oracle.objective(prob, f_x)[0]
+    print("storage", storage, "rel objective vs exact-matrix oracle", abs(phi_g - phi_x) / phi_x, flush=True)
+    assert abs(phi_g - phi_x) / phi_x <= 1e-3
