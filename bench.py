@@ -51,6 +51,29 @@ def algorithmic_bytes(prob, value_bytes, fmt):
     return out
 
 
+def measured_traffic(kernel, storage, fmt, config):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when there is none for this workload or the kernel sources changed since."""
+    import hashlib
+    import re
+    if storage != "f32" or fmt != "tiled" or config != "paper" or kernel not in ("forward", "back"):
+        return None
+    path = os.path.join(ROOT, "profiles", "tiled_product_fp32_paper_scan.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256()
+    for f in ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1601_08201_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"].get(kernel)
+
+
 def cpu_baseline(prob, iters):
     import numpy as np
     import oracle
@@ -183,7 +206,9 @@ def main():
         "iteration_alg_GBs": iter_bytes * 1e3 / ms_per_step / 1e9,
         "kernels": kern,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, args.storage, args.format, args.config),
+                     "traffic_unit": "bytes per launch"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

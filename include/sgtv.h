@@ -131,6 +131,13 @@ int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind);
 /* Run n_iters >= 0 ADMM iterations (Eqs. 4-6) asynchronously on the stream. */
 int sgtv_iterate(sgtv_ctx ctx, int n_iters);
 
+/* Graph replay of sgtv_iterate (default on): the launch sequence of n
+ * iterations is captured once into a HIP graph per (n, buffer parity) and
+ * replayed on the context stream; captured graphs are dropped by every call
+ * that changes the system, data, parameters or state.  enable = 0 launches
+ * the kernels one by one. */
+int sgtv_set_graphs(sgtv_ctx ctx, int enable);
+
 /* Objective and residuals of the current state (FP64 reductions); synchronises. */
 int sgtv_objective(sgtv_ctx ctx, sgtv_report *out);
 

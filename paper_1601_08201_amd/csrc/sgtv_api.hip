@@ -322,6 +322,9 @@ struct System {
 
 }  // namespace
 
+struct sgtv_ctx_s;
+typedef sgtv_ctx_s Context;
+
 struct sgtv_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -340,6 +343,11 @@ struct sgtv_ctx_s {
     // reductions
     DBuf part, red;
     int64_t part_cap = 0;
+    // graph replay of iterate(n)
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;   // capture stream (own, created on first use)
+    struct Graph { int n, fcur, vcur, fcur_after, vcur_after; hipGraphExec_t exec; };
+    std::vector<Graph> graphs;
     // optional kernel timing: (class, start, end) per launch
     bool profiling = false;
     struct Timed { int cls; hipEvent_t beg, end; };
@@ -347,6 +355,11 @@ struct sgtv_ctx_s {
 };
 
 namespace {
+
+void drop_graphs(sgtv_ctx_s *c) {
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
 
 int64_t n_groups(const sgtv_ctx_s *c) {
     return c->grouping == SGTV_GROUP_SPECTRAL ? c->sys->S : c->sys->J;
@@ -763,6 +776,8 @@ void sgtv_destroy(sgtv_ctx ctx) {
         (void)hipEventDestroy(t.beg);
         (void)hipEventDestroy(t.end);
     }
+    drop_graphs(ctx);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
 
@@ -790,6 +805,7 @@ int sgtv_set_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q,
                                  w_len, mem_kind))
             return e;
         // commit
+        drop_graphs(ctx);
         ctx->sys = std::move(S);
         ctx->has_data = false;
         ctx->y.release(); ctx->r.release(); ctx->ratio.release();
@@ -832,6 +848,7 @@ int sgtv_set_data(sgtv_ctx ctx, const float *y, const float *r, double beta, dou
         HIP_TRY(upload(dy, py));
         HIP_TRY(upload(dr, pr));
         HIP_TRY(dratio.alloc(sizeof(float) * (S.I + kVecPad)));
+        drop_graphs(ctx);
         ctx->y = std::move(dy);
         ctx->r = std::move(dr);
         ctx->ratio = std::move(dratio);
@@ -864,6 +881,7 @@ int sgtv_set_grouping(sgtv_ctx ctx, int grouping) {
         return SGTV_OK;
     }
     DeviceGuard g(ctx->device);
+    drop_graphs(ctx);
     const int old = ctx->grouping;
     ctx->grouping = grouping;
     if (ctx->sys && ctx->has_data) {
@@ -889,6 +907,7 @@ int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind) {
     DeviceGuard g(ctx->device);
     try {
         const System &S = *ctx->sys;
+        drop_graphs(ctx);
         if (x0) {
             DBuf staged;
             if (int e = stage_floats(staged, x0, S.J, mem_kind, ctx->stream, finite_nonneg, "x0"))
@@ -912,8 +931,61 @@ int sgtv_iterate(sgtv_ctx ctx, int n_iters) {
     if (int e = check_ready(ctx)) return e;
     if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
     DeviceGuard g(ctx->device);
-    for (int it = 0; it < n_iters; ++it)
-        if (int e = step(ctx)) return e;
+    if (!ctx->use_graphs || ctx->profiling || n_iters < 2) {
+        for (int it = 0; it < n_iters; ++it)
+            if (int e = step(ctx)) return e;
+        return SGTV_OK;
+    }
+    for (auto &gr : ctx->graphs)
+        if (gr.n == n_iters && gr.fcur == ctx->fcur && gr.vcur == ctx->vcur) {
+            HIP_TRY(hipGraphLaunch(gr.exec, ctx->stream));
+            ctx->fcur = gr.fcur_after;
+            ctx->vcur = gr.vcur_after;
+            ctx->k += n_iters;
+            return SGTV_OK;
+        }
+    // capture the launch sequence on the context's own stream
+    if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    const int f0 = ctx->fcur, v0 = ctx->vcur;
+    const int64_t k0 = ctx->k;
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->cap;
+    hipError_t e = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed);
+    int status = e == hipSuccess ? SGTV_OK : hip_fail(e, "hipStreamBeginCapture");
+    for (int it = 0; it < n_iters && status == SGTV_OK && e == hipSuccess; ++it) status = step(ctx);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) {
+        hipError_t e2 = hipStreamEndCapture(ctx->cap, &graph);
+        if (status == SGTV_OK && e2 != hipSuccess) status = hip_fail(e2, "hipStreamEndCapture");
+    }
+    ctx->stream = user;
+    Context::Graph gr{n_iters, f0, v0, ctx->fcur, ctx->vcur, nullptr};
+    ctx->fcur = f0;
+    ctx->vcur = v0;
+    ctx->k = k0;
+    if (status == SGTV_OK) {
+        hipError_t e3 = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) status = hip_fail(e3, "hipGraphInstantiate");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (status != SGTV_OK) return status;
+    if (ctx->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(gr);
+    HIP_TRY(hipGraphLaunch(gr.exec, ctx->stream));
+    ctx->fcur = gr.fcur_after;
+    ctx->vcur = gr.vcur_after;
+    ctx->k += n_iters;
+    return SGTV_OK;
+}
+
+int sgtv_set_graphs(sgtv_ctx ctx, int enable) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    DeviceGuard g(ctx->device);
+    drop_graphs(ctx);
+    ctx->use_graphs = enable != 0;
     return SGTV_OK;
 }
 
@@ -1019,6 +1091,7 @@ int sgtv_set_state(sgtv_ctx ctx, const float *f, const float *v, const float *a,
         if (int e = stage_floats(sf, f, S.J, mem_kind, ctx->stream, finite_nonneg, "f")) return e;
         if (int e = stage_floats(sv, v, S.J * 4, mem_kind, ctx->stream, finite_any, "v")) return e;
         if (int e = stage_floats(sa, a, n_groups(ctx), mem_kind, ctx->stream, unit_interval, "a")) return e;
+        drop_graphs(ctx);
         ctx->fcur = 0;
         ctx->vcur = 0;
         HIP_TRY(hipMemcpyAsync(ctx->f[0].p, sf.p, sizeof(float) * S.J, hipMemcpyDeviceToDevice, ctx->stream));

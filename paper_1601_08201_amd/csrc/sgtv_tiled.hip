@@ -218,13 +218,21 @@ static unsigned stride_blocks(int64_t n) {
     return static_cast<unsigned>(b);
 }
 
+// Largest dynamic LDS of one workgroup on gfx950.
+constexpr int kMaxLds = 163840;
+
 template <int VT, int MODE>
 static hipError_t launch_tiled_t(const TileMap &M, const float *x, float *part, hipStream_t st) {
     const size_t lds = M.lds_bytes();
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<VT, MODE>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
-    if (e != hipSuccess) return e;
+    // raise the kernel's dynamic-LDS limit once (outside any graph capture
+    // that may follow: the first launch of a context is never captured)
+    static bool raised = false;
+    if (!raised) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<VT, MODE>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+        if (e != hipSuccess) return e;
+        raised = true;
+    }
     hipLaunchKernelGGL((k_tiled<VT, MODE>), dim3(static_cast<unsigned>(M.n_rb * M.ns)),
                        dim3(static_cast<unsigned>(M.waves * kWave)), lds, st, M, M.pk,
                        static_cast<const typename Code<VT>::T *>(M.val), M.goff, x, part);

@@ -84,6 +84,7 @@ def lib():
             "sgtv_set_state": (_I, [_P, _P, _P, _P, _I64, _I]),
             "sgtv_backprojection": (_I, [_P, _P, _I]),
             "sgtv_set_profiling": (_I, [_P, _I]),
+            "sgtv_set_graphs": (_I, [_P, _I]),
             "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_get_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_kernel_times": (_I, [_P, _P, _P]),
@@ -249,6 +250,10 @@ def sgtv_get_schedule(ctx):
     return sch.as_dict()
 
 
+def sgtv_set_graphs(ctx, enable):
+    _check(lib().sgtv_set_graphs(ctx, int(bool(enable))))
+
+
 def sgtv_set_profiling(ctx, enable):
     _check(lib().sgtv_set_profiling(ctx, int(bool(enable))))
 
@@ -337,6 +342,10 @@ class Reconstructor:
 
     def schedule(self):
         return sgtv_get_schedule(self._ctx)
+
+    def set_graphs(self, enable=True):
+        sgtv_set_graphs(self._ctx, enable)
+        return self
 
     def set_profiling(self, enable=True):
         sgtv_set_profiling(self._ctx, enable)
