@@ -212,6 +212,40 @@ int sgtv_get_schedule(sgtv_ctx ctx, sgtv_schedule *s);
 int sgtv_set_profiling(sgtv_ctx ctx, int enable);
 int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts);
 
+/*
+ * Batches: many independent scans iterated together.  Each ADMM iteration
+ * of the whole batch is five launches (forward products of every scan, the
+ * ratios, the backprojections, the image updates, the split and dual
+ * updates), each covering all scans; sgtv_batch_iterate captures the n
+ * iterations into one HIP graph and launches it once.  Scans use FP32
+ * values, unit weights, the spectral grouping and one surrogate sweep; each
+ * scan may have its own grid, matrix, data, beta, rho and schedule.  A scan
+ * of a batch gives bit-identical results to the same scan in its own context
+ * with the same schedule.
+ */
+typedef struct sgtv_batch_s *sgtv_batch;
+
+int sgtv_batch_create(sgtv_batch *out, int device, void *hip_stream);
+void sgtv_batch_destroy(sgtv_batch b);
+/* Add one scan (arguments as sgtv_set_system / sgtv_set_data; schedule NULL:
+ * automatic; schedules of one batch must agree on waves and variant).  The
+ * new scan starts from the uniform image; index receives its position.
+ * Several threads may add scans to one batch at the same time (the host-side
+ * packing of each matrix runs in the calling thread); the scan order is then
+ * the order in which the calls finish. */
+int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t Q,
+                        const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                        int64_t nnz, const float *y, const float *r, double beta, double rho,
+                        const sgtv_schedule *schedule, int mem_kind, int32_t *index);
+int sgtv_batch_size(sgtv_batch b, int32_t *n_scans);
+/* n_iters iterations of every scan in batched launches (graph replay). */
+int sgtv_batch_iterate(sgtv_batch b, int n_iters);
+/* The same iterations scan after scan, each with its own graph: the
+ * reference the batched launch is measured against. */
+int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters);
+int sgtv_batch_objective(sgtv_batch b, int32_t scan, sgtv_report *out);
+int sgtv_batch_get_image(sgtv_batch b, int32_t scan, float *x, int mem_kind);
+
 #ifdef __cplusplus
 }
 #endif

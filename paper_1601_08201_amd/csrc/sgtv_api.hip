@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1172,6 +1173,305 @@ int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts) {
     }
     ctx->timed.clear();
     return status;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct sgtv_batch_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;                    // add_scan may be called from several threads
+    std::vector<sgtv_ctx_s *> scans;
+    bool dirty = true;
+    // device tables
+    DBuf tiles_f, tiles_b, maps_f, maps_b, xs_f[2], xs_b, parts_f, parts_b, scandev;
+    DBuf rblocks, vblocks, sblocks;
+    int64_t n_tiles_f = 0, n_tiles_b = 0, n_rblocks = 0, n_vblocks = 0, n_sblocks = 0;
+    size_t lds_f = 0, lds_b = 0;
+    int waves = 16, variant = 1;
+    int fcur = 0, vcur = 0;
+    hipStream_t cap = nullptr;
+    std::vector<sgtv_ctx_s::Graph> graphs;
+    ~sgtv_batch_s() {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (auto *c : scans) {
+            drop_graphs(c);
+            if (c->cap) (void)hipStreamDestroy(c->cap);
+            delete c;
+        }
+    }
+};
+
+namespace {
+
+template <class T>
+hipError_t upload_vec(DBuf &d, const std::vector<T> &h) { return upload(d, h); }
+
+int batch_tables(sgtv_batch_s *b) {
+    const size_t n = b->scans.size();
+    // scans by decreasing nonzeros: large tiles first, small ones fill the tail
+    std::vector<size_t> order(n);
+    for (size_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return b->scans[x]->sys->nnz > b->scans[y]->sys->nnz;
+    });
+    std::vector<sgtv::BatchTile> tf, tb;
+    std::vector<sgtv::TileMap> mf(n), mb(n);
+    std::vector<const float *> xf0(n), xf1(n), xb(n);
+    std::vector<float *> pf(n), pb(n);
+    std::vector<sgtv::ScanDev> sd(n);
+    std::vector<sgtv::BatchBlock> rbl, vbl, sbl;
+    b->lds_f = b->lds_b = 0;
+    for (size_t i = 0; i < n; ++i) {
+        sgtv_ctx_s *c = b->scans[i];
+        const System &S = *c->sys;
+        mf[i] = S.fwd.map;
+        mb[i] = S.back.map;
+        xf0[i] = c->f[0].as<float>();
+        xf1[i] = c->f[1].as<float>();
+        xb[i] = c->ratio.as<float>();
+        pf[i] = S.fpart.as<float>();
+        pb[i] = S.bpart.as<float>();
+        b->lds_f = std::max(b->lds_f, S.fwd.map.lds_bytes());
+        b->lds_b = std::max(b->lds_b, S.back.map.lds_bytes());
+        sgtv::ScanDev &d = sd[i];
+        d.y = c->y.as<float>();
+        d.r = c->r.as<float>();
+        d.ratio = c->ratio.as<float>();
+        d.fpart = S.fpart.as<float>();
+        d.bpart = S.bpart.as<float>();
+        for (int k = 0; k < 2; ++k) {
+            d.f[k] = c->f[k].as<float>();
+            d.v[k] = c->v[k].as<float>();
+            d.a[k] = c->a[k].as<float>();
+        }
+        d.sens = S.sens.as<float>();
+        d.H = S.H.as<float>();
+        d.grid = S.grid;
+        d.I = S.I;
+        d.ns_f = S.fwd.map.ns;
+        d.ns_b = S.back.map.ns;
+        int sl = 0;
+        while ((1 << sl) < S.Q && sl < 6) ++sl;
+        d.seg_log2 = sl;
+        d.lam = static_cast<float>(c->rho);
+        d.thr = static_cast<float>(c->beta / c->rho);
+    }
+    for (size_t oi = 0; oi < n; ++oi) {
+        const int32_t i = static_cast<int32_t>(order[oi]);
+        const System &S = *b->scans[i]->sys;
+        // tiles of one scan start at a multiple of 8 so each slab keeps its XCDs
+        auto add_tiles = [&](std::vector<sgtv::BatchTile> &t, const sgtv::TileMap &M) {
+            const int64_t nt = M.n_rb * M.ns;
+            for (int64_t k = 0; k < nt; ++k) t.push_back({i, static_cast<int32_t>(k)});
+            while (t.size() % 8) t.push_back({i, -1});
+        };
+        add_tiles(tf, S.fwd.map);
+        add_tiles(tb, S.back.map);
+        for (int64_t st = 0; st < S.I; st += sgtv::kBlock) rbl.push_back({i, 0, st});
+        for (int64_t st = 0; st < S.J; st += sgtv::kBlock) vbl.push_back({i, 0, st});
+        const int64_t segs = sgtv::kBlock >> sd[i].seg_log2;
+        for (int64_t st = 0; st < S.S; st += segs) sbl.push_back({i, 0, st});
+    }
+    HIP_TRY(upload_vec(b->tiles_f, tf));
+    HIP_TRY(upload_vec(b->tiles_b, tb));
+    HIP_TRY(upload_vec(b->maps_f, mf));
+    HIP_TRY(upload_vec(b->maps_b, mb));
+    HIP_TRY(upload_vec(b->xs_f[0], xf0));
+    HIP_TRY(upload_vec(b->xs_f[1], xf1));
+    HIP_TRY(upload_vec(b->xs_b, xb));
+    HIP_TRY(upload_vec(b->parts_f, pf));
+    HIP_TRY(upload_vec(b->parts_b, pb));
+    HIP_TRY(upload_vec(b->scandev, sd));
+    HIP_TRY(upload_vec(b->rblocks, rbl));
+    HIP_TRY(upload_vec(b->vblocks, vbl));
+    HIP_TRY(upload_vec(b->sblocks, sbl));
+    b->n_tiles_f = static_cast<int64_t>(tf.size());
+    b->n_tiles_b = static_cast<int64_t>(tb.size());
+    b->n_rblocks = static_cast<int64_t>(rbl.size());
+    b->n_vblocks = static_cast<int64_t>(vbl.size());
+    b->n_sblocks = static_cast<int64_t>(sbl.size());
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+    b->dirty = false;
+    return SGTV_OK;
+}
+
+int batch_step(sgtv_batch_s *b) {
+    hipStream_t st = b->stream;
+    HIP_TRY(sgtv::launch_tiled_batch(b->tiles_f.as<sgtv::BatchTile>(), b->n_tiles_f,
+                                     b->maps_f.as<sgtv::TileMap>(), b->xs_f[b->fcur].as<const float *>(),
+                                     b->parts_f.as<float *>(), b->waves, b->lds_f, b->variant, st));
+    HIP_TRY(sgtv::launch_ratio_batch(b->rblocks.as<sgtv::BatchBlock>(), b->n_rblocks,
+                                     b->scandev.as<sgtv::ScanDev>(), st));
+    HIP_TRY(sgtv::launch_tiled_batch(b->tiles_b.as<sgtv::BatchTile>(), b->n_tiles_b,
+                                     b->maps_b.as<sgtv::TileMap>(), b->xs_b.as<const float *>(),
+                                     b->parts_b.as<float *>(), b->waves, b->lds_b, b->variant, st));
+    HIP_TRY(sgtv::launch_voxel_batch(b->vblocks.as<sgtv::BatchBlock>(), b->n_vblocks,
+                                     b->scandev.as<sgtv::ScanDev>(), b->fcur, b->vcur, st));
+    b->fcur ^= 1;
+    HIP_TRY(sgtv::launch_split_batch(b->sblocks.as<sgtv::BatchBlock>(), b->n_sblocks,
+                                     b->scandev.as<sgtv::ScanDev>(), b->fcur, b->vcur, st));
+    b->vcur ^= 1;
+    return SGTV_OK;
+}
+
+void batch_sync_scans(sgtv_batch_s *b, int n_iters) {
+    for (auto *c : b->scans) {
+        c->fcur = b->fcur;
+        c->vcur = b->vcur;
+        c->k += n_iters;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgtv_batch_create(sgtv_batch *out, int device, void *hip_stream) {
+    if (!out) return fail(SGTV_EINVAL, "out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(SGTV_EINVAL, "device index out of range");
+    try {
+        auto b = new sgtv_batch_s();
+        b->device = device;
+        b->stream = static_cast<hipStream_t>(hip_stream);
+        *out = b;
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+void sgtv_batch_destroy(sgtv_batch b) {
+    if (!b) return;
+    DeviceGuard g(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    else (void)hipDeviceSynchronize();
+    delete b;
+}
+
+int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t Q,
+                        const int64_t *row_ptr, const int32_t *col_idx, const float *val,
+                        int64_t nnz, const float *y, const float *r, double beta, double rho,
+                        const sgtv_schedule *schedule, int mem_kind, int32_t *index) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    {
+        std::lock_guard<std::mutex> lock(b->mu);
+        if (b->scans.size() >= (size_t(1) << 30)) return fail(SGTV_ESHAPE, "too many scans");
+        // keep the batch in lockstep: a new scan may only join before the first iteration
+        if (!b->scans.empty() && b->scans.front()->k != 0)
+            return fail(SGTV_ESTATE, "scans can only be added before the batch iterates");
+    }
+    sgtv_ctx c = nullptr;
+    if (int e = sgtv_create(&c, b->device, b->stream)) return e;
+    std::unique_ptr<sgtv_ctx_s> own(c);
+    sgtv_schedule sch{};
+    if (schedule) sch = *schedule;
+    sch.format = SGTV_FORMAT_TILED;
+    if (int e = sgtv_set_schedule(c, &sch)) return e;
+    if (int e = sgtv_set_system(c, I, ny, nx, Q, row_ptr, col_idx, val, nnz, SGTV_F32, nullptr, 0, mem_kind))
+        return e;
+    if (int e = sgtv_set_data(c, y, r, beta, rho, 1, mem_kind)) return e;
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (!b->scans.empty() && b->scans.front()->k != 0)
+        return fail(SGTV_ESTATE, "scans can only be added before the batch iterates");
+    const sgtv_schedule &got = c->sys->sched;
+    if (!b->scans.empty()) {
+        const sgtv_schedule &first = b->scans.front()->sys->sched;
+        if (got.waves != first.waves || got.variant != first.variant)
+            return fail(SGTV_EINVAL, "scans of one batch must share waves and variant");
+    } else {
+        b->waves = got.waves;
+        b->variant = got.variant - 1;
+    }
+    b->scans.push_back(own.release());
+    b->dirty = true;
+    if (index) *index = static_cast<int32_t>(b->scans.size() - 1);
+    return SGTV_OK;
+}
+
+int sgtv_batch_size(sgtv_batch b, int32_t *n_scans) {
+    if (!b || !n_scans) return fail(SGTV_EINVAL, "null argument");
+    *n_scans = static_cast<int32_t>(b->scans.size());
+    return SGTV_OK;
+}
+
+int sgtv_batch_iterate(sgtv_batch b, int n_iters) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    if (b->scans.empty() || n_iters == 0) return SGTV_OK;
+    DeviceGuard g(b->device);
+    if (b->dirty)
+        if (int e = batch_tables(b)) return e;
+    for (auto &gr : b->graphs)
+        if (gr.n == n_iters && gr.fcur == b->fcur && gr.vcur == b->vcur) {
+            HIP_TRY(hipGraphLaunch(gr.exec, b->stream));
+            b->fcur = gr.fcur_after;
+            b->vcur = gr.vcur_after;
+            batch_sync_scans(b, n_iters);
+            return SGTV_OK;
+        }
+    if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    const int f0 = b->fcur, v0 = b->vcur;
+    hipStream_t user = b->stream;
+    b->stream = b->cap;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+    int status = e == hipSuccess ? SGTV_OK : hip_fail(e, "hipStreamBeginCapture");
+    for (int it = 0; it < n_iters && status == SGTV_OK && e == hipSuccess; ++it) status = batch_step(b);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) {
+        hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+        if (status == SGTV_OK && e2 != hipSuccess) status = hip_fail(e2, "hipStreamEndCapture");
+    }
+    b->stream = user;
+    sgtv_ctx_s::Graph gr{n_iters, f0, v0, b->fcur, b->vcur, nullptr};
+    b->fcur = f0;
+    b->vcur = v0;
+    if (status == SGTV_OK) {
+        hipError_t e3 = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) status = hip_fail(e3, "hipGraphInstantiate");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (status != SGTV_OK) return status;
+    if (b->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(b->graphs.front().exec);
+        b->graphs.erase(b->graphs.begin());
+    }
+    b->graphs.push_back(gr);
+    HIP_TRY(hipGraphLaunch(gr.exec, b->stream));
+    b->fcur = gr.fcur_after;
+    b->vcur = gr.vcur_after;
+    batch_sync_scans(b, n_iters);
+    return SGTV_OK;
+}
+
+int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    for (auto *c : b->scans)
+        if (int e = sgtv_iterate(c, n_iters)) return e;
+    if (!b->scans.empty()) {
+        b->fcur = b->scans.front()->fcur;
+        b->vcur = b->scans.front()->vcur;
+    }
+    return SGTV_OK;
+}
+
+int sgtv_batch_objective(sgtv_batch b, int32_t scan, sgtv_report *out) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (scan < 0 || static_cast<size_t>(scan) >= b->scans.size()) return fail(SGTV_EINVAL, "scan index out of range");
+    return sgtv_objective(b->scans[scan], out);
+}
+
+int sgtv_batch_get_image(sgtv_batch b, int32_t scan, float *x, int mem_kind) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (scan < 0 || static_cast<size_t>(scan) >= b->scans.size()) return fail(SGTV_EINVAL, "scan index out of range");
+    return sgtv_get_image(b->scans[scan], x, mem_kind);
 }
 
 }  // extern "C"

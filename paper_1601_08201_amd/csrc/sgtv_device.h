@@ -82,10 +82,6 @@ __device__ __forceinline__ float voxel_root(float H, float B, float C) {
     return B <= 0.0f ? (disc - B) / (2.0f * H) : (2.0f * C) / (B + disc);
 }
 
-__device__ __forceinline__ float shrink_factor(float nrm, float thr) {
-    return nrm > thr ? 1.0f - thr / nrm : 0.0f;
-}
-
 // Image update of one hyper-voxel j = (s, q) (Section III, Eq. 4, optimisation
 // transfer): with e = (A^T ratio)_j,
 //   gamma = lam * (D^T t)_j, t = w.*G g - d + c = w.*G g + v - 2 a v   (z = d - c)
@@ -126,6 +122,55 @@ __device__ __forceinline__ float voxel_update_value(int64_t j, float e, const fl
     const float B = sens[j] + lam * dt - h * gs;
     const float C = gs * e;
     return voxel_root(h, B, C);
+}
+
+__device__ __forceinline__ float shrink_factor(float nrm, float thr) {
+    return nrm > thr ? 1.0f - thr / nrm : 0.0f;
+}
+
+// Split and dual update of spatial bin s by a segment of 2^seg_log2 lanes
+// (lane ls strides over q): v_new = w.*G f + c_old, c_old = v_old - a_old v_old,
+// then the shrink factor of the group (Eq. 5).  Every lane of the wave must
+// call this (the segment reduction shuffles), with active = false for bins
+// past the end.
+template <int GROUPING>
+__device__ __forceinline__ void split_bin(int64_t s, bool active, int ls, int seg_log2,
+                                          const float *__restrict__ f,
+                                          const float *__restrict__ v_old,
+                                          const float *__restrict__ a_old,
+                                          float *__restrict__ v_new, float *__restrict__ a_new,
+                                          const Grid &grid, const Weights &wts, float thr) {
+    const int G = 1 << seg_log2;
+    const int Q = grid.Q;
+    float ss = 0.0f;
+    if (active) {
+        const int iy = static_cast<int>(s / grid.nx), ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
+        int64_t nb[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) nb[p] = neighbour(grid, s, iy, ix, p);
+        const float ag = GROUPING == 0 ? a_old[s] : 0.0f;
+        for (int q = ls; q < Q; q += G) {
+            const float fs = f[s * Q + q];
+            const float aq = GROUPING == 0 ? ag : a_old[s * Q + q];
+            float sq = 0.0f;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const float fn = nb[p] >= 0 ? f[nb[p] * Q + q] : 0.0f;
+                const int64_t o = (s * 4 + p) * Q + q;
+                const float vo = v_old[o];
+                const float c_old = vo - aq * vo;
+                const float vn = fmaf(weight(wts, grid, s, p, q), fs - fn, c_old);
+                v_new[o] = vn;
+                sq = fmaf(vn, vn, sq);
+            }
+            if (GROUPING == 0) ss += sq;
+            else a_new[s * Q + q] = shrink_factor(sqrtf(sq), thr);
+        }
+    }
+    if (GROUPING == 0) {
+        ss = seg_sum(ss, G);
+        if (active && ls == 0) a_new[s] = shrink_factor(sqrtf(ss), thr);
+    }
 }
 
 }  // namespace sgtv

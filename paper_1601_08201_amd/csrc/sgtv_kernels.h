@@ -60,7 +60,42 @@ struct TileMap {
     }
 };
 
+// Batched launches: one work item per workgroup.
+struct BatchTile {
+    int32_t scan;     // index into the per-scan arrays
+    int32_t local;    // tile of that scan's map
+};
+
+// Per-scan vectors and parameters of the batched elementwise kernels; the
+// image and split state are double buffered, the launch passes the parity.
+struct ScanDev {
+    const float *y, *r;
+    float *ratio, *fpart, *bpart;
+    float *f[2], *v[2], *a[2];
+    const float *sens, *H;
+    Grid grid;
+    int64_t I;
+    int ns_f, ns_b, seg_log2;
+    float lam, thr;
+};
+
+// Block of a batched elementwise launch: scan and first element.
+struct BatchBlock {
+    int32_t scan;
+    int32_t pad_;
+    int64_t start;
+};
+
 // Launchers (all asynchronous on `st`).
+hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
+                              const float *const *xs, float *const *parts, int waves, size_t lds,
+                              int variant, hipStream_t st);
+hipError_t launch_ratio_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,
+                              hipStream_t st);
+hipError_t launch_voxel_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,
+                              int fcur, int vcur, hipStream_t st);
+hipError_t launch_split_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,
+                              int fcur, int vcur, hipStream_t st);
 hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st);
 hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,
                                 const float *r, float *ratio, double *partials, bool objective,

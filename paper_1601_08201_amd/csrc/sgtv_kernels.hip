@@ -132,39 +132,9 @@ __global__ __launch_bounds__(kBlock) void k_split_update(
     const float *__restrict__ f, const float *__restrict__ v_old, const float *__restrict__ a_old,
     float *__restrict__ v_new, float *__restrict__ a_new, Grid grid, Weights wts, float thr,
     int seg_log2) {
-    const int G = 1 << seg_log2;
     const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock >> seg_log2) + (threadIdx.x >> seg_log2);
-    const int ls = threadIdx.x & (G - 1);
-    const int Q = grid.Q;
-    float ss = 0.0f;
-    if (s < grid.S) {
-        const int iy = static_cast<int>(s / grid.nx), ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
-        int64_t nb[4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) nb[p] = neighbour(grid, s, iy, ix, p);
-        const float ag = GROUPING == 0 ? a_old[s] : 0.0f;
-        for (int q = ls; q < Q; q += G) {
-            const float fs = f[s * Q + q];
-            const float aq = GROUPING == 0 ? ag : a_old[s * Q + q];
-            float sq = 0.0f;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const float fn = nb[p] >= 0 ? f[nb[p] * Q + q] : 0.0f;
-                const int64_t o = (s * 4 + p) * Q + q;
-                const float vo = v_old[o];
-                const float c_old = vo - aq * vo;
-                const float vn = fmaf(weight(wts, grid, s, p, q), fs - fn, c_old);
-                v_new[o] = vn;
-                sq = fmaf(vn, vn, sq);
-            }
-            if (GROUPING == 0) ss += sq;
-            else a_new[s * Q + q] = shrink_factor(sqrtf(sq), thr);
-        }
-    }
-    if (GROUPING == 0) {
-        ss = seg_sum(ss, G);
-        if (s < grid.S && ls == 0) a_new[s] = shrink_factor(sqrtf(ss), thr);
-    }
+    const int ls = threadIdx.x & ((1 << seg_log2) - 1);
+    split_bin<GROUPING>(s, s < grid.S, ls, seg_log2, f, v_old, a_old, v_new, a_new, grid, wts, thr);
 }
 
 // ---------------------------------------------------------------- report

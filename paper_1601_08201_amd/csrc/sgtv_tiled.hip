@@ -40,11 +40,12 @@ __device__ __forceinline__ void tile_batch(const v4i p, const typename Code<VT>:
 //         float4 per thread; needs cb <= 16 * threads) after the last batch
 //         of the current block has been issued.
 template <int VT, int MODE>
-__global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__restrict__ pk,
-                                                const typename Code<VT>::T *__restrict__ val,
-                                                const int32_t *__restrict__ goff,
-                                                const float *__restrict__ x,
-                                                float *__restrict__ part) {
+__device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
+                                           const int32_t *__restrict__ pk,
+                                           const typename Code<VT>::T *__restrict__ val,
+                                           const int32_t *__restrict__ goff,
+                                           const float *__restrict__ x,
+                                           float *__restrict__ part) {
     typedef typename Code<VT>::T T;
     typedef typename Code<VT>::V4 V4;
     extern __shared__ float lds[];
@@ -58,8 +59,8 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__rest
     // the wave index is uniform: scalar list offsets and uniform loop bounds
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int lane = tid & (kWave - 1);
-    const int slab = static_cast<int>(blockIdx.x % M.ns);
-    const int64_t rb = blockIdx.x / M.ns;
+    const int slab = static_cast<int>(tile % M.ns);
+    const int64_t rb = tile / M.ns;
     float *my = acc + w * rw1;
 
     for (int i = tid; i < M.waves * rw1; i += nthr) acc[i] = 0.0f;
@@ -154,6 +155,29 @@ __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__rest
         const int64_t row = row0 + i;
         if (row < M.n_rows) out[row] = acc[(i / M.rw) * rw1 + (i % M.rw)];
     }
+}
+
+template <int VT, int MODE>
+__global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__restrict__ pk,
+                                                const typename Code<VT>::T *__restrict__ val,
+                                                const int32_t *__restrict__ goff,
+                                                const float *__restrict__ x,
+                                                float *__restrict__ part) {
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
+}
+
+// Many scans in one launch: workgroup b runs tile tiles[b].local of scan
+// tiles[b].scan with that scan's map and vectors.
+template <int VT, int MODE>
+__global__ __launch_bounds__(1024) void k_tiled_batch(const BatchTile *__restrict__ tiles,
+                                                      const TileMap *__restrict__ maps,
+                                                      const float *const *__restrict__ xs,
+                                                      float *const *__restrict__ parts) {
+    const BatchTile bt = tiles[blockIdx.x];
+    if (bt.local < 0) return;   // alignment filler: the whole workgroup leaves
+    const TileMap M = maps[bt.scan];
+    tiled_body<VT, MODE>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
+                         M.goff, xs[bt.scan], parts[bt.scan]);
 }
 
 // ratio_i = y_i / (sum_k part[k][i] + r_i), with optional FP64 partials of
@@ -252,6 +276,31 @@ hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, h
     if (vt == 0) return launch_tiled_v<0>(M, x, part, st);
     if (vt == 1) return launch_tiled_v<1>(M, x, part, st);
     return launch_tiled_v<2>(M, x, part, st);
+}
+
+template <int MODE>
+static hipError_t launch_tiled_batch_t(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
+                                       const float *const *xs, float *const *parts, int waves,
+                                       size_t lds, hipStream_t st) {
+    static bool raised = false;
+    if (!raised) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled_batch<0, MODE>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+        if (e != hipSuccess) return e;
+        raised = true;
+    }
+    hipLaunchKernelGGL((k_tiled_batch<0, MODE>), dim3(static_cast<unsigned>(n_tiles)),
+                       dim3(static_cast<unsigned>(waves * kWave)), lds, st, tiles, maps, xs, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
+                              const float *const *xs, float *const *parts, int waves, size_t lds,
+                              int variant, hipStream_t st) {
+    if (n_tiles == 0) return hipSuccess;
+    if (variant == 1)
+        return launch_tiled_batch_t<1>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
+    return launch_tiled_batch_t<0>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
 }
 
 hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,

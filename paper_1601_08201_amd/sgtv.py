@@ -85,6 +85,15 @@ def lib():
             "sgtv_backprojection": (_I, [_P, _P, _I]),
             "sgtv_set_profiling": (_I, [_P, _I]),
             "sgtv_set_graphs": (_I, [_P, _I]),
+            "sgtv_batch_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+            "sgtv_batch_destroy": (None, [_P]),
+            "sgtv_batch_add_scan": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _P, _D, _D,
+                                         ctypes.POINTER(Schedule), _I, ctypes.POINTER(_I32)]),
+            "sgtv_batch_size": (_I, [_P, ctypes.POINTER(_I32)]),
+            "sgtv_batch_iterate": (_I, [_P, _I]),
+            "sgtv_batch_iterate_sequential": (_I, [_P, _I]),
+            "sgtv_batch_objective": (_I, [_P, _I32, ctypes.POINTER(Report)]),
+            "sgtv_batch_get_image": (_I, [_P, _I32, _P, _I]),
             "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_get_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_kernel_times": (_I, [_P, _P, _P]),
@@ -353,3 +362,98 @@ class Reconstructor:
 
     def kernel_times(self):
         return sgtv_kernel_times(self._ctx)
+
+
+# ---- batches -----------------------------------------------------------------------------
+
+def sgtv_batch_create(device=0, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().sgtv_batch_create(ctypes.byref(h), int(device), stream))
+    return h
+
+
+def sgtv_batch_destroy(b):
+    lib().sgtv_batch_destroy(b)
+
+
+def sgtv_batch_add_scan(b, I, ny, nx, Q, row_ptr, col_idx, val, y, r, beta, rho, schedule=None):
+    a = _arg(row_ptr, np.int64)
+    c = _arg(col_idx, np.int32)
+    v = _arg(val, np.float32)
+    ya, ra = _arg(y, np.float32), _arg(r, np.float32)
+    mk = _kind(a, c, v, ya, ra)
+    sch = ctypes.byref(Schedule(**{k: int(x) for k, x in schedule.items()})) if schedule else None
+    idx = _I32()
+    _check(lib().sgtv_batch_add_scan(b, int(I), int(ny), int(nx), int(Q), a[0], c[0], v[0],
+                                     int(c[2].shape[0]), ya[0], ra[0], float(beta), float(rho), sch, mk,
+                                     ctypes.byref(idx)))
+    return idx.value
+
+
+def sgtv_batch_size(b):
+    n = _I32()
+    _check(lib().sgtv_batch_size(b, ctypes.byref(n)))
+    return n.value
+
+
+def sgtv_batch_iterate(b, n_iters):
+    _check(lib().sgtv_batch_iterate(b, int(n_iters)))
+
+
+def sgtv_batch_iterate_sequential(b, n_iters):
+    _check(lib().sgtv_batch_iterate_sequential(b, int(n_iters)))
+
+
+def sgtv_batch_objective(b, scan):
+    rep = Report()
+    _check(lib().sgtv_batch_objective(b, int(scan), ctypes.byref(rep)))
+    return rep.as_dict()
+
+
+def sgtv_batch_get_image(b, scan, n, out=None):
+    out = _out(n, out)
+    p, mk = _out_arg(out)
+    _check(lib().sgtv_batch_get_image(b, int(scan), p, mk))
+    return out
+
+
+class Batch:
+    """Owning handle around a batch of scans iterated together."""
+
+    def __init__(self, device=0, stream=None):
+        self._b = sgtv_batch_create(device, stream)
+        self._J = []
+
+    def close(self):
+        if self._b is not None:
+            sgtv_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_scan(self, prob, schedule=None):
+        i = sgtv_batch_add_scan(self._b, prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col,
+                                prob.val, prob.y, prob.r, prob.beta, prob.rho, schedule)
+        self._J.append(prob.ny * prob.nx * prob.Q)
+        return i
+
+    def __len__(self):
+        return sgtv_batch_size(self._b)
+
+    def iterate(self, n):
+        sgtv_batch_iterate(self._b, n)
+        return self
+
+    def iterate_sequential(self, n):
+        sgtv_batch_iterate_sequential(self._b, n)
+        return self
+
+    def objective(self, scan):
+        return sgtv_batch_objective(self._b, scan)
+
+    def image(self, scan, out=None):
+        return sgtv_batch_get_image(self._b, scan, self._J[scan], out)

@@ -1,0 +1,82 @@
+"""Batched scans: every scan of a batch reproduces its own single-scan run bit
+for bit (same schedule), matches the FP64 oracle, and the batched graph replays
+agree with scan-after-scan launches."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_08201_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1601_08201_amd import sgtv
+    sgtv.lib()
+    return sgtv
+
+
+def scans():
+    shapes = [(8, 8, 16, 0.1, 1.0), (12, 12, 24, 0.2, 1.0), (16, 16, 32, 0.1, 0.5),
+              (5, 7, 9, 0.05, 2.0), (16, 16, 32, 0.1, 1.0), (20, 10, 40, 0.3, 1.0)]
+    out = []
+    for k, (ny, nx, Q, beta, rho) in enumerate(shapes):
+        J = ny * nx * Q
+        p = datagen.make_problem(dict(ny=ny, nx=nx, Q=Q, I=max(J // 2, 64), nnz_per_col=8, rects=3,
+                                      beta=beta, rho=rho), seed=500 + k)
+        out.append(p)
+    return out
+
+
+SCHED = dict(fwd_rows_per_wave=64, back_rows_per_wave=128, fwd_block_cols=2048, back_block_cols=1024)
+
+
+def test_batch_matches_single_scans_and_oracle(sg):
+    probs = scans()
+    B = sg.Batch()
+    for p in probs:
+        B.add_scan(p, schedule=SCHED)
+    assert len(B) == len(probs)
+    B.iterate(20)
+    B.iterate(10)
+    for i, p in enumerate(probs):
+        R = sg.Reconstructor()
+        R.set_schedule(**SCHED)
+        R.set_problem(p)
+        R.iterate(30)
+        np.testing.assert_array_equal(B.image(i), R.image())
+        assert B.objective(i) == R.objective()
+        f_o, _, _, _ = oracle.admm(p, 30, report=False)
+        err = np.linalg.norm(B.image(i) - f_o) / np.linalg.norm(f_o)
+        print("scan", i, p.ny, p.nx, p.Q, "rel_l2", err, flush=True)
+        assert err <= 1e-5
+        R.close()
+
+
+def test_batched_graph_replays_equal_sequential(sg):
+    probs = scans()
+    A = sg.Batch()
+    S = sg.Batch()
+    for p in probs:
+        A.add_scan(p, schedule=SCHED)
+        S.add_scan(p, schedule=SCHED)
+    for rep in range(3):
+        A.iterate(6)
+        S.iterate_sequential(6)
+        for i in range(len(probs)):
+            assert A.objective(i) == S.objective(i)
+            np.testing.assert_array_equal(A.image(i), S.image(i))
+
+
+def test_add_scan_after_iterating_is_refused(sg):
+    probs = scans()
+    B = sg.Batch()
+    B.add_scan(probs[0])
+    B.iterate(2)
+    with pytest.raises(sg.SgtvError) as ei:
+        B.add_scan(probs[1])
+    assert ei.value.code == sg.SGTV_ESTATE
+    assert len(B) == 1
