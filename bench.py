@@ -95,6 +95,83 @@ def cpu_baseline(prob, iters):
     return iters / dt, dt
 
 
+def _gen_batch_scan(args):
+    from paper_1601_08201_amd import datagen
+    ny, nx, Q, seed = args
+    return datagen.make_batch_scan(ny, nx, Q, seed=seed)
+
+
+def batch_main(args):
+    """Batch of uneven scans: batched launches (one graph per call) against the
+    same scans iterated one after another."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import torch
+    from paper_1601_08201_amd import autotune, datagen, sgtv
+
+    torch.cuda.set_device(0)
+    shapes = datagen.batch_shapes(args.batch_scans, 300)
+    t0 = time.time()
+    with mp.get_context("fork").Pool(min(16, len(shapes))) as pool:
+        probs = pool.map(_gen_batch_scan, [(ny, nx, Q, 300 + k) for k, (ny, nx, Q) in enumerate(shapes)])
+    nnz = sum(p.nnz for p in probs)
+    unknowns = sum(p.J for p in probs)
+    log("generated %d scans: %d unknowns, %d nonzeros in %.1fs" % (len(probs), unknowns, nnz, time.time() - t0))
+    stream = torch.cuda.current_stream()
+    B = sgtv.Batch(stream=stream.cuda_stream)
+    t0 = time.time()
+    tuned = 0
+    scheds = []
+    for p in probs:
+        sch = autotune.cached_schedule(p)
+        tuned += sch is not None
+        scheds.append(sch)
+    with cf.ThreadPoolExecutor(8) as ex:
+        list(ex.map(lambda ps: B.add_scan(ps[0], ps[1]), zip(probs, scheds)))
+    log("batch built in %.1fs (%d scans with tuned schedules)" % (time.time() - t0, tuned))
+    B.iterate(args.warmup)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    a, b = ev(), ev()
+    a.record(stream)
+    B.iterate(args.steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_batched = a.elapsed_time(b)
+    B.iterate_sequential(args.warmup)
+    torch.cuda.synchronize()
+    a.record(stream)
+    B.iterate_sequential(args.steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = a.elapsed_time(b)
+    alg = sum(sum(algorithmic_bytes(p, 4, "tiled").values()) for p in probs)
+    scan_its = len(probs) * args.steps
+    out = {
+        "metric": "aggregate scan-iterations/s, batched launch vs sequential launches",
+        "value": scan_its / (ms_batched * 1e-3),
+        "unit": "scan-iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_batched / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded phantoms, random coded-mask system matrices, Poisson counts)",
+        "config": {"workload": "batch of %d scans, side in {32,48,64,96,128}, Q in {64,96,128}, "
+                               "I = J/2, 32 nnz/col; %d unknowns, %d nonzeros" % (len(probs), unknowns, nnz),
+                   "global_batch": len(probs), "parallelism": "single GPU"},
+        "sequential": {"value": scan_its / (ms_seq * 1e-3), "ms_per_step": ms_seq / args.steps},
+        "speedup_vs_sequential": ms_seq / ms_batched,
+        "batch_iteration_alg_GBs": alg * args.steps / (ms_batched * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "whole batched iteration",
+                     "achieved": alg * args.steps / (ms_batched * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg * args.steps / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +185,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="scan", choices=["scan", "batch"],
+                    help="scan: the paper-scale scan (default); batch: 64 uneven scans")
+    ap.add_argument("--batch-scans", type=int, default=64)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -123,6 +203,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        if args.steps == 200:
+            args.steps = 100
+        return batch_main(args)
 
     t0 = time.time()
     prob = datagen.make_problem(args.config, args.seed)
@@ -131,7 +215,13 @@ def main():
 
     stream = torch.cuda.current_stream()
     R = sgtv.Reconstructor(device=0, stream=stream.cuda_stream)
-    R.set_schedule(format=0 if args.format == "tiled" else 1)
+    from paper_1601_08201_amd import autotune
+    tuned = autotune.cached_schedule(prob) if args.format == "tiled" else None
+    if tuned:
+        R.set_schedule(format=0, **tuned)
+        log("tuned schedule from the autotuner cache: " + json.dumps(tuned))
+    else:
+        R.set_schedule(format=0 if args.format == "tiled" else 1)
     t0 = time.time()
     R.set_problem(prob, storage=args.storage)
     log("system and data set in %.1fs" % (time.time() - t0))

@@ -1,0 +1,163 @@
+"""Autotuner for the launch schedule of the tiled sparse products.
+
+For one system the tuner builds the tiled matrices under a list of candidate
+schedules (rows per wave, column-block width, number of slabs, inner-loop
+variant), times the forward and the back product with HIP events on the
+device, and keeps the fastest forward and the fastest back parameters
+independently (the two products share no data layout).  Results are cached
+per problem shape in a JSON file so a batch of scans tunes every distinct
+shape once.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import sgtv
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules.json")
+MAX_LDS = 163840
+
+
+def lds_bytes(waves, rw, cb):
+    a = waves * (rw + 1) * 4
+    a = (a + 15) // 16 * 16
+    return a + cb * 4
+
+
+def shape_key(I, ny, nx, Q, nnz):
+    return "I%d_g%dx%dx%d_nnz%d" % (I, ny, nx, Q, nnz)
+
+
+def candidates(I, J, waves=16, per_side=10):
+    """Ranked candidate (rows per wave, block columns, slabs) for the forward
+    product (rows = measurements) and the back product (rows = voxels)."""
+    import math
+
+    def side(n_rows, n_cols):
+        out = []
+        for rw in (64, 128, 256, 512, 1024):
+            for cb in (4096, 8192, 16384):
+                cb_eff = min(cb, max(4, 1 << (max(n_cols, 4) - 1).bit_length()))
+                if lds_bytes(waves, rw, cb_eff) > MAX_LDS:
+                    continue
+                n_cb = -(-n_cols // cb_eff)
+                for ns in (1, 2, 4, 8):
+                    if ns > n_cb:
+                        continue
+                    tiles = -(-n_rows // (waves * rw)) * ns
+                    slab = n_cols * 4 / ns
+                    entries = rw * cb_eff * 1.0   # list length scales with this (fixed density)
+                    # heuristic rank: ~256-512 workgroups, ~2 MiB slabs, long lists
+                    score = (abs(math.log2(max(tiles, 1) / 384.0)) + 0.5 * abs(math.log2(slab / 2 ** 21))
+                             - 0.25 * math.log2(entries / 2 ** 24))
+                    out.append((score, (rw, cb_eff, ns)))
+        out.sort()
+        seen, ranked = set(), []
+        for _, c in out:
+            if c not in seen:
+                seen.add(c)
+                ranked.append(c)
+        return ranked[:per_side]
+    return side(I, J), side(J, I)
+
+
+def _time_schedule(prob, sched, reps):
+    R = sgtv.Reconstructor()
+    R.set_schedule(format=0, **sched)
+    R.set_problem(prob)
+    R.set_graphs(False)
+    R.iterate(1)
+    R.set_profiling(True)
+    R.iterate(reps)
+    t = R.kernel_times()
+    R.close()
+    return t["forward"][0] / t["forward"][1] * 1e3, t["back"][0] / t["back"][1] * 1e3
+
+
+def tune(prob, reps=8, max_candidates=10, variants=(1,), log=None, cache_path=CACHE_PATH):
+    """Time candidate schedules on the device; return (schedule dict, report)."""
+    I, J = prob.I, prob.J
+    fw, bk = candidates(I, J, per_side=max_candidates)
+    # pair forward and back candidates so each build measures both products
+    n = max(len(fw), len(bk))
+    pairs = [(fw[k % len(fw)], bk[k % len(bk)]) for k in range(n)][:max_candidates]
+    best_f, best_b = None, None
+    report = []
+    t0 = time.time()
+    for (f, b) in pairs:
+        for v in variants:
+            sched = dict(waves=16, variant=v, fwd_rows_per_wave=f[0], fwd_block_cols=f[1], fwd_slabs=f[2],
+                         back_rows_per_wave=b[0], back_block_cols=b[1], back_slabs=b[2])
+            try:
+                tf, tb = _time_schedule(prob, sched, reps)
+            except sgtv.SgtvError as e:
+                report.append(dict(schedule=sched, error=str(e)))
+                continue
+            report.append(dict(schedule=sched, forward_us=tf, back_us=tb))
+            if log:
+                log("autotune %s: forward %.1f us, back %.1f us" % (json.dumps(sched), tf, tb))
+            if best_f is None or tf < best_f[0]:
+                best_f = (tf, f, v)
+            if best_b is None or tb < best_b[0]:
+                best_b = (tb, b, v)
+    if best_f is None:
+        return {}, report
+    # one variant per launch family: take the forward product's
+    best = dict(waves=16, variant=best_f[2],
+                fwd_rows_per_wave=best_f[1][0], fwd_block_cols=best_f[1][1], fwd_slabs=best_f[1][2],
+                back_rows_per_wave=best_b[1][0], back_block_cols=best_b[1][1], back_slabs=best_b[1][2])
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[shape_key(I, prob.ny, prob.nx, prob.Q, prob.nnz)] = dict(
+            schedule=best, forward_us=best_f[0], back_us=best_b[0], seconds=time.time() - t0,
+            candidates=len(report))
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return best, report
+
+
+def load_cache(path=CACHE_PATH):
+    if os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def cached_schedule(prob, path=CACHE_PATH):
+    """The tuned schedule for this problem's shape, or None (automatic)."""
+    rec = load_cache(path).get(shape_key(prob.I, prob.ny, prob.nx, prob.Q, prob.nnz))
+    return rec["schedule"] if rec else None
+
+
+def _main():
+    import argparse
+    import sys
+
+    from . import datagen
+    ap = argparse.ArgumentParser(description="tune the tiled-product schedules of standard workloads")
+    ap.add_argument("--workloads", default="paper,warmstart,batch")
+    ap.add_argument("--out", default=CACHE_PATH)
+    ap.add_argument("--candidates", type=int, default=8)
+    ap.add_argument("--batch-scans", type=int, default=64)
+    args = ap.parse_args()
+    log = lambda m: print("[autotune] " + m, file=sys.stderr, flush=True)
+    probs = []
+    for w in args.workloads.split(","):
+        if w in ("paper", "warmstart", "small"):
+            probs.append(datagen.make_problem(w, 1))
+        elif w == "batch":
+            seen = set()
+            for (ny, nx, Q) in datagen.batch_shapes(args.batch_scans, 300):
+                if (ny, nx, Q) not in seen:
+                    seen.add((ny, nx, Q))
+                    probs.append(datagen.make_batch_scan(ny, nx, Q, seed=900))
+    for p in probs:
+        t0 = time.time()
+        best, rep = tune(p, max_candidates=args.candidates, log=log, cache_path=args.out)
+        log("shape %dx%dx%d I=%d: best %s (%.1fs)" % (p.ny, p.nx, p.Q, p.I, json.dumps(best), time.time() - t0))
+
+
+if __name__ == "__main__":
+    _main()
