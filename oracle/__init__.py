@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _BUILD = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_BUILD, "liboracle.so")
-_SOURCES = ["sgtv_oracle.c"]
+_SOURCES = ["sgtv_oracle.c", "wsnet_oracle.c"]
 _lib = None
 
 NDIR = 4
@@ -73,6 +73,12 @@ def _declare(lib):
         "or_image_sweep_flat": (None, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _P, _P]),
         "or_plain_init_flat": (_D, [_I64, _I, _I, _I, _P, _P, _P, _P]),
         "or_quantise": (None, [_I64, _I64, _P, _P, _I, _P, _P, _P]),
+        "wn_conv_fwd": (None, [_I, _I, _I, _I, _I, _P, _P, _P, _P]),
+        "wn_conv_bwd_data": (None, [_I, _I, _I, _I, _I, _P, _P, _P]),
+        "wn_conv_bwd_weight": (None, [_I, _I, _I, _I, _I, _P, _P, _P, _P]),
+        "wn_forward": (None, [_I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
+        "wn_loss_grad": (_D, [_I, _I, _I, _I, _I, _P, _P, _P, _P]),
+        "wn_adam": (None, [_I64, _P, _P, _P, _P, _I64, _D, _D, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -257,3 +263,69 @@ def admm(prob, n_iter, f0=None, d0=None, c0=None, sweeps=None, beta=None, lam=No
     if st != 0:
         raise MemoryError("oracle allocation failed")
     return f, d, cc, (rep[:n_iter] if report else None)
+
+
+# ---- warm-start network (NHWC images, weights [co][ky][kx][ci]) ---------------------------
+
+def wn_n_params(C, L=6):
+    return L * (C * 9 * C + C)
+
+
+def wn_conv_fwd(x, w, b=None):
+    """x [B,H,W,Ci], w [Co,3,3,Ci], b [Co] -> z [B,H,W,Co] (zero padding 1)."""
+    lib = _load()
+    x, w = _f64(x), _f64(w)
+    B, H, W, Ci = x.shape
+    Co = w.shape[0]
+    z = np.empty((B, H, W, Co), np.float64)
+    bb = _f64(b) if b is not None else None
+    lib.wn_conv_fwd(B, H, W, Ci, Co, _ptr(x), _ptr(w), _ptr(bb), _ptr(z))
+    return z
+
+
+def wn_conv_bwd_data(dz, w, Ci):
+    lib = _load()
+    dz, w = _f64(dz), _f64(w)
+    B, H, W, Co = dz.shape
+    dx = np.empty((B, H, W, Ci), np.float64)
+    lib.wn_conv_bwd_data(B, H, W, Ci, Co, _ptr(dz), _ptr(w), _ptr(dx))
+    return dx
+
+
+def wn_conv_bwd_weight(x, dz):
+    lib = _load()
+    x, dz = _f64(x), _f64(dz)
+    B, H, W, Ci = x.shape
+    Co = dz.shape[3]
+    dw = np.empty((Co, 3, 3, Ci), np.float64)
+    db = np.empty(Co, np.float64)
+    lib.wn_conv_bwd_weight(B, H, W, Ci, Co, _ptr(x), _ptr(dz), _ptr(dw), _ptr(db))
+    return dw, db
+
+
+def wn_forward(params, x_in, L=6):
+    lib = _load()
+    x_in = _f64(x_in)
+    B, H, W, C = x_in.shape
+    p = _f64(params)
+    out = np.empty_like(x_in)
+    lib.wn_forward(L, B, H, W, C, _ptr(p), _ptr(x_in), _ptr(out), None, None)
+    return out
+
+
+def wn_loss_grad(params, x_in, target, L=6):
+    lib = _load()
+    x_in, t, p = _f64(x_in), _f64(target), _f64(params)
+    B, H, W, C = x_in.shape
+    g = np.empty_like(p)
+    loss = lib.wn_loss_grad(L, B, H, W, C, _ptr(p), _ptr(x_in), _ptr(t), _ptr(g))
+    return loss, g
+
+
+def wn_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays; t is the 1-based step."""
+    lib = _load()
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib.wn_adam(params.size, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr),
+                float(b1), float(b2), float(eps))

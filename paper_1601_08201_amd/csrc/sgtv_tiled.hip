@@ -175,7 +175,9 @@ __global__ __launch_bounds__(1024) void k_tiled_batch(const BatchTile *__restric
                                                       float *const *__restrict__ parts) {
     const BatchTile bt = tiles[blockIdx.x];
     if (bt.local < 0) return;   // alignment filler: the whole workgroup leaves
-    const TileMap M = maps[bt.scan];
+    // a reference, not a copy: fields (and the slab table indexed at run time)
+    // are read with scalar loads instead of living in scratch memory
+    const TileMap &M = maps[bt.scan];
     tiled_body<VT, MODE>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
                          M.goff, xs[bt.scan], parts[bt.scan]);
 }
