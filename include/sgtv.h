@@ -246,6 +246,43 @@ int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters);
 int sgtv_batch_objective(sgtv_batch b, int32_t scan, sgtv_report *out);
 int sgtv_batch_get_image(sgtv_batch b, int32_t scan, float *x, int mem_kind);
 
+/*
+ * Learned warm start: a convolutional network that maps the normalised
+ * backprojection of a scan (sgtv_backprojection, an image of height x width
+ * pixels with one channel per spectral bin, NHWC = the voxel order above) to
+ * a nonnegative start image for sgtv_set_init.  Architecture: `layers`
+ * 3x3 convolutions with zero padding 1, 64 channels in and out, weights
+ * [co][ky][kx][ci] and one bias per output channel; ReLU after every layer
+ * but the last, softplus after the last.  Training minimises the mean
+ * squared error against target images (reconstructions of the plain method)
+ * with Adam.  Convolutions run on bfloat16 matrix cores with FP32
+ * accumulation; master weights, gradients and Adam moments are FP32; the
+ * loss is reduced in FP64.  Parameters are flat FP32, layer by layer:
+ * weights (64*9*64) then bias (64).
+ * Limits: channels = 64, width = 64, height even, 1 <= layers <= 16,
+ * 1 <= batch <= max_batch.
+ */
+typedef struct wsnet_s *wsnet;
+
+int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32_t height,
+                 int32_t width, int32_t channels, int32_t max_batch);
+void wsnet_destroy(wsnet net);
+/* Number of parameters of a network with `layers` layers and `channels` channels. */
+int64_t wsnet_param_count(int32_t layers, int32_t channels);
+int wsnet_set_params(wsnet net, const float *params, int64_t n, int mem_kind);
+int wsnet_get_params(wsnet net, float *params, int64_t n, int mem_kind);
+/* x0 = network(x_in) for `batch` images (FP32 NHWC in and out). */
+int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int mem_kind);
+/* Loss and gradient of the mean squared error of network(x_in) against
+ * target; the gradient stays in the network for wsnet_adam_step and is
+ * copied to grad (n parameters) when grad is not NULL. */
+int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t batch,
+                   double *loss, float *grad, int mem_kind);
+/* One Adam step with the last gradient (Kingma and Ba); the step counter
+ * starts at 1 after set_params or reset. */
+int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps);
+int wsnet_reset_adam(wsnet net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@
 
 #include "sgtv.h"
 #include "sgtv_kernels.h"
+#include "sgtv_wsnet.h"
 
 namespace {
 
@@ -1472,6 +1473,235 @@ int sgtv_batch_get_image(sgtv_batch b, int32_t scan, float *x, int mem_kind) {
     if (!b) return fail(SGTV_EINVAL, "null batch");
     if (scan < 0 || static_cast<size_t>(scan) >= b->scans.size()) return fail(SGTV_EINVAL, "scan index out of range");
     return sgtv_get_image(b->scans[scan], x, mem_kind);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ warm-start network
+
+struct wsnet_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int L = 0, H = 0, W = 0, C = 0, max_batch = 0;
+    int64_t n_param = 0, per_layer = 0, img = 0;   // img = H * W * C
+    DBuf params, grad, m, v;                        // FP32
+    DBuf wf, wb;                                    // bf16 weights, L blocks of C*9*C
+    DBuf acts;                                      // bf16 inputs of every layer
+    DBuf z_last, out, xin, tgt;                     // FP32
+    DBuf dz[2];                                     // bf16 gradients w.r.t. pre-activations
+    DBuf wpart, lpart, lred;
+    int64_t step = 0;
+    bool have_grad = false, have_params = false;
+};
+
+namespace {
+
+constexpr int kWgradRows = 8;       // image rows per weight-gradient block
+constexpr int kLossBlocks = 1024;
+
+__bf16 *bf(const DBuf &b, int64_t off = 0) { return b.as<__bf16>() + off; }
+
+int net_weights(wsnet_s *n) {
+    for (int l = 0; l < n->L; ++l)
+        HIP_TRY(sgtv::wsn::weights_bf16(n->params.as<float>() + l * n->per_layer,
+                                        bf(n->wf, l * n->C * 9 * n->C), bf(n->wb, l * n->C * 9 * n->C),
+                                        n->stream));
+    return SGTV_OK;
+}
+
+int net_stage(wsnet_s *n, DBuf &dst, const float *src, int64_t count, int mk) {
+    HIP_TRY(hipMemcpyAsync(dst.p, src, sizeof(float) * count,
+                           mk == SGTV_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, n->stream));
+    return SGTV_OK;
+}
+
+int net_forward(wsnet_s *n, int B) {
+    const int64_t cnt = B * n->img;
+    HIP_TRY(sgtv::wsn::to_bf16(n->xin.as<float>(), bf(n->acts), cnt, n->stream));
+    const int64_t CK = static_cast<int64_t>(n->C) * 9 * n->C;
+    for (int l = 0; l < n->L; ++l) {
+        const float *bias = n->params.as<float>() + l * n->per_layer + CK;
+        const __bf16 *X = bf(n->acts, l * n->max_batch * n->img);
+        if (l + 1 < n->L)
+            HIP_TRY(sgtv::wsn::conv_relu(X, bf(n->wf, l * CK), bias, B, n->H, n->W,
+                                         bf(n->acts, (l + 1) * n->max_batch * n->img), n->stream));
+        else
+            HIP_TRY(sgtv::wsn::conv_softplus(X, bf(n->wf, l * CK), bias, B, n->H, n->W,
+                                             n->z_last.as<float>(), n->out.as<float>(), n->stream));
+    }
+    return SGTV_OK;
+}
+
+int net_check(wsnet_s *n, int B, int mk) {
+    if (!n) return fail(SGTV_EINVAL, "null network");
+    if (!n->have_params) return fail(SGTV_ESTATE, "no parameters set (call wsnet_set_params)");
+    if (B < 1 || B > n->max_batch) return fail(SGTV_EINVAL, "batch must be in [1, max_batch]");
+    return check_mem_kind(mk);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t wsnet_param_count(int32_t layers, int32_t channels) {
+    return static_cast<int64_t>(layers) * (static_cast<int64_t>(channels) * 9 * channels + channels);
+}
+
+int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32_t height,
+                 int32_t width, int32_t channels, int32_t max_batch) {
+    if (!out) return fail(SGTV_EINVAL, "out is NULL");
+    if (channels != 64) return fail(SGTV_ESHAPE, "channels must be 64");
+    if (width != 64) return fail(SGTV_ESHAPE, "width must be 64");
+    if (height < 2 || height % kWgradRows != 0) return fail(SGTV_ESHAPE, "height must be a positive multiple of 8");
+    if (layers < 1 || layers > 16) return fail(SGTV_EINVAL, "layers must be in [1, 16]");
+    if (max_batch < 1 || max_batch > 4096) return fail(SGTV_EINVAL, "max_batch must be in [1, 4096]");
+    int nd = 0;
+    HIP_TRY(hipGetDeviceCount(&nd));
+    if (device < 0 || device >= nd) return fail(SGTV_EINVAL, "device index out of range");
+    DeviceGuard g(device);
+    try {
+        auto n = std::make_unique<wsnet_s>();
+        n->device = device;
+        n->stream = static_cast<hipStream_t>(hip_stream);
+        n->L = layers; n->H = height; n->W = width; n->C = channels; n->max_batch = max_batch;
+        n->per_layer = static_cast<int64_t>(channels) * 9 * channels + channels;
+        n->n_param = wsnet_param_count(layers, channels);
+        n->img = static_cast<int64_t>(height) * width * channels;
+        const int64_t CK = static_cast<int64_t>(channels) * 9 * channels;
+        const int64_t big = static_cast<int64_t>(max_batch) * n->img;
+        HIP_TRY(n->params.alloc(sizeof(float) * n->n_param));
+        HIP_TRY(n->grad.alloc(sizeof(float) * n->n_param));
+        HIP_TRY(n->m.alloc(sizeof(float) * n->n_param));
+        HIP_TRY(n->v.alloc(sizeof(float) * n->n_param));
+        HIP_TRY(n->wf.alloc(2 * CK * layers));
+        HIP_TRY(n->wb.alloc(2 * CK * layers));
+        HIP_TRY(n->acts.alloc(2 * big * layers));
+        HIP_TRY(n->z_last.alloc(sizeof(float) * big));
+        HIP_TRY(n->out.alloc(sizeof(float) * big));
+        HIP_TRY(n->xin.alloc(sizeof(float) * big));
+        HIP_TRY(n->tgt.alloc(sizeof(float) * big));
+        HIP_TRY(n->dz[0].alloc(2 * big));
+        HIP_TRY(n->dz[1].alloc(2 * big));
+        HIP_TRY(n->wpart.alloc(sizeof(float) * (CK + channels) * max_batch * (height / kWgradRows)));
+        HIP_TRY(n->lpart.alloc(sizeof(double) * kLossBlocks));
+        HIP_TRY(n->lred.alloc(sizeof(double) * 4));
+        *out = n.release();
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+void wsnet_destroy(wsnet net) {
+    if (!net) return;
+    DeviceGuard g(net->device);
+    if (net->stream) (void)hipStreamSynchronize(net->stream);
+    else (void)hipDeviceSynchronize();
+    delete net;
+}
+
+int wsnet_set_params(wsnet net, const float *params, int64_t n, int mem_kind) {
+    if (!net || !params) return fail(SGTV_EINVAL, "null argument");
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (n != net->n_param) return fail(SGTV_ESHAPE, "parameter count does not match the network");
+    DeviceGuard g(net->device);
+    std::vector<float> h;
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    HIP_TRY(fetch(h, params, n, mem_kind));
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(h[i])) return fail(SGTV_EINVAL, "parameters must be finite");
+    HIP_TRY(hipMemcpyAsync(net->params.p, h.data(), sizeof(float) * n, hipMemcpyHostToDevice, net->stream));
+    HIP_TRY(hipMemsetAsync(net->m.p, 0, sizeof(float) * n, net->stream));
+    HIP_TRY(hipMemsetAsync(net->v.p, 0, sizeof(float) * n, net->stream));
+    if (int e = net_weights(net)) return e;
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    net->step = 0;
+    net->have_params = true;
+    net->have_grad = false;
+    return SGTV_OK;
+}
+
+int wsnet_get_params(wsnet net, float *params, int64_t n, int mem_kind) {
+    if (!net || !params) return fail(SGTV_EINVAL, "null argument");
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (n != net->n_param) return fail(SGTV_ESHAPE, "parameter count does not match the network");
+    DeviceGuard g(net->device);
+    HIP_TRY(hipMemcpyAsync(params, net->params.p, sizeof(float) * n, to_caller(mem_kind), net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return SGTV_OK;
+}
+
+int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int mem_kind) {
+    if (int e = net_check(net, batch, mem_kind)) return e;
+    if (!x_in || !x0) return fail(SGTV_EINVAL, "null argument");
+    DeviceGuard g(net->device);
+    const int64_t cnt = batch * net->img;
+    if (int e = net_stage(net, net->xin, x_in, cnt, mem_kind)) return e;
+    if (int e = net_forward(net, batch)) return e;
+    HIP_TRY(hipMemcpyAsync(x0, net->out.p, sizeof(float) * cnt, to_caller(mem_kind), net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return SGTV_OK;
+}
+
+int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t batch,
+                   double *loss, float *grad, int mem_kind) {
+    if (int e = net_check(net, batch, mem_kind)) return e;
+    if (!x_in || !target) return fail(SGTV_EINVAL, "null argument");
+    DeviceGuard g(net->device);
+    const int64_t cnt = batch * net->img;
+    const int64_t CK = static_cast<int64_t>(net->C) * 9 * net->C;
+    if (int e = net_stage(net, net->xin, x_in, cnt, mem_kind)) return e;
+    if (int e = net_stage(net, net->tgt, target, cnt, mem_kind)) return e;
+    if (int e = net_forward(net, batch)) return e;
+    int cur = 0;
+    HIP_TRY(sgtv::wsn::mse_grad(net->out.as<float>(), net->tgt.as<float>(), net->z_last.as<float>(), cnt,
+                                bf(net->dz[cur]), net->lpart.as<double>(), kLossBlocks, net->stream));
+    HIP_TRY(sgtv::launch_reduce(net->lpart.as<double>(), kLossBlocks, 1, net->lred.as<double>(), net->stream));
+    for (int l = net->L - 1; l >= 0; --l) {
+        const __bf16 *X = bf(net->acts, l * net->max_batch * net->img);
+        HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, net->W, kWgradRows,
+                                      net->wpart.as<float>(), net->grad.as<float>() + l * net->per_layer,
+                                      net->stream));
+        if (l == 0) break;
+        HIP_TRY(sgtv::wsn::conv_masked(bf(net->dz[cur]), bf(net->wb, l * CK), batch, net->H, net->W, X,
+                                       bf(net->dz[cur ^ 1]), net->stream));
+        cur ^= 1;
+    }
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, net->lred.p, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+    if (grad)
+        HIP_TRY(hipMemcpyAsync(grad, net->grad.p, sizeof(float) * net->n_param, to_caller(mem_kind), net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    if (loss) *loss = h / static_cast<double>(cnt);
+    net->have_grad = true;
+    return SGTV_OK;
+}
+
+int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps) {
+    if (!net) return fail(SGTV_EINVAL, "null network");
+    if (!net->have_grad) return fail(SGTV_ESTATE, "no gradient (call wsnet_backward first)");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return fail(SGTV_EINVAL, "Adam needs lr > 0, 0 <= beta1, beta2 < 1 and eps > 0");
+    DeviceGuard g(net->device);
+    net->step += 1;
+    const double c1 = 1.0 - std::pow(beta1, static_cast<double>(net->step));
+    const double c2 = 1.0 - std::pow(beta2, static_cast<double>(net->step));
+    HIP_TRY(sgtv::wsn::adam(net->params.as<float>(), net->grad.as<float>(), net->m.as<float>(),
+                            net->v.as<float>(), net->n_param, static_cast<float>(lr), static_cast<float>(beta1),
+                            static_cast<float>(beta2), static_cast<float>(eps), static_cast<float>(c1),
+                            static_cast<float>(c2), net->stream));
+    if (int e = net_weights(net)) return e;
+    return SGTV_OK;
+}
+
+int wsnet_reset_adam(wsnet net) {
+    if (!net) return fail(SGTV_EINVAL, "null network");
+    DeviceGuard g(net->device);
+    HIP_TRY(hipMemsetAsync(net->m.p, 0, sizeof(float) * net->n_param, net->stream));
+    HIP_TRY(hipMemsetAsync(net->v.p, 0, sizeof(float) * net->n_param, net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    net->step = 0;
+    return SGTV_OK;
 }
 
 }  // extern "C"

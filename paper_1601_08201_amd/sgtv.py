@@ -94,6 +94,15 @@ def lib():
             "sgtv_batch_iterate_sequential": (_I, [_P, _I]),
             "sgtv_batch_objective": (_I, [_P, _I32, ctypes.POINTER(Report)]),
             "sgtv_batch_get_image": (_I, [_P, _I32, _P, _I]),
+            "wsnet_create": (_I, [ctypes.POINTER(_P), _I, _P, _I32, _I32, _I32, _I32, _I32]),
+            "wsnet_destroy": (None, [_P]),
+            "wsnet_param_count": (_I64, [_I32, _I32]),
+            "wsnet_set_params": (_I, [_P, _P, _I64, _I]),
+            "wsnet_get_params": (_I, [_P, _P, _I64, _I]),
+            "wsnet_forward": (_I, [_P, _P, _I32, _P, _I]),
+            "wsnet_backward": (_I, [_P, _P, _P, _I32, ctypes.POINTER(_D), _P, _I]),
+            "wsnet_adam_step": (_I, [_P, _D, _D, _D, _D]),
+            "wsnet_reset_adam": (_I, [_P]),
             "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_get_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_kernel_times": (_I, [_P, _P, _P]),
@@ -457,3 +466,118 @@ class Batch:
 
     def image(self, scan, out=None):
         return sgtv_batch_get_image(self._b, scan, self._J[scan], out)
+
+
+# ---- warm-start network ------------------------------------------------------------------
+
+def wsnet_create(device=0, stream=None, layers=6, height=64, width=64, channels=64, max_batch=32):
+    h = ctypes.c_void_p()
+    _check(lib().wsnet_create(ctypes.byref(h), int(device), stream, int(layers), int(height),
+                              int(width), int(channels), int(max_batch)))
+    return h
+
+
+def wsnet_destroy(net):
+    lib().wsnet_destroy(net)
+
+
+def wsnet_param_count(layers, channels):
+    return int(lib().wsnet_param_count(int(layers), int(channels)))
+
+
+def wsnet_set_params(net, params):
+    a = _arg(params, np.float32)
+    _check(lib().wsnet_set_params(net, a[0], int(np.prod(a[2].shape)), _kind(a)))
+
+
+def wsnet_get_params(net, n):
+    out = np.empty(n, np.float32)
+    _check(lib().wsnet_get_params(net, out.ctypes.data_as(_P), n, SGTV_HOST))
+    return out
+
+
+def wsnet_forward(net, x_in, batch, out):
+    a = _arg(x_in, np.float32)
+    p, mk = _out_arg(out)
+    if mk != _kind(a):
+        raise ValueError("x_in and out must both be host arrays or both device tensors")
+    _check(lib().wsnet_forward(net, a[0], int(batch), p, mk))
+    return out
+
+
+def wsnet_backward(net, x_in, target, batch, grad=None):
+    a, t = _arg(x_in, np.float32), _arg(target, np.float32)
+    mk = _kind(a, t)
+    loss = ctypes.c_double()
+    gp = None
+    if grad is not None:
+        gp, gmk = _out_arg(grad)
+        if gmk != mk:
+            raise ValueError("grad must live where the inputs live")
+    _check(lib().wsnet_backward(net, a[0], t[0], int(batch), ctypes.byref(loss), gp, mk))
+    return loss.value
+
+
+def wsnet_adam_step(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().wsnet_adam_step(net, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def wsnet_reset_adam(net):
+    _check(lib().wsnet_reset_adam(net))
+
+
+class WarmStartNet:
+    """Owning handle of the warm-start network (images NHWC, 64 channels)."""
+
+    def __init__(self, device=0, stream=None, layers=6, height=64, width=64, channels=64, max_batch=32):
+        self.shape = (height, width, channels)
+        self.layers = layers
+        self.max_batch = max_batch
+        self.n_params = wsnet_param_count(layers, channels)
+        self._n = wsnet_create(device, stream, layers, height, width, channels, max_batch)
+
+    def close(self):
+        if self._n is not None:
+            wsnet_destroy(self._n)
+            self._n = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        wsnet_set_params(self._n, params)
+        return self
+
+    def params(self):
+        return wsnet_get_params(self._n, self.n_params)
+
+    def forward(self, x_in, out=None):
+        b = x_in.shape[0]
+        if out is None:
+            out = np.empty((b,) + self.shape, np.float32) if not _is_torch_cuda(x_in) else x_in.new_empty(x_in.shape)
+        return wsnet_forward(self._n, x_in, b, out)
+
+    def backward(self, x_in, target, grad=None):
+        return wsnet_backward(self._n, x_in, target, x_in.shape[0], grad)
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        wsnet_adam_step(self._n, lr, beta1, beta2, eps)
+        return self
+
+    def reset_adam(self):
+        wsnet_reset_adam(self._n)
+        return self
+
+
+def init_params(layers=6, channels=64, seed=0):
+    """He-style random initial parameters (float32), biases zero."""
+    rng = np.random.default_rng(seed)
+    per = channels * 9 * channels
+    out = []
+    for _ in range(layers):
+        out.append(rng.normal(scale=np.sqrt(2.0 / (9 * channels)), size=per).astype(np.float32))
+        out.append(np.zeros(channels, np.float32))
+    return np.concatenate(out)

@@ -1,0 +1,155 @@
+"""Warm-start network kernels against the FP64 oracle.
+
+One layer isolates the convolution: the GPU rounds input and weights to
+bfloat16 and accumulates in FP32, so the oracle fed the same rounded values
+must agree to FP32 accumulation error.  The six-layer network also rounds
+every hidden activation and every activation gradient to bfloat16 (relative
+error 2^-9 each), so it is compared with the unrounded FP64 oracle at 2e-2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sg():
+    assert torch.cuda.is_available()
+    from paper_1601_08201_amd import sgtv
+    sgtv.lib()
+    return sgtv
+
+
+def bf16(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def data(seed, B=2, H=8, C=64, scale=1.0):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, scale, size=(B, H, 64, C)).astype(np.float32)
+    t = rng.uniform(0, scale, size=(B, H, 64, C)).astype(np.float32)
+    return x, t
+
+
+def layer_params(sg, L, seed):
+    return sg.init_params(L, 64, seed) + np.float32(0.01) * np.random.default_rng(seed + 1).normal(
+        size=sg.wsnet_param_count(L, 64)).astype(np.float32)
+
+
+def rounded_params(p, L):
+    """weights rounded to bfloat16 as the GPU multiplies them; biases kept FP32."""
+    q = p.astype(np.float64).copy()
+    per = 64 * 9 * 64 + 64
+    for l in range(L):
+        q[l * per: l * per + 64 * 9 * 64] = bf16(p[l * per: l * per + 64 * 9 * 64])
+    return q
+
+
+def test_one_layer_forward_tight(sg):
+    x, _ = data(1)
+    p = layer_params(sg, 1, 3)
+    N = sg.WarmStartNet(layers=1, height=8, max_batch=4).set_params(p)
+    out = N.forward(x)
+    ref = oracle.wn_forward(rounded_params(p, 1), bf16(x), L=1)
+    err = rel(out, ref)
+    print("one-layer forward rel L2", err, flush=True)
+    assert err <= 1e-5
+
+
+def test_one_layer_gradient(sg):
+    x, t = data(2)
+    p = layer_params(sg, 1, 4)
+    N = sg.WarmStartNet(layers=1, height=8, max_batch=4).set_params(p)
+    g = np.empty(p.size, np.float32)
+    loss = N.backward(x, t, g)
+    loss_o, g_o = oracle.wn_loss_grad(rounded_params(p, 1), bf16(x), t, L=1)
+    print("one-layer loss", loss, loss_o, "grad rel L2", rel(g, g_o), flush=True)
+    assert loss == pytest.approx(loss_o, rel=1e-5)
+    assert rel(g, g_o) <= 5e-3
+
+
+def test_six_layer_network_against_fp64(sg):
+    x, t = data(3, B=3, H=16)
+    p = layer_params(sg, 6, 5)
+    N = sg.WarmStartNet(layers=6, height=16, max_batch=4).set_params(p)
+    out = N.forward(x)
+    g = np.empty(p.size, np.float32)
+    loss = N.backward(x, t, g)
+    out_o = oracle.wn_forward(p, x, L=6)
+    loss_o, g_o = oracle.wn_loss_grad(p, x, t, L=6)
+    print("six-layer out rel", rel(out, out_o), "loss", loss, loss_o, "grad rel", rel(g, g_o), flush=True)
+    assert rel(out, out_o) <= 2e-2
+    assert loss == pytest.approx(loss_o, rel=2e-2)
+    assert rel(g, g_o) <= 2e-2
+    # per layer as well
+    per = 64 * 9 * 64 + 64
+    for l in range(6):
+        assert rel(g[l * per:(l + 1) * per], g_o[l * per:(l + 1) * per]) <= 5e-2
+
+
+def test_backward_is_deterministic(sg):
+    x, t = data(4)
+    p = layer_params(sg, 6, 6)
+    N = sg.WarmStartNet(layers=6, height=8, max_batch=4).set_params(p)
+    g1, g2 = np.empty(p.size, np.float32), np.empty(p.size, np.float32)
+    l1 = N.backward(x, t, g1)
+    l2 = N.backward(x, t, g2)
+    assert l1 == l2
+    np.testing.assert_array_equal(g1, g2)
+
+
+def test_adam_first_step_follows_gradient_signs(sg):
+    """After one step Adam moves every parameter by -lr * g / (|g| + eps'),
+    i.e. about -lr sign(g); signs agree with the oracle's FP64 gradient
+    wherever that gradient is not tiny."""
+    x, t = data(5)
+    p = layer_params(sg, 2, 7)
+    N = sg.WarmStartNet(layers=2, height=8, max_batch=4).set_params(p)
+    N.backward(x, t)
+    lr = 1e-3
+    N.adam_step(lr=lr)
+    step = (N.params().astype(np.float64) - p) / lr
+    _, g_o = oracle.wn_loss_grad(p, x, t, L=2)
+    m = np.zeros_like(g_o)
+    v = np.zeros_like(g_o)
+    q = p.astype(np.float64).copy()
+    oracle.wn_adam(q, g_o, m, v, 1, lr=lr)
+    big = np.abs(g_o) > 1e-2 * np.abs(g_o).max()
+    np.testing.assert_allclose(step[big], ((q - p) / lr)[big], atol=2e-3)
+
+
+def test_training_lowers_the_loss(sg):
+    x, _ = data(6, B=4)
+    t = np.sqrt(x).astype(np.float32)
+    p = layer_params(sg, 6, 8)
+    N = sg.WarmStartNet(layers=6, height=8, max_batch=4).set_params(p)
+    first = N.backward(x, t)
+    for _ in range(40):
+        N.adam_step(lr=2e-3)
+        last = N.backward(x, t)
+    print("loss", first, "->", last, flush=True)
+    assert last < 0.5 * first
+
+
+def test_invalid_network_arguments(sg):
+    with pytest.raises(sg.SgtvError):
+        sg.WarmStartNet(channels=32)
+    with pytest.raises(sg.SgtvError):
+        sg.WarmStartNet(width=32)
+    N = sg.WarmStartNet(layers=2, height=8, max_batch=2)
+    x, t = data(7, B=3)
+    with pytest.raises(sg.SgtvError):
+        N.forward(x)              # no parameters yet
+    N.set_params(layer_params(sg, 2, 1))
+    with pytest.raises(sg.SgtvError):
+        N.forward(x)              # batch above max_batch
+    with pytest.raises(sg.SgtvError):
+        N.adam_step()             # no gradient yet
