@@ -172,6 +172,106 @@ def batch_main(args):
     B.close()
 
 
+def warmstart_main(args):
+    """Learned warm start against the plain uniform start on held-out phantoms of
+    a fixed 64x64x64 scanner: iterations and wall time until the objective is
+    within 1e-4 (relative) of the plain converged objective."""
+    import numpy as np
+    import torch
+    from paper_1601_08201_amd import autotune, sgtv, warmstart
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    scanner = warmstart.make_scanner(1)
+    tuned = autotune.cached_schedule(datagen_problem_like(scanner))
+    recon = warmstart.Reconstruction(scanner, schedule=tuned)
+    xin, tgt, _ = warmstart.make_dataset(scanner, range(10000, 10000 + args.train_scans), iters=300,
+                                         log=log, recon=recon)
+    log("training set: %d scans in %.1fs" % (args.train_scans, time.time() - t0))
+    t1 = time.time()
+    model, net, hist = warmstart.train(xin, tgt, epochs=args.epochs, log=log)
+    train_s = time.time() - t1
+    log("trained %d epochs in %.1fs, loss %.5f -> %.5f" % (args.epochs, train_s, hist[0], hist[-1]))
+    del xin, tgt
+    scans = warmstart.draw_scans(scanner, range(20000, 20000 + args.eval_scans))
+    R = recon.R
+    tols = (1e-2, 1e-3, 1e-4)
+    recs = {"plain": [], "learned": [], "learned_zero_dual": []}
+    fallbacks = 0
+    for k, (_, y, r) in enumerate(scans):
+        recon.load(y, r)
+        phi_star, n_conv = warmstart.converged_objective(R)
+        torch.cuda.synchronize()
+        # plain: uniform start (its setup is inside the timed region too)
+        t = time.perf_counter()
+        R.set_init(None)
+        setup = time.perf_counter() - t
+        it, sec = warmstart.iterations_to_targets(R, phi_star, tols)
+        recs["plain"].append((it, [setup + s_ if s_ is not None else None for s_ in sec]))
+        # learned: backprojection, network, fallback test, then ADMM from the
+        # network image with the split and dual that make it a fixed point
+        t = time.perf_counter()
+        x_bp = R.backprojection().reshape(1, scanner.ny, scanner.nx, scanner.Q)
+        x0 = warmstart.predict(net, model, x_bp).reshape(-1)
+        R.set_init(None)
+        phi_u = R.objective()["total"]
+        R.set_init_dual(x0)
+        phi_n = R.objective()["total"]
+        if phi_n > phi_u:
+            fallbacks += 1
+            R.set_init(None)
+        setup = time.perf_counter() - t
+        it, sec = warmstart.iterations_to_targets(R, phi_star, tols)
+        recs["learned"].append((it, [setup + s_ if s_ is not None else None for s_ in sec]))
+        # the same network image with d = c = 0
+        t = time.perf_counter()
+        R.set_init(x0)
+        it, sec = warmstart.iterations_to_targets(R, phi_star, tols)
+        recs["learned_zero_dual"].append((it, [setup + s_ if s_ is not None else None for s_ in sec]))
+        if (k + 1) % 25 == 0:
+            log("eval %d / %d" % (k + 1, args.eval_scans))
+
+    def quart(vals):
+        v = np.array([np.nan if x is None else x for x in vals], np.float64)
+        return [float(np.nanpercentile(v, 25)), float(np.nanmedian(v)), float(np.nanpercentile(v, 75))]
+
+    summary = {}
+    for name, rr in recs.items():
+        summary[name] = {}
+        for i, tol in enumerate(tols):
+            summary[name]["%g" % tol] = {"iterations_q25_q50_q75": quart([x[0][i] for x in rr]),
+                                         "ms_q25_q50_q75": [1e3 * v for v in quart([x[1][i] for x in rr])],
+                                         "reached": int(sum(x[0][i] is not None for x in rr))}
+    med_plain = summary["plain"]["0.0001"]["ms_q25_q50_q75"][1]
+    med_learn = summary["learned"]["0.0001"]["ms_q25_q50_q75"][1]
+    out = {
+        "metric": "time to 1e-4 rel obj, learned vs plain (64x64x64 scanner, held-out phantoms)",
+        "value": med_plain / med_learn,
+        "unit": "x speedup of median wall time (plain / learned)",
+        "n_gpus": 1, "steps": args.eval_scans, "warmup": 0,
+        "ms_per_step": med_learn,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 ADMM, bf16 MFMA network",
+        "data": "synthetic (fixed random coded-mask scanner, seeded phantoms with 6-16 rectangles, Poisson counts)",
+        "config": {"workload": "warm start 64x64x64, I=131072, 32 nnz/col; %d training scans (300-iteration targets), "
+                               "%d epochs, %d held-out scans" % (args.train_scans, args.epochs, args.eval_scans),
+                   "global_batch": 32, "parallelism": "single GPU"},
+        "by_tolerance": summary,
+        "fallbacks": fallbacks,
+        "training_seconds": train_s,
+        "train_loss_first_last": [hist[0], hist[-1]],
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def datagen_problem_like(s):
+    class P:
+        pass
+    p = P()
+    p.I, p.ny, p.nx, p.Q, p.nnz = s.I, s.ny, s.nx, s.Q, int(s.col.shape[0])
+    return p
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,8 +285,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="scan", choices=["scan", "batch"],
-                    help="scan: the paper-scale scan (default); batch: 64 uneven scans")
+    ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart"],
+                    help="scan: the paper-scale scan (default); batch: 64 uneven scans; "
+                         "warmstart: learned start vs plain start")
+    ap.add_argument("--train-scans", type=int, default=2000)
+    ap.add_argument("--eval-scans", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch-scans", type=int, default=64)
     args = ap.parse_args()
 
@@ -207,6 +311,8 @@ def main():
         if args.steps == 200:
             args.steps = 100
         return batch_main(args)
+    if args.workload == "warmstart":
+        return warmstart_main(args)
 
     t0 = time.time()
     prob = datagen.make_problem(args.config, args.seed)

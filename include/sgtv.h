@@ -128,6 +128,14 @@ int sgtv_set_grouping(sgtv_ctx ctx, int grouping);
  * kappa * 1.  Resets d = c = 0, k = 0. */
 int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind);
 
+/* Start image x0 (J values, finite, >= 0) together with the split and dual
+ * variables for which x0 is a fixed point of the split and dual updates
+ * (Eqs. 5-6): d = w.*G x0 and, on every group g with d_g != 0, the scaled
+ * dual c_g = (beta / rho) d_g / ||d_g|| (0 on the other groups), the
+ * optimality condition of Eq. 5.  A start image near the solution then
+ * starts near the ADMM fixed point, where d = c = 0 would not.  k = 0. */
+int sgtv_set_init_dual(sgtv_ctx ctx, const float *x0, int mem_kind);
+
 /* Run n_iters >= 0 ADMM iterations (Eqs. 4-6) asynchronously on the stream. */
 int sgtv_iterate(sgtv_ctx ctx, int n_iters);
 

@@ -929,6 +929,33 @@ int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind) {
     return SGTV_OK;
 }
 
+int sgtv_set_init_dual(sgtv_ctx ctx, const float *x0, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (!x0) return fail(SGTV_EINVAL, "x0 is NULL");
+    DeviceGuard g(ctx->device);
+    try {
+        const System &S = *ctx->sys;
+        DBuf staged;
+        if (int e = stage_floats(staged, x0, S.J, mem_kind, ctx->stream, finite_nonneg, "x0")) return e;
+        drop_graphs(ctx);
+        HIP_TRY(hipMemcpyAsync(ctx->f[0].p, staged.p, sizeof(float) * S.J, hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->fcur = 0;
+        ctx->vcur = 0;
+        HIP_TRY(sgtv::launch_consistent_split(ctx->f[0].as<float>(), ctx->v[0].as<float>(), ctx->a[0].as<float>(),
+                                              S.grid, S.weights(), ctx->grouping,
+                                              static_cast<float>(ctx->beta / ctx->rho), ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->v[1].p, ctx->v[0].p, sizeof(float) * S.J * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->a[1].p, ctx->a[0].p, sizeof(float) * n_groups(ctx), hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->k = 0;
+        if (int e = refresh_scaled(ctx)) return e;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
 int sgtv_iterate(sgtv_ctx ctx, int n_iters) {
     if (int e = check_ready(ctx)) return e;
     if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");

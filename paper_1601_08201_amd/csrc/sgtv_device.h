@@ -173,4 +173,63 @@ __device__ __forceinline__ void split_bin(int64_t s, bool active, int ls, int se
     }
 }
 
+// Split state that makes image f a fixed point of the split update: with
+// d = w.*G f and thr = beta / rho, the scaled dual satisfying the optimality
+// condition of Eq. 5 is c_g = thr d_g / ||d_g|| on every group g with d_g != 0
+// (0 otherwise).  Stored as v = d + c = d (1 + thr / ||d_g||) and
+// a = ||d_g|| / (||d_g|| + thr), so that shrink(v) = a v = d.
+template <int GROUPING>
+__device__ __forceinline__ void consistent_bin(int64_t s, bool active, int ls, int seg_log2,
+                                               const float *__restrict__ f, float *__restrict__ v,
+                                               float *__restrict__ a, const Grid &grid,
+                                               const Weights &wts, float thr) {
+    const int G = 1 << seg_log2;
+    const int Q = grid.Q;
+    float ss = 0.0f;
+    int iy = 0, ix = 0;
+    int64_t nb[4] = {-1, -1, -1, -1};
+    if (active) {
+        iy = static_cast<int>(s / grid.nx);
+        ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) nb[p] = neighbour(grid, s, iy, ix, p);
+        for (int q = ls; q < Q; q += G) {
+            const float fs = f[s * Q + q];
+            float sq = 0.0f;
+            float d[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const float fn = nb[p] >= 0 ? f[nb[p] * Q + q] : 0.0f;
+                d[p] = weight(wts, grid, s, p, q) * (fs - fn);
+                sq = fmaf(d[p], d[p], sq);
+            }
+            if (GROUPING == 0) {
+                ss += sq;
+            } else {
+                const float nrm = sqrtf(sq);
+                const float scale = nrm > 0.0f ? 1.0f + thr / nrm : 0.0f;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) v[(s * 4 + p) * Q + q] = d[p] * scale;
+                a[s * Q + q] = nrm > 0.0f ? nrm / (nrm + thr) : 0.0f;
+            }
+        }
+    }
+    if (GROUPING == 0) {
+        ss = seg_sum(ss, G);
+        const float nrm = sqrtf(ss);
+        if (active) {
+            const float scale = nrm > 0.0f ? 1.0f + thr / nrm : 0.0f;
+            for (int q = ls; q < Q; q += G) {
+                const float fs = f[s * Q + q];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const float fn = nb[p] >= 0 ? f[nb[p] * Q + q] : 0.0f;
+                    v[(s * 4 + p) * Q + q] = weight(wts, grid, s, p, q) * (fs - fn) * scale;
+                }
+            }
+            if (ls == 0) a[s] = nrm > 0.0f ? nrm / (nrm + thr) : 0.0f;
+        }
+    }
+}
+
 }  // namespace sgtv

@@ -117,6 +117,8 @@ hipError_t launch_back_update(const Sell &At, int vt, const float *ratio, const 
 hipError_t launch_split_update(const float *f, const float *v_old, const float *a_old,
                                float *v_new, float *a_new, const Grid &grid, const Weights &w,
                                int grouping, float thr, hipStream_t st);
+hipError_t launch_consistent_split(const float *f, float *v, float *a, const Grid &grid,
+                                   const Weights &w, int grouping, float thr, hipStream_t st);
 hipError_t launch_report(const float *f, const float *v, const float *a, const float *v_prev,
                          const float *a_prev, const Grid &grid, const Weights &w, int grouping,
                          double *partials, hipStream_t st, int64_t *n_blocks);

@@ -137,6 +137,16 @@ __global__ __launch_bounds__(kBlock) void k_split_update(
     split_bin<GROUPING>(s, s < grid.S, ls, seg_log2, f, v_old, a_old, v_new, a_new, grid, wts, thr);
 }
 
+template <int GROUPING>
+__global__ __launch_bounds__(kBlock) void k_consistent_split(const float *__restrict__ f,
+                                                             float *__restrict__ v,
+                                                             float *__restrict__ a, Grid grid,
+                                                             Weights wts, float thr, int seg_log2) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock >> seg_log2) + (threadIdx.x >> seg_log2);
+    const int ls = threadIdx.x & ((1 << seg_log2) - 1);
+    consistent_bin<GROUPING>(s, s < grid.S, ls, seg_log2, f, v, a, grid, wts, thr);
+}
+
 // ---------------------------------------------------------------- report
 // FP64 partials per block: [0] R(w.*G f), [1] ||w.*G f - d||^2,
 // [2] ||(w.*G)^T (d - d_prev)||^2 with d = a v, d_prev = a_prev v_prev.
@@ -344,6 +354,18 @@ hipError_t launch_split_update(const float *f, const float *v_old, const float *
     else
         hipLaunchKernelGGL(k_split_update<1>, dim3(nb), dim3(kBlock), 0, st, f, v_old, a_old,
                            v_new, a_new, grid, w, thr, sl);
+    return hipGetLastError();
+}
+
+hipError_t launch_consistent_split(const float *f, float *v, float *a, const Grid &grid,
+                                   const Weights &w, int grouping, float thr, hipStream_t st) {
+    const int sl = seg_log2_for(grid.Q);
+    const unsigned nb = blocks_for(grid.S, kBlock >> sl);
+    if (nb == 0) return hipSuccess;
+    if (grouping == 0)
+        hipLaunchKernelGGL(k_consistent_split<0>, dim3(nb), dim3(kBlock), 0, st, f, v, a, grid, w, thr, sl);
+    else
+        hipLaunchKernelGGL(k_consistent_split<1>, dim3(nb), dim3(kBlock), 0, st, f, v, a, grid, w, thr, sl);
     return hipGetLastError();
 }
 

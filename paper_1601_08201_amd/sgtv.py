@@ -75,6 +75,7 @@ def lib():
             "sgtv_set_data": (_I, [_P, _P, _P, _D, _D, _I, _I]),
             "sgtv_set_grouping": (_I, [_P, _I]),
             "sgtv_set_init": (_I, [_P, _P, _I]),
+            "sgtv_set_init_dual": (_I, [_P, _P, _I]),
             "sgtv_iterate": (_I, [_P, _I]),
             "sgtv_objective": (_I, [_P, ctypes.POINTER(Report)]),
             "sgtv_get_image": (_I, [_P, _P, _I]),
@@ -189,6 +190,11 @@ def sgtv_set_grouping(ctx, grouping):
 def sgtv_set_init(ctx, x0=None):
     a = _arg(x0, np.float32)
     _check(lib().sgtv_set_init(ctx, a[0], _kind(a)))
+
+
+def sgtv_set_init_dual(ctx, x0):
+    a = _arg(x0, np.float32)
+    _check(lib().sgtv_set_init_dual(ctx, a[0], _kind(a)))
 
 
 def sgtv_iterate(ctx, n_iters):
@@ -329,6 +335,10 @@ class Reconstructor:
 
     def set_init(self, x0=None):
         sgtv_set_init(self._ctx, x0)
+        return self
+
+    def set_init_dual(self, x0):
+        sgtv_set_init_dual(self._ctx, x0)
         return self
 
     def iterate(self, n):

@@ -298,3 +298,58 @@ def test_reduced_precision_matches_oracle_on_quantised_matrix(sg, storage, fmt):
     phi_x = oracle.objective(prob, f_x)[0]
     print("storage", storage, "rel objective vs exact-matrix oracle", abs(phi_g - phi_x) / phi_x, flush=True)
     assert abs(phi_g - phi_x) / phi_x <= 1e-3
+
+
+def consistent_split(prob, x0, grouping=0):
+    """d = D x0 and c = (beta/rho) d_g/||d_g|| per group (0 where d_g = 0)."""
+    thr = prob.beta / prob.rho
+    d = oracle.diff(prob.ny, prob.nx, prob.Q, x0).reshape(prob.ny * prob.nx, 4, prob.Q)
+    if grouping == 0:
+        n = np.sqrt((d ** 2).sum(axis=(1, 2)))[:, None, None]
+    else:
+        n = np.sqrt((d ** 2).sum(axis=1))[:, None, :]
+    c = np.where(n > 0, thr * d / np.where(n > 0, n, 1), 0.0)
+    return d.ravel(), c.ravel()
+
+
+@pytest.mark.parametrize("grouping", [0, 1])
+def test_dual_consistent_start_matches_oracle(sg, grouping):
+    prob = datagen.make_problem("small", 13)
+    x0 = np.random.default_rng(2).uniform(0, 3, prob.J).astype(np.float32)
+    R = sg.Reconstructor()
+    if grouping:
+        R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val)
+        R.set_grouping(grouping)
+        R.set_data(prob.y, prob.r, prob.beta, prob.rho, 1)
+    else:
+        R.set_problem(prob)
+    R.set_init_dual(x0)
+    d_g, c_g = R.split()
+    d0, c0 = consistent_split(prob, x0.astype(np.float64), grouping)
+    assert rel_l2(d_g, d0) <= 1e-6
+    # c = v - a v is formed in FP32 from the stored (v, a): cancellation of
+    # order eps * ||d_g|| / (beta / rho)
+    assert rel_l2(c_g, c0) <= 1e-4
+    R.iterate(20)
+    f_o, _, _, _ = oracle.admm(prob, 20, f0=x0, d0=d0, c0=c0, grouping=grouping, report=False)
+    assert rel_l2(R.image(), f_o) <= IMG_TOL
+
+
+def test_dual_consistent_start_is_near_fixed_point(sg):
+    """Started at a converged image with its consistent split, one iteration
+    barely moves it; with d = c = 0 the same image moves away."""
+    prob = datagen.make_problem("small", 14)
+    R = sg.Reconstructor().set_problem(prob)
+    R.iterate(3000)
+    f_star = R.image()
+    phi_star = R.objective()["total"]
+    R.set_init_dual(f_star)
+    R.iterate(1)
+    moved_dual = rel_l2(R.image(), f_star)
+    phi_dual = R.objective()["total"]
+    R.set_init(f_star)
+    R.iterate(1)
+    moved_zero = rel_l2(R.image(), f_star)
+    print("moved: consistent", moved_dual, "zero", moved_zero, flush=True)
+    assert moved_dual < 0.1 * moved_zero
+    assert abs(phi_dual - phi_star) <= 1e-5 * phi_star
