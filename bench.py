@@ -172,6 +172,94 @@ def batch_main(args):
     B.close()
 
 
+def sweep_main(args):
+    """The beta sweep of both regularisers on the paper-shaped problem as one
+    batch (one batched launch per kernel and iteration), against the same
+    scans launched one after another; the images after warmup + steps
+    iterations are scored against the phantom."""
+    import numpy as np
+    import torch
+    from paper_1601_08201_amd import datagen, sgtv, study
+
+    torch.cuda.set_device(0)
+    prob = datagen.make_problem("teflon", args.seed)
+    w = prob.meta["weights"]
+    betas = [float(b) for b in args.betas.split(",")]
+    pairs = [(g, b) for g in (0, 1) for b in betas]
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def run(sequential):
+        B = sgtv.Batch(stream=stream.cuda_stream)
+        for g, b in pairs:
+            B.add_scan(prob, w=w, grouping=g, beta=b)
+        it = B.iterate_sequential if sequential else B.iterate
+        it(args.warmup)
+        torch.cuda.synchronize()
+        a, e = ev(), ev()
+        a.record(stream)
+        it(args.steps)
+        e.record(stream)
+        torch.cuda.synchronize()
+        return B, a.elapsed_time(e)
+
+    B, ms_batched = run(False)
+    Bs, ms_seq = run(True)
+    S, Q = prob.ny * prob.nx, prob.Q
+    res = []
+    same = True
+    for i, (g, b) in enumerate(pairs):
+        x = B.image(i)
+        same = same and bool(np.array_equal(x, Bs.image(i)))
+        res.append(dict(grouping=g, beta=b, spatial_error=study.spatial_error(x, prob.x_true, S, Q),
+                        spectral_error=study.spectral_error(x, prob.x_true, S, Q)))
+    best = study.select(res)
+    n_total = args.warmup + args.steps
+    log("sweep of %d scans: batched %.3f ms/iter, sequential %.3f ms/iter, images equal: %s"
+        % (len(pairs), ms_batched / args.steps, ms_seq / args.steps, same))
+    for r in res:
+        log("  %-18s beta %-6g spatial error %.4f  spectral error %.5f"
+            % (study.GROUPINGS[r["grouping"]], r["beta"], r["spatial_error"], r["spectral_error"]))
+    alg = len(pairs) * sum(algorithmic_bytes(prob, 4, "tiled").values())
+    scan_its = len(pairs) * args.steps
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_cpu = args.cpu_iters
+        t0 = time.perf_counter()
+        oracle.admm(prob, n_cpu, beta=betas[0], w=w, grouping=0, report=False)
+        dt = time.perf_counter() - t0
+        cpu = {"value": n_cpu / dt, "unit": "scan-iters/s", "cores": 1, "kind": "oracle",
+               "sample": "one scan of the sweep, %d iterations (FP64 C oracle, one thread)" % n_cpu}
+    out = {
+        "metric": "beta-sweep scan-iterations/s (both regularisers, one batch)",
+        "value": scan_its / (ms_batched * 1e-3),
+        "unit": "scan-iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_batched / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded phantom scaled to ~26 mean counts, random coded-mask system matrix, Poisson counts)",
+        "config": {"workload": "paper-shaped scan 9x41x54, I=8192, 24 nnz/col, weights from 5 mm x 1.5 mm pitch; "
+                               "%d betas x 2 regularisers = %d scans, images after %d iterations"
+                               % (len(betas), len(pairs), n_total),
+                   "global_batch": len(pairs), "parallelism": "single GPU"},
+        "sequential": {"value": scan_its / (ms_seq * 1e-3), "ms_per_step": ms_seq / args.steps,
+                       "images_bitwise_equal": same},
+        "speedup_vs_sequential": ms_seq / ms_batched,
+        "selected": {study.GROUPINGS[g]: {"beta": r["beta"], "spatial_error": r["spatial_error"],
+                                          "spectral_error": r["spectral_error"]} for g, r in best.items()},
+        "sweep": [[r["grouping"], r["beta"], r["spatial_error"], r["spectral_error"]] for r in res],
+        "roofline": {"bound": "hbm", "kernel": "whole batched iteration",
+                     "achieved": alg * args.steps / (ms_batched * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg * args.steps / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
+    Bs.close()
+
+
 def warmstart_main(args):
     """Learned warm start against the plain uniform start on held-out phantoms of
     a fixed 64x64x64 scanner: iterations and wall time until the objective is
@@ -285,9 +373,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart"],
+    ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart", "sweep"],
                     help="scan: the paper-scale scan (default); batch: 64 uneven scans; "
-                         "warmstart: learned start vs plain start")
+                         "warmstart: learned start vs plain start; sweep: beta sweep of both "
+                         "regularisers on the paper-shaped scan in one batch")
+    ap.add_argument("--betas", default="0.05,0.1,0.2,0.5,1,2,5,10")
     ap.add_argument("--train-scans", type=int, default=2000)
     ap.add_argument("--eval-scans", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=40)
@@ -313,6 +403,14 @@ def main():
         return batch_main(args)
     if args.workload == "warmstart":
         return warmstart_main(args)
+    if args.workload == "sweep":
+        if args.steps == 200:
+            args.steps = 1000
+        if args.warmup == 10:
+            args.warmup = 50
+        if args.cpu_iters == 40:
+            args.cpu_iters = 4000
+        return sweep_main(args)
 
     t0 = time.time()
     prob = datagen.make_problem(args.config, args.seed)

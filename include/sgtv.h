@@ -226,8 +226,8 @@ int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts);
  * ratios, the backprojections, the image updates, the split and dual
  * updates), each covering all scans; sgtv_batch_iterate captures the n
  * iterations into one HIP graph and launches it once.  Scans use FP32
- * values, unit weights, the spectral grouping and one surrogate sweep; each
- * scan may have its own grid, matrix, data, beta, rho and schedule.  A scan
+ * values and one surrogate sweep; each scan may have its own grid, matrix,
+ * weights, grouping, data, beta, rho and schedule.  A scan
  * of a batch gives bit-identical results to the same scan in its own context
  * with the same schedule.
  */
@@ -235,16 +235,18 @@ typedef struct sgtv_batch_s *sgtv_batch;
 
 int sgtv_batch_create(sgtv_batch *out, int device, void *hip_stream);
 void sgtv_batch_destroy(sgtv_batch b);
-/* Add one scan (arguments as sgtv_set_system / sgtv_set_data; schedule NULL:
- * automatic; schedules of one batch must agree on waves and variant).  The
- * new scan starts from the uniform image; index receives its position.
+/* Add one scan (arguments as sgtv_set_system / sgtv_set_grouping /
+ * sgtv_set_data; schedule NULL: automatic; schedules of one batch must agree
+ * on waves and variant).  The new scan starts from the uniform image; index
+ * receives its position.
  * Several threads may add scans to one batch at the same time (the host-side
  * packing of each matrix runs in the calling thread); the scan order is then
  * the order in which the calls finish. */
 int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t Q,
                         const int64_t *row_ptr, const int32_t *col_idx, const float *val,
-                        int64_t nnz, const float *y, const float *r, double beta, double rho,
-                        const sgtv_schedule *schedule, int mem_kind, int32_t *index);
+                        int64_t nnz, const float *w, int64_t w_len, const float *y, const float *r,
+                        double beta, double rho, int grouping, const sgtv_schedule *schedule,
+                        int mem_kind, int32_t *index);
 int sgtv_batch_size(sgtv_batch b, int32_t *n_scans);
 /* n_iters iterations of every scan in batched launches (graph replay). */
 int sgtv_batch_iterate(sgtv_batch b, int n_iters);

@@ -1279,6 +1279,8 @@ int batch_tables(sgtv_batch_s *b) {
         d.sens = S.sens.as<float>();
         d.H = S.H.as<float>();
         d.grid = S.grid;
+        d.wts = S.weights();
+        d.grouping = c->grouping;
         d.I = S.I;
         d.ns_f = S.fwd.map.ns;
         d.ns_b = S.back.map.ns;
@@ -1385,8 +1387,9 @@ void sgtv_batch_destroy(sgtv_batch b) {
 
 int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t Q,
                         const int64_t *row_ptr, const int32_t *col_idx, const float *val,
-                        int64_t nnz, const float *y, const float *r, double beta, double rho,
-                        const sgtv_schedule *schedule, int mem_kind, int32_t *index) {
+                        int64_t nnz, const float *w, int64_t w_len, const float *y, const float *r,
+                        double beta, double rho, int grouping, const sgtv_schedule *schedule,
+                        int mem_kind, int32_t *index) {
     if (!b) return fail(SGTV_EINVAL, "null batch");
     {
         std::lock_guard<std::mutex> lock(b->mu);
@@ -1402,8 +1405,9 @@ int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t
     if (schedule) sch = *schedule;
     sch.format = SGTV_FORMAT_TILED;
     if (int e = sgtv_set_schedule(c, &sch)) return e;
-    if (int e = sgtv_set_system(c, I, ny, nx, Q, row_ptr, col_idx, val, nnz, SGTV_F32, nullptr, 0, mem_kind))
+    if (int e = sgtv_set_system(c, I, ny, nx, Q, row_ptr, col_idx, val, nnz, SGTV_F32, w, w_len, mem_kind))
         return e;
+    if (int e = sgtv_set_grouping(c, grouping)) return e;
     if (int e = sgtv_set_data(c, y, r, beta, rho, 1, mem_kind)) return e;
     std::lock_guard<std::mutex> lock(b->mu);
     if (!b->scans.empty() && b->scans.front()->k != 0)

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(kBlock) void k_ratio_batch(const BatchBlock *__rest
     S.ratio[i] = S.y[i] / p;
 }
 
-// image update of every voxel (FP32 values, unit weights, spectral groups)
+// image update of every voxel (FP32 values)
 __global__ __launch_bounds__(kBlock) void k_voxel_batch(const BatchBlock *__restrict__ blocks,
                                                         const ScanDev *__restrict__ scans,
                                                         int fcur, int vcur) {
@@ -29,11 +29,12 @@ __global__ __launch_bounds__(kBlock) void k_voxel_batch(const BatchBlock *__rest
     if (j >= S.grid.J) return;
     float e = S.bpart[j];
     for (int k = 1; k < S.ns_b; ++k) e += S.bpart[static_cast<int64_t>(k) * S.grid.J + j];
-    Weights wts;
-    wts.w[0] = wts.w[1] = wts.w[2] = wts.w[3] = 1.0f;
-    wts.full = nullptr;
-    S.f[fcur ^ 1][j] = voxel_update_value<0>(j, e, S.f[fcur], S.v[vcur], S.a[vcur], S.sens, S.H,
-                                             S.grid, wts, S.lam);
+    if (S.grouping == 0)
+        S.f[fcur ^ 1][j] = voxel_update_value<0>(j, e, S.f[fcur], S.v[vcur], S.a[vcur], S.sens, S.H,
+                                                 S.grid, S.wts, S.lam);
+    else
+        S.f[fcur ^ 1][j] = voxel_update_value<1>(j, e, S.f[fcur], S.v[vcur], S.a[vcur], S.sens, S.H,
+                                                 S.grid, S.wts, S.lam);
 }
 
 // split and dual update, one segment of 2^seg_log2 lanes per spatial bin
@@ -45,11 +46,12 @@ __global__ __launch_bounds__(kBlock) void k_split_batch(const BatchBlock *__rest
     const int sl = S.seg_log2;
     const int64_t s = bb.start + (threadIdx.x >> sl);
     const int ls = threadIdx.x & ((1 << sl) - 1);
-    Weights wts;
-    wts.w[0] = wts.w[1] = wts.w[2] = wts.w[3] = 1.0f;
-    wts.full = nullptr;
-    split_bin<0>(s, s < S.grid.S, ls, sl, S.f[fcur], S.v[vcur], S.a[vcur], S.v[vcur ^ 1],
-                 S.a[vcur ^ 1], S.grid, wts, S.thr);
+    if (S.grouping == 0)
+        split_bin<0>(s, s < S.grid.S, ls, sl, S.f[fcur], S.v[vcur], S.a[vcur], S.v[vcur ^ 1],
+                     S.a[vcur ^ 1], S.grid, S.wts, S.thr);
+    else
+        split_bin<1>(s, s < S.grid.S, ls, sl, S.f[fcur], S.v[vcur], S.a[vcur], S.v[vcur ^ 1],
+                     S.a[vcur ^ 1], S.grid, S.wts, S.thr);
 }
 
 hipError_t launch_ratio_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,

@@ -74,8 +74,9 @@ struct ScanDev {
     float *f[2], *v[2], *a[2];
     const float *sens, *H;
     Grid grid;
+    Weights wts;
     int64_t I;
-    int ns_f, ns_b, seg_log2;
+    int ns_f, ns_b, seg_log2, grouping;
     float lam, thr;
 };
 

@@ -42,7 +42,21 @@ CONFIGS = {
                   beta=0.05, rho=1.0, iters=200, sweeps=1),
     "warmstart": dict(ny=64, nx=64, Q=64, I=131072, nnz_per_col=32, rects=(6, 16),
                       beta=0.1, rho=1.0, iters=300, sweeps=1),
+    # the shape of the paper's experiment (Section IV): a 205 mm x 13.5 mm region
+    # sampled every 5 mm along z (x here) and 1.5 mm along y, 54 momentum-transfer
+    # bins, a 128-pixel x 64-channel detector, about 26 detected photons per
+    # measurement; difference weights follow the voxel pitches
+    "teflon": dict(ny=9, nx=41, Q=54, I=8192, nnz_per_col=24, rects=2, beta=0.5, rho=1.0,
+                   iters=300, sweeps=1, mean_count=26.0, pitch=(5.0, 1.5)),
 }
+
+
+def direction_weights(pitch_x, pitch_y):
+    """Weights of the +x, -x, +y, -y differences for voxel pitches (any unit):
+    each difference is divided by its pitch, scaled so the finer direction has
+    weight one."""
+    fine = min(pitch_x, pitch_y)
+    return np.array([fine / pitch_x, fine / pitch_x, fine / pitch_y, fine / pitch_y], np.float32)
 
 
 @dataclass
@@ -147,12 +161,19 @@ def make_problem(cfg, seed: int) -> Problem:
         rects = int(rng.integers(rects[0], rects[1] + 1))
     x_true = make_phantom(rng, ny, nx, Q, int(rects))
     rowptr, col, val = make_system(rng, I, ny * nx * Q, int(c["nnz_per_col"]))
+    if c.get("mean_count"):
+        # scale the object so that the expected counts average mean_count (no draws)
+        A = sp.csr_matrix((val.astype(np.float64), col, rowptr), shape=(I, ny * nx * Q))
+        mean = float((A @ x_true.astype(np.float64)).mean())
+        if mean > 0:
+            x_true = (x_true.astype(np.float64) * ((c["mean_count"] - float(BACKGROUND)) / mean)).astype(np.float32)
     y, r = draw_counts(rng, rowptr, col, val, x_true, I)
     return Problem(ny=ny, nx=nx, Q=Q, I=I, rowptr=rowptr, col=col, val=val, y=y, r=r,
                    x_true=x_true, beta=float(c.get("beta", 0.1)), rho=float(c.get("rho", 1.0)),
                    iters=int(c.get("iters", 50)), sweeps=int(c.get("sweeps", 1)),
                    meta=dict(cfg=cfg if isinstance(cfg, str) else "custom", seed=seed,
-                             rects=int(rects)))
+                             rects=int(rects),
+                             weights=(direction_weights(*c["pitch"]) if c.get("pitch") else None)))
 
 
 def make_scan_for_system(rowptr, col, val, ny: int, nx: int, Q: int, I: int, seed: int,

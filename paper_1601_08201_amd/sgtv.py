@@ -88,8 +88,8 @@ def lib():
             "sgtv_set_graphs": (_I, [_P, _I]),
             "sgtv_batch_create": (_I, [ctypes.POINTER(_P), _I, _P]),
             "sgtv_batch_destroy": (None, [_P]),
-            "sgtv_batch_add_scan": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _P, _D, _D,
-                                         ctypes.POINTER(Schedule), _I, ctypes.POINTER(_I32)]),
+            "sgtv_batch_add_scan": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _I64, _P, _P,
+                                         _D, _D, _I, ctypes.POINTER(Schedule), _I, ctypes.POINTER(_I32)]),
             "sgtv_batch_size": (_I, [_P, ctypes.POINTER(_I32)]),
             "sgtv_batch_iterate": (_I, [_P, _I]),
             "sgtv_batch_iterate_sequential": (_I, [_P, _I]),
@@ -395,17 +395,20 @@ def sgtv_batch_destroy(b):
     lib().sgtv_batch_destroy(b)
 
 
-def sgtv_batch_add_scan(b, I, ny, nx, Q, row_ptr, col_idx, val, y, r, beta, rho, schedule=None):
+def sgtv_batch_add_scan(b, I, ny, nx, Q, row_ptr, col_idx, val, y, r, beta, rho, schedule=None,
+                        w=None, grouping=0):
     a = _arg(row_ptr, np.int64)
     c = _arg(col_idx, np.int32)
     v = _arg(val, np.float32)
     ya, ra = _arg(y, np.float32), _arg(r, np.float32)
-    mk = _kind(a, c, v, ya, ra)
+    wa = _arg(w, np.float32)
+    mk = _kind(a, c, v, ya, ra, wa)
+    wlen = 0 if w is None else int(np.prod(wa[2].shape))
     sch = ctypes.byref(Schedule(**{k: int(x) for k, x in schedule.items()})) if schedule else None
     idx = _I32()
     _check(lib().sgtv_batch_add_scan(b, int(I), int(ny), int(nx), int(Q), a[0], c[0], v[0],
-                                     int(c[2].shape[0]), ya[0], ra[0], float(beta), float(rho), sch, mk,
-                                     ctypes.byref(idx)))
+                                     int(c[2].shape[0]), wa[0], wlen, ya[0], ra[0], float(beta), float(rho),
+                                     int(grouping), sch, mk, ctypes.byref(idx)))
     return idx.value
 
 
@@ -454,9 +457,10 @@ class Batch:
         except Exception:
             pass
 
-    def add_scan(self, prob, schedule=None):
+    def add_scan(self, prob, schedule=None, w=None, grouping=0, beta=None):
         i = sgtv_batch_add_scan(self._b, prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col,
-                                prob.val, prob.y, prob.r, prob.beta, prob.rho, schedule)
+                                prob.val, prob.y, prob.r, prob.beta if beta is None else beta, prob.rho,
+                                schedule, w, grouping)
         self._J.append(prob.ny * prob.nx * prob.Q)
         return i
 
