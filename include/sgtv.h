@@ -283,6 +283,17 @@ int wsnet_set_params(wsnet net, const float *params, int64_t n, int mem_kind);
 int wsnet_get_params(wsnet net, float *params, int64_t n, int mem_kind);
 /* x0 = network(x_in) for `batch` images (FP32 NHWC in and out). */
 int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int mem_kind);
+/* Start images for the reconstruction (the learned warm start).  For each of
+ * `batch` images f (FP32 NHWC, J = height*width*channels values each: the
+ * image after a few plain iterations, or the normalised backprojection),
+ * m = mean(f) (FP64 sum; 1 where not positive) and s = network(f / m):
+ *   WSNET_START_RATIO:  x0 = c_out * s * f   (per-voxel correction factor)
+ *   WSNET_START_DIRECT: x0 = c_out * s * m   (the image itself)
+ * c_out is the scale the targets were divided by in training (> 0). */
+#define WSNET_START_RATIO 0
+#define WSNET_START_DIRECT 1
+int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out, float *x0,
+                int mem_kind);
 /* Loss and gradient of the mean squared error of network(x_in) against
  * target; the gradient stays in the network for wsnet_adam_step and is
  * copied to grad (n parameters) when grad is not NULL. */

@@ -1521,6 +1521,7 @@ struct wsnet_s {
     DBuf z_last, out, xin, tgt;                     // FP32
     DBuf dz[2];                                     // bf16 gradients w.r.t. pre-activations
     DBuf wpart, lpart, lred;
+    DBuf ipart, isum;                               // per-image FP64 sums (start images)
     int64_t step = 0;
     bool have_grad = false, have_params = false;
 };
@@ -1529,6 +1530,7 @@ namespace {
 
 constexpr int kWgradRows = 8;       // image rows per weight-gradient block
 constexpr int kLossBlocks = 1024;
+constexpr int kImageBlocks = 64;    // partial sums per image (start images)
 
 __bf16 *bf(const DBuf &b, int64_t off = 0) { return b.as<__bf16>() + off; }
 
@@ -1546,9 +1548,8 @@ int net_stage(wsnet_s *n, DBuf &dst, const float *src, int64_t count, int mk) {
     return SGTV_OK;
 }
 
-int net_forward(wsnet_s *n, int B) {
-    const int64_t cnt = B * n->img;
-    HIP_TRY(sgtv::wsn::to_bf16(n->xin.as<float>(), bf(n->acts), cnt, n->stream));
+// the layers, from the bf16 input already in the first activation buffer
+int net_layers(wsnet_s *n, int B) {
     const int64_t CK = static_cast<int64_t>(n->C) * 9 * n->C;
     for (int l = 0; l < n->L; ++l) {
         const float *bias = n->params.as<float>() + l * n->per_layer + CK;
@@ -1561,6 +1562,11 @@ int net_forward(wsnet_s *n, int B) {
                                              n->z_last.as<float>(), n->out.as<float>(), n->stream));
     }
     return SGTV_OK;
+}
+
+int net_forward(wsnet_s *n, int B) {
+    HIP_TRY(sgtv::wsn::to_bf16(n->xin.as<float>(), bf(n->acts), B * n->img, n->stream));
+    return net_layers(n, B);
 }
 
 int net_check(wsnet_s *n, int B, int mk) {
@@ -1616,6 +1622,8 @@ int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32
         HIP_TRY(n->wpart.alloc(sizeof(float) * (CK + channels) * max_batch * (height / kWgradRows)));
         HIP_TRY(n->lpart.alloc(sizeof(double) * kLossBlocks));
         HIP_TRY(n->lred.alloc(sizeof(double) * 4));
+        HIP_TRY(n->ipart.alloc(sizeof(double) * kImageBlocks * max_batch));
+        HIP_TRY(n->isum.alloc(sizeof(double) * max_batch));
         *out = n.release();
     } catch (const std::bad_alloc &) {
         return fail(SGTV_ENOMEM, "host allocation failed");
@@ -1670,6 +1678,29 @@ int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int me
     if (int e = net_stage(net, net->xin, x_in, cnt, mem_kind)) return e;
     if (int e = net_forward(net, batch)) return e;
     HIP_TRY(hipMemcpyAsync(x0, net->out.p, sizeof(float) * cnt, to_caller(mem_kind), net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return SGTV_OK;
+}
+
+int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out, float *x0,
+                int mem_kind) {
+    if (int e = net_check(net, batch, mem_kind)) return e;
+    if (!f || !x0) return fail(SGTV_EINVAL, "null argument");
+    if (mode != WSNET_START_RATIO && mode != WSNET_START_DIRECT) return fail(SGTV_EINVAL, "unknown start mode");
+    if (!(c_out > 0.0) || !std::isfinite(c_out)) return fail(SGTV_EINVAL, "c_out must be finite and > 0");
+    DeviceGuard g(net->device);
+    const int64_t cnt = batch * net->img;
+    if (int e = net_stage(net, net->xin, f, cnt, mem_kind)) return e;
+    HIP_TRY(sgtv::wsn::image_partials(net->xin.as<float>(), net->img, batch, kImageBlocks,
+                                      net->ipart.as<double>(), net->stream));
+    HIP_TRY(sgtv::launch_reduce(net->ipart.as<double>(), kImageBlocks, batch, net->isum.as<double>(), net->stream));
+    HIP_TRY(sgtv::wsn::scale_to_bf16(net->xin.as<float>(), net->isum.as<double>(), net->img, cnt, bf(net->acts),
+                                     net->stream));
+    if (int e = net_layers(net, batch)) return e;
+    HIP_TRY(sgtv::wsn::start_image(net->xin.as<float>(), net->out.as<float>(), net->isum.as<double>(), net->img,
+                                   cnt, static_cast<float>(c_out), mode == WSNET_START_RATIO,
+                                   net->tgt.as<float>(), net->stream));
+    HIP_TRY(hipMemcpyAsync(x0, net->tgt.p, sizeof(float) * cnt, to_caller(mem_kind), net->stream));
     HIP_TRY(hipStreamSynchronize(net->stream));
     return SGTV_OK;
 }

@@ -203,6 +203,42 @@ __global__ void k_to_bf16(const float *__restrict__ x, __bf16 *__restrict__ y, i
         y[i] = static_cast<__bf16>(x[i]);
 }
 
+// FP64 partial sums of each image: grid (n_blocks, images)
+__global__ __launch_bounds__(256) void k_image_partials(const float *__restrict__ x, int64_t img,
+                                                        double *__restrict__ partials) {
+    const float *xi = x + static_cast<int64_t>(blockIdx.y) * img;
+    double acc = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < img;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        acc += xi[i];
+    block_sum_store(acc, partials + static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x);
+}
+
+// mean of image b from its sum; 1 where the mean is not positive
+__device__ __forceinline__ double image_mean(const double *sums, int64_t b, int64_t img) {
+    const double m = sums[b] / static_cast<double>(img);
+    return m > 0.0 ? m : 1.0;
+}
+
+// network input: x / mean(image), rounded to bfloat16
+__global__ void k_scale_to_bf16(const float *__restrict__ x, const double *__restrict__ sums,
+                                int64_t img, int64_t n, __bf16 *__restrict__ y) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        y[i] = static_cast<__bf16>(static_cast<float>(x[i] / image_mean(sums, i / img, img)));
+}
+
+// start image from the network output s: c_out * s * f (ratio) or c_out * s * mean(f) (direct)
+__global__ void k_start_image(const float *__restrict__ f, const float *__restrict__ s,
+                              const double *__restrict__ sums, int64_t img, int64_t n, float c_out,
+                              int ratio, float *__restrict__ x0) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const float base = ratio ? f[i] : static_cast<float>(image_mean(sums, i / img, img));
+        x0[i] = c_out * s[i] * base;
+    }
+}
+
 // dZ of the last layer: 2 (out - target) / n * softplus'(z); FP64 loss partials
 __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ out,
                                                   const float *__restrict__ target,
@@ -300,6 +336,30 @@ hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, int W, in
 hipError_t to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_to_bf16, dim3(static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256))),
                        dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t image_partials(const float *x, int64_t img, int n_images, int n_blocks, double *partials,
+                          hipStream_t st) {
+    if (n_images == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_image_partials, dim3(static_cast<unsigned>(n_blocks), static_cast<unsigned>(n_images)),
+                       dim3(256), 0, st, x, img, partials);
+    return hipGetLastError();
+}
+
+hipError_t scale_to_bf16(const float *x, const double *sums, int64_t img, int64_t n, __bf16 *y,
+                         hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_to_bf16, dim3(static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256))),
+                       dim3(256), 0, st, x, sums, img, n, y);
+    return hipGetLastError();
+}
+
+hipError_t start_image(const float *f, const float *s, const double *sums, int64_t img, int64_t n,
+                       float c_out, int ratio, float *x0, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_start_image, dim3(static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256))),
+                       dim3(256), 0, st, f, s, sums, img, n, c_out, ratio, x0);
     return hipGetLastError();
 }
 

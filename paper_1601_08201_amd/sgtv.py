@@ -19,6 +19,7 @@ from .build import LIB_PATH
 SGTV_OK, SGTV_EINVAL, SGTV_ESHAPE, SGTV_ESTATE, SGTV_EDEVICE, SGTV_ENOMEM = 0, -1, -2, -3, -4, -5
 SGTV_F32, SGTV_BF16, SGTV_F16 = 0, 1, 2
 SGTV_HOST, SGTV_DEVICE = 0, 1
+WSNET_START_RATIO, WSNET_START_DIRECT = 0, 1
 SGTV_GROUP_SPECTRAL, SGTV_GROUP_STANDARD = 0, 1
 
 STORAGE = {"f32": SGTV_F32, "bf16": SGTV_BF16, "f16": SGTV_F16}
@@ -101,6 +102,7 @@ def lib():
             "wsnet_set_params": (_I, [_P, _P, _I64, _I]),
             "wsnet_get_params": (_I, [_P, _P, _I64, _I]),
             "wsnet_forward": (_I, [_P, _P, _I32, _P, _I]),
+            "wsnet_start": (_I, [_P, _P, _I32, _I, _D, _P, _I]),
             "wsnet_backward": (_I, [_P, _P, _P, _I32, ctypes.POINTER(_D), _P, _I]),
             "wsnet_adam_step": (_I, [_P, _D, _D, _D, _D]),
             "wsnet_reset_adam": (_I, [_P]),
@@ -519,6 +521,15 @@ def wsnet_forward(net, x_in, batch, out):
     return out
 
 
+def wsnet_start(net, f, batch, mode, c_out, out):
+    a = _arg(f, np.float32)
+    p, mk = _out_arg(out)
+    if mk != _kind(a):
+        raise ValueError("f and out must both be host arrays or both device tensors")
+    _check(lib().wsnet_start(net, a[0], int(batch), int(mode), float(c_out), p, mk))
+    return out
+
+
 def wsnet_backward(net, x_in, target, batch, grad=None):
     a, t = _arg(x_in, np.float32), _arg(target, np.float32)
     mk = _kind(a, t)
@@ -573,6 +584,15 @@ class WarmStartNet:
         if out is None:
             out = np.empty((b,) + self.shape, np.float32) if not _is_torch_cuda(x_in) else x_in.new_empty(x_in.shape)
         return wsnet_forward(self._n, x_in, b, out)
+
+    def start(self, f, mode="ratio", c_out=1.0, out=None):
+        """Start images x0 from images f (see wsnet_start): mode "ratio" gives
+        c_out * net(f / mean f) * f, "direct" c_out * net(f / mean f) * mean f."""
+        b = f.shape[0]
+        if out is None:
+            out = np.empty((b,) + self.shape, np.float32) if not _is_torch_cuda(f) else f.new_empty(f.shape)
+        m = {"ratio": WSNET_START_RATIO, "direct": WSNET_START_DIRECT}[mode]
+        return wsnet_start(self._n, f, b, m, c_out, out)
 
     def backward(self, x_in, target, grad=None):
         return wsnet_backward(self._n, x_in, target, x_in.shape[0], grad)

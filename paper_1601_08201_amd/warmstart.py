@@ -2,13 +2,19 @@
 
 A fixed scanner (one system matrix) sees many phantoms.  For each training
 phantom the plain method (uniform start, 300 ADMM iterations) gives the
-target image; the network learns to map the normalised backprojection
-A^T y / A^T 1 to that image.  At inference the network's output starts ADMM
-(d = c = 0) unless its objective is worse than the uniform start's, in which
-case the uniform start is used (fallback).
+target image.  The network sees an early image of the same run, scaled by
+its mean: by default the image f_k after k = 10 plain iterations, from which
+it predicts a per-voxel correction factor (start image x0 = f_k * factor,
+mode "ratio"); with k = 0 it sees the normalised backprojection A^T y / A^T 1
+and predicts the image itself (mode "direct").  ADMM then restarts from x0
+with the split and dual that make x0 consistent (sgtv_set_init_dual), unless
+x0's objective is worse than that of the uniform start, in which case the
+plain run continues unchanged (fallback).  (A start can converge faster than
+the plain image it came from while its objective is higher: the objective is
+only a guard against unusable network output.)
 
 Every reconstruction and network step runs in the library (sgtv / wsnet
-entry points); NumPy and torch only hold arrays.
+entry points); NumPy and torch hold arrays and prepare the training targets.
 """
 from __future__ import annotations
 
@@ -87,33 +93,55 @@ class Reconstruction:
         return self.R.backprojection()
 
 
-def make_dataset(scanner, seeds, iters=300, log=None, recon=None):
-    """(inputs, targets) as float32 [N, ny, nx, Q]: normalised backprojections
-    and plain reconstructions after `iters` iterations."""
+def make_dataset(scanner, seeds, iters=300, input_iters=(10,), log=None, recon=None):
+    """Network inputs and targets as float32 [N, ny, nx, Q]: for each k in
+    `input_iters` the plain image after k iterations (k = 0: the normalised
+    backprojection), and the plain image after `iters` iterations.  Returns
+    ({k: inputs}, targets, scans)."""
     scans = draw_scans(scanner, seeds)
     rc = recon or Reconstruction(scanner)
+    R = rc.R
     N = len(seeds)
     shp = (N, scanner.ny, scanner.nx, scanner.Q)
-    xin = np.empty(shp, np.float32)
+    ks = sorted(set(int(k) for k in input_iters))
+    if ks and ks[-1] > iters:
+        raise ValueError("input iterations exceed the target's")
+    xin = {k: np.empty(shp, np.float32) for k in ks}
     tgt = np.empty(shp, np.float32)
     t0 = time.time()
-    for k, (_, y, r) in enumerate(scans):
+    for n, (_, y, r) in enumerate(scans):
         rc.load(y, r)
-        xin[k] = rc.backprojection().reshape(shp[1:])
-        tgt[k] = rc.plain(iters).reshape(shp[1:])
-        if log and (k + 1) % 250 == 0:
-            log("dataset: %d / %d scans reconstructed (%.1fs)" % (k + 1, N, time.time() - t0))
+        R.set_init(None)
+        done = 0
+        for k in ks:
+            if k == 0:
+                xin[0][n] = R.backprojection().reshape(shp[1:])
+                continue
+            R.iterate(k - done)
+            done = k
+            xin[k][n] = R.image().reshape(shp[1:])
+        R.iterate(iters - done)
+        tgt[n] = R.image().reshape(shp[1:])
+        if log and (n + 1) % 250 == 0:
+            log("dataset: %d / %d scans reconstructed (%.1fs)" % (n + 1, N, time.time() - t0))
     return xin, tgt, scans
+
+
+RATIO_CLIP = 20.0      # training targets of the correction factor are clipped to [0, RATIO_CLIP]
+RATIO_EPS = 1e-3       # ... and computed as target / (input + RATIO_EPS * mean(input))
 
 
 @dataclass
 class Model:
-    """Trained parameters and the output scale: the network sees each input
-    image divided by its own mean m and its output is multiplied by c_out * m
-    (the counts, the backprojection and the image all scale with the object's
-    intensity, so the network only has to learn the shape)."""
+    """Trained parameters, the output scale c_out, the output mode and the
+    number of plain iterations whose image the network sees.  The network sees
+    each input image divided by its own mean m (counts, backprojection and
+    image all scale with the object's intensity, so only the shape is learned);
+    mode "ratio": x0 = c_out * net * f_k, mode "direct": x0 = c_out * net * m."""
     params: np.ndarray
     c_out: float
+    mode: str = "ratio"
+    input_iters: int = 10
     layers: int = 6
 
 
@@ -122,14 +150,30 @@ def image_means(x):
     return np.where(m > 0, m, np.float32(1.0))
 
 
-def train(xin, tgt, epochs=40, batch=32, lr=1e-3, lr_min=1e-5, seed=0, log=None, device=0):
-    """Adam on the mean squared error of the scaled images; cosine learning rate."""
+def training_targets(xin, tgt, mode):
+    """Scaled network targets and c_out for the given output mode."""
+    m = image_means(xin)[:, None, None, None]
+    if mode == "ratio":
+        t = np.clip(tgt / (xin + np.float32(RATIO_EPS) * m), 0.0, RATIO_CLIP).astype(np.float32)
+    elif mode == "direct":
+        t = (tgt / m).astype(np.float32)
+    else:
+        raise ValueError("mode must be 'ratio' or 'direct'")
+    c_out = float(t.mean())
+    t /= np.float32(c_out)
+    return t, c_out
+
+
+def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, lr_min=1e-5, seed=0,
+          log=None, device=0):
+    """Adam on the mean squared error of the scaled targets; cosine learning rate."""
     import torch
     dev = torch.device("cuda", device)
     m = image_means(xin)[:, None, None, None]
-    c_out = float((tgt / m).mean())
+    t, c_out = training_targets(xin, tgt, mode)
     X = torch.from_numpy(xin / m).to(dev)
-    T = torch.from_numpy(tgt / (m * np.float32(c_out))).to(dev)
+    T = torch.from_numpy(t).to(dev)
+    del t
     N = X.shape[0]
     H, W, C = X.shape[1:]
     net = sgtv.WarmStartNet(device=device, stream=torch.cuda.current_stream(dev).cuda_stream,
@@ -155,15 +199,45 @@ def train(xin, tgt, epochs=40, batch=32, lr=1e-3, lr_min=1e-5, seed=0, log=None,
         history.append(tot / max(N // batch, 1))
         if log and (ep + 1) % 5 == 0:
             log("train: epoch %d / %d, loss %.5f (%.1fs)" % (ep + 1, epochs, history[-1], time.time() - t0))
-    model = Model(net.params(), c_out)
+    model = Model(net.params(), c_out, mode, int(input_iters))
     return model, net, history
 
 
-def predict(net, model, xin):
-    """Start images for a batch of normalised backprojections (float32 NHWC)."""
-    m = image_means(xin)[:, None, None, None]
-    out = net.forward(np.ascontiguousarray(xin / m, np.float32))
-    return out * (m * np.float32(model.c_out))
+def predict(net, model, f):
+    """Start images for a batch of network inputs f (float32 NHWC, host array
+    or device tensor): the plain images after model.input_iters iterations, or
+    normalised backprojections."""
+    return net.start(f, model.mode, model.c_out)
+
+
+def warm_start(R, net, model, shape):
+    """Initialise reconstructor R (data set) from the network: plain start,
+    model.input_iters plain iterations (none: the backprojection is the input),
+    then the network's start image with a consistent split and dual, unless
+    its objective is worse than the uniform start's (fallback: the plain run
+    continues).  shape = (ny, nx, Q).  Returns (plain iterations spent,
+    fell back)."""
+    import torch
+    k = int(model.input_iters)
+    buf = torch.empty(int(np.prod(shape)), dtype=torch.float32, device="cuda")
+    R.set_init(None)
+    phi_ref = R.objective()["total"]
+    if k > 0:
+        R.iterate(k)
+        saved = R.state()
+        R.image(out=buf)
+    else:
+        R.backprojection(out=buf)
+    x0 = predict(net, model, buf.view(1, *shape))
+    R.set_init_dual(x0.view(-1))
+    phi = R.objective()["total"]
+    if math.isfinite(phi) and phi <= phi_ref:
+        return k, False
+    if k > 0:
+        R.set_state(*saved)
+    else:
+        R.set_init(None)
+    return k, True
 
 
 def iterations_to_target(R, phi_star, tol=1e-4, check=5, cap=3000):

@@ -153,3 +153,52 @@ def test_invalid_network_arguments(sg):
         N.forward(x)              # batch above max_batch
     with pytest.raises(sg.SgtvError):
         N.adam_step()             # no gradient yet
+
+
+@pytest.mark.parametrize("mode", ["ratio", "direct"])
+def test_start_images_against_fp64(sg, mode):
+    """wsnet_start: the network sees f / mean(f) and the start image is
+    c_out * s * f (ratio) or c_out * s * mean(f) (direct)."""
+    rng = np.random.default_rng(11)
+    f = rng.gamma(2.0, 1.5, size=(3, 8, 64, 64)).astype(np.float32)
+    f[1] *= np.float32(40.0)
+    f[2, :4] = 0.0
+    p = layer_params(sg, 1, 5)
+    N = sg.WarmStartNet(layers=1, height=8, max_batch=4).set_params(p)
+    c_out = 1.75
+    x0 = N.start(f, mode, c_out)
+    m = f.reshape(3, -1).astype(np.float64).mean(axis=1)[:, None, None, None]
+    xin = bf16((f.astype(np.float64) / m).astype(np.float32))
+    s = oracle.wn_forward(rounded_params(p, 1), xin, L=1)
+    ref = c_out * s * (f.astype(np.float64) if mode == "ratio" else m)
+    err = rel(x0, ref)
+    print("start", mode, "rel L2", err, flush=True)
+    assert err <= 1e-5
+    assert np.all(x0 >= 0)
+    # power-of-two scaling of an image is exact through the mean and the
+    # network input, so the start image scales bit for bit
+    x4 = N.start(np.float32(4.0) * f, mode, c_out)
+    np.testing.assert_array_equal(x4, np.float32(4.0) * x0)
+
+
+def test_start_image_of_zero_image(sg):
+    p = layer_params(sg, 1, 6)
+    N = sg.WarmStartNet(layers=1, height=8, max_batch=2).set_params(p)
+    z = np.zeros((1, 8, 64, 64), np.float32)
+    assert np.all(N.start(z, "ratio", 2.0) == 0.0)
+    s = N.forward(z)
+    np.testing.assert_allclose(N.start(z, "direct", 2.0), 2.0 * s, rtol=1e-6)
+
+
+def test_start_rejects_bad_arguments(sg):
+    p = layer_params(sg, 1, 7)
+    N = sg.WarmStartNet(layers=1, height=8, max_batch=2).set_params(p)
+    f = np.ones((1, 8, 64, 64), np.float32)
+    with pytest.raises(sg.SgtvError):
+        sg.wsnet_start(N._n, f, 1, 7, 1.0, np.empty_like(f))
+    with pytest.raises(sg.SgtvError):
+        N.start(f, "ratio", 0.0)
+    with pytest.raises(sg.SgtvError):
+        N.start(f, "ratio", float("nan"))
+    with pytest.raises(sg.SgtvError):
+        N.start(np.ones((3, 8, 64, 64), np.float32), "ratio", 1.0)
