@@ -121,15 +121,10 @@ def batch_main(args):
     stream = torch.cuda.current_stream()
     B = sgtv.Batch(stream=stream.cuda_stream)
     t0 = time.time()
-    tuned = 0
-    scheds = []
-    for p in probs:
-        sch = autotune.cached_schedule(p)
-        tuned += sch is not None
-        scheds.append(sch)
+    sched = autotune.batch_schedule([(p.I, p.J) for p in probs])
     with cf.ThreadPoolExecutor(8) as ex:
-        list(ex.map(lambda ps: B.add_scan(ps[0], ps[1]), zip(probs, scheds)))
-    log("batch built in %.1fs (%d scans with tuned schedules)" % (time.time() - t0, tuned))
+        list(ex.map(lambda p: B.add_scan(p, sched), probs))
+    log("batch built in %.1fs (schedule %s)" % (time.time() - t0, sched))
     B.iterate(args.warmup)
     torch.cuda.synchronize()
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -381,7 +376,7 @@ def main():
                     help="scan: the paper-scale scan (default); batch: 64 uneven scans; "
                          "warmstart: learned start vs plain start; sweep: beta sweep of both "
                          "regularisers on the paper-shaped scan in one batch")
-    ap.add_argument("--betas", default="0.05,0.1,0.2,0.5,1,2,5,10")
+    ap.add_argument("--betas", default="0.01,0.02,0.05,0.1,0.2,0.5,1,2")
     ap.add_argument("--train-scans", type=int, default=2000)
     ap.add_argument("--eval-scans", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=40)

@@ -63,6 +63,30 @@ def candidates(I, J, waves=16, per_side=10):
     return side(I, J), side(J, I)
 
 
+def _auto_slabs(n_cols):
+    """Slab count of the automatic schedule (slab of the gathered vector <= 2 MiB)."""
+    cb = min(16384, max(4, 1 << (max(n_cols, 4) - 1).bit_length()))
+    n_cb = -(-n_cols // cb)
+    want = 1 << max(0, (-(-(n_cols * 4) // 2 ** 21) - 1).bit_length())
+    return max(1, min(want, 8, n_cb))
+
+
+def batch_schedule(sizes, waves=16, min_tiles=1024):
+    """One schedule for every scan of a batch, sizes = [(I, J), ...]: the
+    largest rows per wave (up to 1024) whose forward and back tiles over the
+    whole batch still number at least min_tiles.  A single scan must fill the
+    GPU by itself and so takes short tiles; in a batch the scans fill it
+    together, and longer tiles stage each gathered block for more entries."""
+    rw = 1024
+    while rw > 64:
+        tf = sum(-(-I // (waves * rw)) * _auto_slabs(J) for I, J in sizes)
+        tb = sum(-(-J // (waves * rw)) * _auto_slabs(I) for I, J in sizes)
+        if min(tf, tb) >= min_tiles:
+            break
+        rw //= 2
+    return dict(fwd_rows_per_wave=rw, back_rows_per_wave=rw)
+
+
 def _time_schedule(prob, sched, reps):
     R = sgtv.Reconstructor()
     R.set_schedule(format=0, **sched)

@@ -1,0 +1,34 @@
+"""Host-side schedule rules (no GPU): candidate ranking limits, the slab rule
+and the batch rule."""
+from paper_1601_08201_amd import autotune
+
+
+def test_candidates_fit_lds_and_slabs():
+    fwd, back = autotune.candidates(1 << 20, 1 << 21)
+    assert fwd and back
+    for rw, cb, ns in fwd + back:
+        assert autotune.lds_bytes(16, rw, cb) <= autotune.MAX_LDS
+        assert ns in (1, 2, 4, 8)
+
+
+def test_auto_slabs_keep_slab_at_most_2mib():
+    for n in (1, 100, 4096, 1 << 19, (1 << 19) + 1, 1 << 21, 3 << 20, 1 << 22, 10 ** 8):
+        ns = autotune._auto_slabs(n)
+        assert 1 <= ns <= 8 and ns & (ns - 1) == 0
+        if ns < 8:
+            assert n * 4 / ns <= 2 ** 21 or -(-n // 16384) == ns
+
+
+def test_batch_schedule_prefers_long_tiles_for_big_batches():
+    big = [(ny * nx * q // 2, ny * nx * q) for ny, nx, q in [(128, 128, 128)] * 32 + [(64, 64, 96)] * 32]
+    assert autotune.batch_schedule(big) == dict(fwd_rows_per_wave=1024, back_rows_per_wave=1024)
+    # a handful of tiny scans cannot fill the GPU with long tiles
+    tiny = [(8192, 19926)] * 16
+    assert autotune.batch_schedule(tiny) == dict(fwd_rows_per_wave=64, back_rows_per_wave=64)
+    # in between, the tile count over the batch decides
+    mid = [(1 << 18, 1 << 19)] * 8
+    s = autotune.batch_schedule(mid, min_tiles=256)
+    rw = s["fwd_rows_per_wave"]
+    tiles = lambda r: sum(-(-I // (16 * r)) * autotune._auto_slabs(J) for I, J in mid)
+    assert tiles(rw) >= 256 and (rw == 1024 or tiles(2 * rw) < 256 or
+                                 sum(-(-J // (32 * rw)) * autotune._auto_slabs(I) for I, J in mid) < 256)
