@@ -1521,6 +1521,7 @@ struct wsnet_s {
     DBuf z_last, out, xin, tgt;                     // FP32
     DBuf dz[2];                                     // bf16 gradients w.r.t. pre-activations
     DBuf wpart, lpart, lred;
+    DBuf xt, dt, bpart;                             // weight-gradient scratch
     DBuf ipart, isum;                               // per-image FP64 sums (start images)
     int64_t step = 0;
     bool have_grad = false, have_params = false;
@@ -1528,7 +1529,6 @@ struct wsnet_s {
 
 namespace {
 
-constexpr int kWgradRows = 8;       // image rows per weight-gradient block
 constexpr int kLossBlocks = 1024;
 constexpr int kImageBlocks = 64;    // partial sums per image (start images)
 
@@ -1589,7 +1589,7 @@ int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32
     if (!out) return fail(SGTV_EINVAL, "out is NULL");
     if (channels != 64) return fail(SGTV_ESHAPE, "channels must be 64");
     if (width != 64) return fail(SGTV_ESHAPE, "width must be 64");
-    if (height < 2 || height % kWgradRows != 0) return fail(SGTV_ESHAPE, "height must be a positive multiple of 8");
+    if (height < 2 || height % 2 != 0) return fail(SGTV_ESHAPE, "height must be even and at least 2");
     if (layers < 1 || layers > 16) return fail(SGTV_EINVAL, "layers must be in [1, 16]");
     if (max_batch < 1 || max_batch > 4096) return fail(SGTV_EINVAL, "max_batch must be in [1, 4096]");
     int nd = 0;
@@ -1619,7 +1619,10 @@ int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32
         HIP_TRY(n->tgt.alloc(sizeof(float) * big));
         HIP_TRY(n->dz[0].alloc(2 * big));
         HIP_TRY(n->dz[1].alloc(2 * big));
-        HIP_TRY(n->wpart.alloc(sizeof(float) * (CK + channels) * max_batch * (height / kWgradRows)));
+        HIP_TRY(n->wpart.alloc(sizeof(float) * CK * max_batch * (height / sgtv::wsn::wgrad_rows(height))));
+        HIP_TRY(n->xt.alloc(2 * 3 * big));
+        HIP_TRY(n->dt.alloc(2 * big));
+        HIP_TRY(n->bpart.alloc(sizeof(float) * channels * max_batch * height));
         HIP_TRY(n->lpart.alloc(sizeof(double) * kLossBlocks));
         HIP_TRY(n->lred.alloc(sizeof(double) * 4));
         HIP_TRY(n->ipart.alloc(sizeof(double) * kImageBlocks * max_batch));
@@ -1721,9 +1724,9 @@ int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t ba
     HIP_TRY(sgtv::launch_reduce(net->lpart.as<double>(), kLossBlocks, 1, net->lred.as<double>(), net->stream));
     for (int l = net->L - 1; l >= 0; --l) {
         const __bf16 *X = bf(net->acts, l * net->max_batch * net->img);
-        HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, net->W, kWgradRows,
-                                      net->wpart.as<float>(), net->grad.as<float>() + l * net->per_layer,
-                                      net->stream));
+        HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, net->xt.as<float>(),
+                                      net->dt.as<float>(), net->wpart.as<float>(), net->bpart.as<float>(),
+                                      net->grad.as<float>() + l * net->per_layer, net->stream));
         if (l == 0) break;
         HIP_TRY(sgtv::wsn::conv_masked(bf(net->dz[cur]), bf(net->wb, l * CK), batch, net->H, net->W, X,
                                        bf(net->dz[cur ^ 1]), net->stream));

@@ -10,7 +10,6 @@ namespace sgtv {
 namespace wsn {
 
 size_t conv_lds_bytes(int W);
-size_t wgrad_lds_bytes();
 
 hipError_t conv_relu(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H, int W,
                      __bf16 *out, hipStream_t st);
@@ -18,8 +17,13 @@ hipError_t conv_softplus(const __bf16 *X, const __bf16 *Wk, const float *bias, i
                          int W, float *z, float *sp, hipStream_t st);
 hipError_t conv_masked(const __bf16 *X, const __bf16 *Wk, int B, int H, int W, const __bf16 *mask,
                        __bf16 *out, hipStream_t st);
-hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, int W, int rows_per_block,
-                      float *part, float *grad, hipStream_t st);
+// image rows per weight-gradient block (divides H; H even)
+int wgrad_rows(int H);
+// weight and bias gradient of one layer into grad (C*9*C weights, then C biases);
+// xt: 3*B*H*W*C bf16, dt: B*H*W*C bf16, wpart: (B*H / wgrad_rows(H)) * C*9*C floats,
+// bpart: B*H*C floats (all scratch)
+hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt, float *dt,
+                      float *wpart, float *bpart, float *grad, hipStream_t st);
 hipError_t to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);
 // per-image FP64 partial sums (n_blocks per image, image-major)
 hipError_t image_partials(const float *x, int64_t img, int n_images, int n_blocks, double *partials,

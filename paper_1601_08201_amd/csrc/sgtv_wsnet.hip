@@ -115,86 +115,134 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ X,
             }
 }
 
-// Weight and bias gradient of one layer over `rows_per_block` image rows:
-// dW[co][tap][ci] = sum_pixels dZ[pixel][co] X[pixel + tap][ci], as a GEMM
-// with the pixels as reduction; both operands are staged transposed in LDS so
-// that eight consecutive pixels of one channel are one 16-byte read.  Eight
-// waves: wave w owns output channels 16 (w % 4).. and half of the 36 column
-// tiles of (tap, ci).  Each block writes its partial sums; a second kernel adds
-// the blocks in a fixed order.
-constexpr int kRowPad = 64 + 8;        // bf16 per staged channel row (64 pixels + pad)
+// Weight and bias gradient of one layer: dW[co][tap][ci] = sum over pixels of
+// dZ[pixel][co] X[pixel + tap][ci], a GEMM with the pixels as reduction.  The
+// matrix cores want eight consecutive pixels of one channel per lane, so both
+// operands are first rewritten channel-major per image row (dZ once, X in
+// three copies shifted by kx - 1 pixels, zero outside the row); the product
+// kernel then loads every fragment with one aligned 16-byte read.
 
-size_t wgrad_lds_bytes() {
-    return (static_cast<size_t>(kC) * kRowPad + static_cast<size_t>(9) * kC * kRowPad) * 2;
-}
+constexpr int kTPad = kC + 8;          // bf16 per channel row of the staged tile
 
-__global__ __launch_bounds__(512) void k_conv_wgrad(const __bf16 *__restrict__ X,
-                                                    const __bf16 *__restrict__ DZ, int H, int W,
-                                                    int rows_per_block, float *__restrict__ part) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *dzT = reinterpret_cast<__bf16 *>(smem);              // [co][pix]
-    __bf16 *xT = dzT + static_cast<size_t>(kC) * kRowPad;        // [tap][ci][pix]
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int blocks_per_img = H / rows_per_block;
-    const int n = blockIdx.x / blocks_per_img, yb = (blockIdx.x % blocks_per_img) * rows_per_block;
-    const int li = lane & 15, lk = (lane >> 4) * 8;
-    const int u = wv & 3, half = wv >> 2;
-    f32x4 acc[18];
+// One block (256 threads) per image row r = n * H + y: out[(r * shifts + k)][c][x]
+// = in[r][x + k - (shifts == 3)][c]; with bsum, the row's per-channel sums of the
+// (bfloat16) input into bsum[r][c].
+__global__ __launch_bounds__(256) void k_rows_cmajor(const __bf16 *__restrict__ in, int shifts,
+                                                     __bf16 *__restrict__ out, float *__restrict__ bsum) {
+    __shared__ __attribute__((aligned(16))) __bf16 tile[kC * kTPad];   // [c][x]
+    const int64_t r = blockIdx.x;
+    const __bf16 *src = in + r * kC * kC;                              // width = channels = 64
+    for (int i = threadIdx.x; i < kC * kC / 8; i += 256) {
+        const int x = i >> 3, c0 = (i & 7) * 8;
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(src + x * kC + c0);
 #pragma unroll
-    for (int k = 0; k < 18; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    float bsum = 0.0f;
-    for (int yy = 0; yy < rows_per_block; ++yy) {
-        const int y = yb + yy;
-        __syncthreads();
-        // dZ row, transposed: dzT[co][x]
-        for (int i = tid; i < W * kC; i += 512) {
-            const int co = i % kC, x = i / kC;
-            dzT[co * kRowPad + x] = DZ[((static_cast<size_t>(n) * H + y) * W + x) * kC + co];
-        }
-        // inputs of every tap, transposed: xT[tap][ci][x] = X[y + ky - 1][x + kx - 1][ci]
-        for (int i = tid; i < 9 * W * kC; i += 512) {
-            const int ci = i % kC, rest = i / kC;
-            const int x = rest % W, tap = rest / W;
-            const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
-            __bf16 v = static_cast<__bf16>(0.0f);
-            if (sy >= 0 && sy < H && sx >= 0 && sx < W)
-                v = X[((static_cast<size_t>(n) * H + sy) * W + sx) * kC + ci];
-            xT[(tap * kC + ci) * kRowPad + x] = v;
-        }
-        __syncthreads();
-        if (tid < kC)
-            for (int x = 0; x < W; ++x) bsum += static_cast<float>(dzT[tid * kRowPad + x]);
-        for (int p0 = 0; p0 < W; p0 += 32) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(dzT + (16 * u + li) * kRowPad + p0 + lk);
+        for (int j = 0; j < 8; ++j) tile[(c0 + j) * kTPad + x] = v[j];
+    }
+    __syncthreads();
+    if (bsum && threadIdx.x < kC) {
+        float acc = 0.0f;
+        for (int x = 0; x < kC; ++x) acc += static_cast<float>(tile[threadIdx.x * kTPad + x]);
+        bsum[r * kC + threadIdx.x] = acc;
+    }
+    const int off = shifts == 3 ? 1 : 0;
+    for (int k = 0; k < shifts; ++k) {
+        __bf16 *dst = out + (r * shifts + k) * kC * kC;
+        for (int i = threadIdx.x; i < kC * kC / 8; i += 256) {
+            const int c = i >> 3, x0 = (i & 7) * 8;
+            bf16x8 v;
 #pragma unroll
-            for (int k = 0; k < 18; ++k) {
-                const int nt = half * 18 + k;          // column tile: tap = nt / 4, ci0 = 16 (nt % 4)
-                const int col = nt * 16 + li;          // = tap * 64 + ci
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(xT + col * kRowPad + p0 + lk);
-                acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+            for (int j = 0; j < 8; ++j) {
+                const int x = x0 + j + k - off;
+                v[j] = (x >= 0 && x < kC) ? tile[c * kTPad + x] : static_cast<__bf16>(0.0f);
             }
+            *reinterpret_cast<bf16x8 *>(dst + c * kC + x0) = v;
         }
     }
-    float *out = part + static_cast<size_t>(blockIdx.x) * (kC * kK + kC);
-#pragma unroll
-    for (int k = 0; k < 18; ++k)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = 16 * u + (lane >> 4) * 4 + r;
-            const int col = (half * 18 + k) * 16 + li;
-            out[co * kK + col] = acc[k][r];
-        }
-    if (tid < kC) out[kC * kK + tid] = bsum;
 }
 
-// grad[k] = sum over blocks b of part[b][k], fixed order
+// Partial dW over R image rows (block b: rows b R .. b R + R - 1 of one image);
+// wave t = tap (ky, kx) accumulates all 64 x 64 (co, ci) outputs of its tap as
+// 4 x 4 tiles of v_mfma_f32_16x16x32_bf16.  DT = dZ channel-major [row][co][x],
+// XT = X channel-major with the three shifts [row][kx][ci][x].
+__global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ DT,
+                                                    const __bf16 *__restrict__ XT, int H, int R,
+                                                    float *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ky = t / 3, kx = t % 3;
+    const int li = lane & 15, g = lane >> 4, lk = g * 8;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
+    const int64_t n = row0 / H;
+    const int y0 = static_cast<int>(row0 - n * H);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int yy = 0; yy < R; ++yy) {
+        const int y = y0 + yy, sy = y + ky - 1;
+        if (sy < 0 || sy >= H) continue;
+        const __bf16 *drow = DT + (n * H + y) * kC * kC;
+        const __bf16 *xrow = XT + ((n * H + sy) * 3 + kx) * kC * kC;
+#pragma unroll
+        for (int p0 = 0; p0 < kC; p0 += 32) {
+            bf16x8 a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(drow + (16 * i + li) * kC + p0 + lk);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(xrow + (16 * j + li) * kC + p0 + lk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    float *out = part + static_cast<int64_t>(blockIdx.x) * kC * kK;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                out[(16 * i + 4 * g + q) * kK + t * kC + 16 * j + li] = acc[i][j][q];
+}
+
+// grad[k] = sum over blocks b of part[b][k] in a fixed order: four contiguous
+// quarters of the blocks summed in order, then ((q0 + q1) + (q2 + q3)).
 __global__ __launch_bounds__(256) void k_block_sum(const float *__restrict__ part, int n_blocks,
                                                    int64_t len, float *__restrict__ grad) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (k >= len) return;
-    float s = 0.0f;
-    for (int b = 0; b < n_blocks; ++b) s += part[static_cast<int64_t>(b) * len + k];
-    grad[k] = s;
+    __shared__ float s4[4][64];
+    const int kl = threadIdx.x & 63, qt = threadIdx.x >> 6;
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * 64 + kl;
+    const int per = (n_blocks + 3) / 4;
+    const int b0 = qt * per, b1 = min(n_blocks, b0 + per);
+    float acc = 0.0f;
+    if (k < len)
+        for (int b = b0; b < b1; ++b) acc += part[static_cast<int64_t>(b) * len + k];
+    s4[qt][kl] = acc;
+    __syncthreads();
+    if (qt == 0 && k < len) grad[k] = (s4[0][kl] + s4[1][kl]) + (s4[2][kl] + s4[3][kl]);
+}
+
+// bias gradient: grad[c] = sum over rows r of part[r][c] (64 channels), 16
+// contiguous segments of rows summed in order, then combined pairwise in a
+// fixed tree
+__global__ __launch_bounds__(1024) void k_bias_sum(const float *__restrict__ part, int n_rows,
+                                                   float *__restrict__ grad) {
+    __shared__ float s16[16][64];
+    const int c = threadIdx.x & 63, sg = threadIdx.x >> 6;
+    const int per = (n_rows + 15) / 16;
+    const int r0 = sg * per, r1 = min(n_rows, r0 + per);
+    float acc = 0.0f;
+    for (int r = r0; r < r1; ++r) acc += part[static_cast<int64_t>(r) * kC + c];
+    s16[sg][c] = acc;
+    __syncthreads();
+    for (int w = 8; w >= 1; w >>= 1) {
+        if (sg < w) s16[sg][c] = s16[sg][c] + s16[sg + w][c];
+        __syncthreads();
+    }
+    if (sg == 0) grad[c] = s16[0][c];
 }
 
 __global__ void k_to_bf16(const float *__restrict__ x, __bf16 *__restrict__ y, int64_t n) {
@@ -313,23 +361,29 @@ hipError_t conv_masked(const __bf16 *X, const __bf16 *Wk, int B, int H, int W, c
     return conv_t<2>(X, Wk, nullptr, B, H, W, out, nullptr, nullptr, mask, st);
 }
 
-hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, int W, int rows_per_block,
-                      float *part, float *grad, hipStream_t st) {
-    static bool raised = false;
-    if (!raised) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv_wgrad),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        if (e != hipSuccess) return e;
-        raised = true;
-    }
-    const int nb = B * (H / rows_per_block);
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(static_cast<unsigned>(nb)), dim3(512), wgrad_lds_bytes(),
-                       st, X, DZ, H, W, rows_per_block, part);
+int wgrad_rows(int H) { return H % 8 == 0 ? 8 : (H % 4 == 0 ? 4 : 2); }
+
+hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt, float *dt,
+                      float *wpart, float *bpart, float *grad, hipStream_t st) {
+    const int rows = B * H;
+    if (rows == 0) return hipSuccess;
+    __bf16 *XT = reinterpret_cast<__bf16 *>(xt);
+    __bf16 *DT = reinterpret_cast<__bf16 *>(dt);
+    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, DZ, 1, DT, bpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t len = static_cast<int64_t>(kC) * kK + kC;
-    hipLaunchKernelGGL(k_block_sum, dim3(static_cast<unsigned>((len + 255) / 256)), dim3(256), 0, st,
-                       part, nb, len, grad);
+    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, X, 3, XT,
+                       static_cast<float *>(nullptr));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int R = wgrad_rows(H);
+    const int nb = rows / R;
+    hipLaunchKernelGGL(k_wgrad_taps, dim3(static_cast<unsigned>(nb)), dim3(576), 0, st, DT, XT, H, R, wpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t len = static_cast<int64_t>(kC) * kK;
+    hipLaunchKernelGGL(k_block_sum, dim3(static_cast<unsigned>((len + 63) / 64)), dim3(256), 0, st,
+                       wpart, nb, len, grad);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bias_sum, dim3(1), dim3(1024), 0, st, bpart, rows, grad + len);
     return hipGetLastError();
 }
 

@@ -64,10 +64,11 @@ def test_one_layer_forward_tight(sg):
     assert err <= 1e-5
 
 
-def test_one_layer_gradient(sg):
-    x, t = data(2)
+@pytest.mark.parametrize("H", [8, 6, 12])
+def test_one_layer_gradient(sg, H):
+    x, t = data(2, H=H)
     p = layer_params(sg, 1, 4)
-    N = sg.WarmStartNet(layers=1, height=8, max_batch=4).set_params(p)
+    N = sg.WarmStartNet(layers=1, height=H, max_batch=4).set_params(p)
     g = np.empty(p.size, np.float32)
     loss = N.backward(x, t, g)
     loss_o, g_o = oracle.wn_loss_grad(rounded_params(p, 1), bf16(x), t, L=1)
@@ -144,6 +145,8 @@ def test_invalid_network_arguments(sg):
         sg.WarmStartNet(channels=32)
     with pytest.raises(sg.SgtvError):
         sg.WarmStartNet(width=32)
+    with pytest.raises(sg.SgtvError):
+        sg.WarmStartNet(height=7)
     N = sg.WarmStartNet(layers=2, height=8, max_batch=2)
     x, t = data(7, B=3)
     with pytest.raises(sg.SgtvError):
