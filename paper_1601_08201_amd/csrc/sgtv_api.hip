@@ -1521,7 +1521,7 @@ struct wsnet_s {
     DBuf z_last, out, xin, tgt;                     // FP32
     DBuf dz[2];                                     // bf16 gradients w.r.t. pre-activations
     DBuf wpart, lpart, lred;
-    DBuf xt, dt, bpart;                             // weight-gradient scratch
+    DBuf xt, dt;                                    // weight-gradient scratch
     DBuf ipart, isum;                               // per-image FP64 sums (start images)
     int64_t step = 0;
     bool have_grad = false, have_params = false;
@@ -1619,10 +1619,9 @@ int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32
         HIP_TRY(n->tgt.alloc(sizeof(float) * big));
         HIP_TRY(n->dz[0].alloc(2 * big));
         HIP_TRY(n->dz[1].alloc(2 * big));
-        HIP_TRY(n->wpart.alloc(sizeof(float) * CK * max_batch * (height / sgtv::wsn::wgrad_rows(height))));
+        HIP_TRY(n->wpart.alloc(sizeof(float) * (CK + channels) * max_batch * (height / sgtv::wsn::wgrad_rows(height))));
         HIP_TRY(n->xt.alloc(2 * 3 * big));
         HIP_TRY(n->dt.alloc(2 * big));
-        HIP_TRY(n->bpart.alloc(sizeof(float) * channels * max_batch * height));
         HIP_TRY(n->lpart.alloc(sizeof(double) * kLossBlocks));
         HIP_TRY(n->lred.alloc(sizeof(double) * 4));
         HIP_TRY(n->ipart.alloc(sizeof(double) * kImageBlocks * max_batch));
@@ -1725,7 +1724,7 @@ int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t ba
     for (int l = net->L - 1; l >= 0; --l) {
         const __bf16 *X = bf(net->acts, l * net->max_batch * net->img);
         HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, net->xt.as<float>(),
-                                      net->dt.as<float>(), net->wpart.as<float>(), net->bpart.as<float>(),
+                                      net->dt.as<float>(), net->wpart.as<float>(),
                                       net->grad.as<float>() + l * net->per_layer, net->stream));
         if (l == 0) break;
         HIP_TRY(sgtv::wsn::conv_masked(bf(net->dz[cur]), bf(net->wb, l * CK), batch, net->H, net->W, X,

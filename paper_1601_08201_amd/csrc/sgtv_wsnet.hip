@@ -4,10 +4,12 @@
 // voxel order of the reconstruction); weights are [co][ky][kx][ci].
 //
 // Convolution as implicit GEMM: output pixels x output channels, reduction
-// over (tap, input channel), K = 9 * 64 = 576.  One workgroup computes two
-// image rows (128 pixels) x 64 channels from LDS copies of the 4 input rows
-// it needs and of all weights; a wave owns 32 pixels x 64 channels, i.e. 2 x 4
-// tiles of v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+8],
+// over (tap, input channel), K = 9 * 64 = 576.  Persistent workgroups of four
+// waves stage all weights in LDS once and then walk over steps of four image
+// rows: the six input rows a step needs are staged in LDS (the next step's
+// rows are loaded into registers while the current step computes), and wave w
+// computes row w of the step, 64 pixels x 64 channels, as 4 x 4 tiles of
+// v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+8],
 // B[8(l/16)..+8][l%16], D[4(l/16)..+4][l%16]).
 #include "sgtv_device.h"
 #include "sgtv_wsnet.h"
@@ -29,8 +31,14 @@ __device__ __forceinline__ float sigmoidf(float z) {
     return z >= 0.0f ? 1.0f / (1.0f + expf(-z)) : expf(z) / (1.0f + expf(z));
 }
 
-size_t conv_lds_bytes(int W) {
-    return (static_cast<size_t>(4) * (W + 2) * kPixPad + static_cast<size_t>(kC) * kWPad) * 2;
+constexpr int kStepRows = 4;                       // output rows per step (one per wave)
+constexpr int kStageRows = kStepRows + 2;          // input rows a step reads
+constexpr int kRowPix = kC + 2;                    // staged pixels per row (width 64 + halo)
+constexpr int kStageChunks = kStageRows * kRowPix * (kC / 8);   // 16-byte chunks per step
+constexpr int kChunksPerThread = (kStageChunks + 255) / 256;
+
+size_t conv_lds_bytes(int) {
+    return (static_cast<size_t>(kStageRows) * kRowPix * kPixPad + static_cast<size_t>(kC) * kWPad) * 2;
 }
 
 // EP_RELU: out_bf16 = relu(z + b) (hidden layer); EP_SOFTPLUS: out_z = z + b,
@@ -39,80 +47,104 @@ size_t conv_lds_bytes(int W) {
 template <int EP>
 __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ X,
                                                  const __bf16 *__restrict__ Wk,
-                                                 const float *__restrict__ bias, int H, int W,
+                                                 const float *__restrict__ bias, int B, int H,
                                                  __bf16 *__restrict__ out_bf16,
                                                  float *__restrict__ out_z,
                                                  float *__restrict__ out_sp,
                                                  const __bf16 *__restrict__ mask) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *xs = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *ws = xs + static_cast<size_t>(4) * (W + 2) * kPixPad;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int rows = H / 2;
-    const int n = blockIdx.x / rows, y0 = (blockIdx.x % rows) * 2;
+    __bf16 *ws = reinterpret_cast<__bf16 *>(smem);                  // [co][tap * 64 + ci]
+    __bf16 *xs = ws + static_cast<size_t>(kC) * kWPad;              // [row][pixel + 1][ci]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int steps_per_img = (H + kStepRows - 1) / kStepRows;
+    const int n_steps = B * steps_per_img;
 
     for (int i = tid; i < kC * kK / 8; i += 256) {
         const int co = i / (kK / 8), k8 = i % (kK / 8);
         *reinterpret_cast<u16x8 *>(ws + co * kWPad + k8 * 8) =
             *reinterpret_cast<const u16x8 *>(Wk + static_cast<size_t>(co) * kK + k8 * 8);
     }
-    for (int i = tid; i < 4 * (W + 2) * (kC / 8); i += 256) {
-        const int c8 = i % (kC / 8), rest = i / (kC / 8);
-        const int xc = rest % (W + 2), r = rest / (W + 2);
-        const int sy = y0 - 1 + r, sx = xc - 1;
-        u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (sy >= 0 && sy < H && sx >= 0 && sx < W)
-            v = *reinterpret_cast<const u16x8 *>(X + ((static_cast<size_t>(n) * H + sy) * W + sx) * kC + c8 * 8);
-        *reinterpret_cast<u16x8 *>(xs + (r * (W + 2) + xc) * kPixPad + c8 * 8) = v;
-    }
-    __syncthreads();
 
-    const int rr = wv >> 1, xb = (wv & 1) * 32;
+    u16x8 pre[kChunksPerThread];
+    auto load_rows = [&](int step) {
+        const int n = step / steps_per_img, y0 = (step % steps_per_img) * kStepRows;
+#pragma unroll
+        for (int k = 0; k < kChunksPerThread; ++k) {
+            const int i = tid + k * 256;
+            const int c8 = i % (kC / 8), rest = i / (kC / 8);
+            const int xc = rest % kRowPix, r = rest / kRowPix;
+            const int sy = y0 - 1 + r, sx = xc - 1;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (i < kStageChunks && sy >= 0 && sy < H && sx >= 0 && sx < kC)
+                v = *reinterpret_cast<const u16x8 *>(X + ((static_cast<size_t>(n) * H + sy) * kC + sx) * kC + c8 * 8);
+            pre[k] = v;
+        }
+    };
+
     const int li = lane & 15, lk = (lane >> 4) * 8;
-    f32x4 acc[2][4];
+    int step = blockIdx.x;
+    if (step < n_steps) load_rows(step);
+    for (; step < n_steps; step += gridDim.x) {
+        __syncthreads();                               // every wave is done with the staged rows
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int ky = tap / 3, kx = tap % 3;
-#pragma unroll
-        for (int c0 = 0; c0 < kC; c0 += 32) {
-            bf16x8 a[2], b[4];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int px = xb + 16 * t + li;
-                a[t] = *reinterpret_cast<const bf16x8 *>(xs + ((rr + ky) * (W + 2) + px + kx) * kPixPad + c0 + lk);
+        for (int k = 0; k < kChunksPerThread; ++k) {
+            const int i = tid + k * 256;
+            if (i < kStageChunks) {
+                const int c8 = i % (kC / 8), rest = i / (kC / 8);
+                *reinterpret_cast<u16x8 *>(xs + rest * kPixPad + c8 * 8) = pre[k];
             }
+        }
+        __syncthreads();
+        if (step + static_cast<int>(gridDim.x) < n_steps) load_rows(step + gridDim.x);
+
+        const int n = step / steps_per_img;
+        const int y = (step % steps_per_img) * kStepRows + wv;
+        if (y >= H) continue;                          // last step of an image with H % 4 == 2
+        f32x4 acc[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                b[u] = *reinterpret_cast<const bf16x8 *>(ws + (16 * u + li) * kWPad + tap * kC + c0 + lk);
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int u = 0; u < 4; ++u) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = tap / 3, kx = tap % 3;
+            const __bf16 *xrow = xs + ((wv + ky) * kRowPix + kx) * kPixPad;
+#pragma unroll
+            for (int c0 = 0; c0 < kC; c0 += 32) {
+                bf16x8 a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    a[t] = *reinterpret_cast<const bf16x8 *>(xrow + (16 * t + li) * kPixPad + c0 + lk);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[u], acc[t][u], 0, 0, 0);
-        }
-    }
-    const int y = y0 + rr;
+                    b[u] = *reinterpret_cast<const bf16x8 *>(ws + (16 * u + li) * kWPad + tap * kC + c0 + lk);
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int px = xb + 16 * t + (lane >> 4) * 4 + r;
-                const int co = 16 * u + li;
-                const size_t o = ((static_cast<size_t>(n) * H + y) * W + px) * kC + co;
-                float z = acc[t][u][r];
-                if (EP != 2) z += bias[co];
-                if (EP == 0) out_bf16[o] = static_cast<__bf16>(fmaxf(z, 0.0f));
-                if (EP == 1) {
-                    out_z[o] = z;
-                    out_sp[o] = softplusf(z);
-                }
-                if (EP == 2) out_bf16[o] = static_cast<float>(mask[o]) > 0.0f ? static_cast<__bf16>(z) : static_cast<__bf16>(0.0f);
+                    for (int u = 0; u < 4; ++u)
+                        acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[u], acc[t][u], 0, 0, 0);
             }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int px = 16 * t + (lane >> 4) * 4 + r;
+                    const int co = 16 * u + li;
+                    const size_t o = ((static_cast<size_t>(n) * H + y) * kC + px) * kC + co;
+                    float z = acc[t][u][r];
+                    if (EP != 2) z += bias[co];
+                    if (EP == 0) out_bf16[o] = static_cast<__bf16>(fmaxf(z, 0.0f));
+                    if (EP == 1) {
+                        out_z[o] = z;
+                        out_sp[o] = softplusf(z);
+                    }
+                    if (EP == 2)
+                        out_bf16[o] = static_cast<float>(mask[o]) > 0.0f ? static_cast<__bf16>(z) : static_cast<__bf16>(0.0f);
+                }
+    }
 }
 
 // Weight and bias gradient of one layer: dW[co][tap][ci] = sum over pixels of
@@ -125,10 +157,9 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ X,
 constexpr int kTPad = kC + 8;          // bf16 per channel row of the staged tile
 
 // One block (256 threads) per image row r = n * H + y: out[(r * shifts + k)][c][x]
-// = in[r][x + k - (shifts == 3)][c]; with bsum, the row's per-channel sums of the
-// (bfloat16) input into bsum[r][c].
+// = in[r][x + k - (shifts == 3)][c].
 __global__ __launch_bounds__(256) void k_rows_cmajor(const __bf16 *__restrict__ in, int shifts,
-                                                     __bf16 *__restrict__ out, float *__restrict__ bsum) {
+                                                     __bf16 *__restrict__ out) {
     __shared__ __attribute__((aligned(16))) __bf16 tile[kC * kTPad];   // [c][x]
     const int64_t r = blockIdx.x;
     const __bf16 *src = in + r * kC * kC;                              // width = channels = 64
@@ -139,11 +170,6 @@ __global__ __launch_bounds__(256) void k_rows_cmajor(const __bf16 *__restrict__ 
         for (int j = 0; j < 8; ++j) tile[(c0 + j) * kTPad + x] = v[j];
     }
     __syncthreads();
-    if (bsum && threadIdx.x < kC) {
-        float acc = 0.0f;
-        for (int x = 0; x < kC; ++x) acc += static_cast<float>(tile[threadIdx.x * kTPad + x]);
-        bsum[r * kC + threadIdx.x] = acc;
-    }
     const int off = shifts == 3 ? 1 : 0;
     for (int k = 0; k < shifts; ++k) {
         __bf16 *dst = out + (r * shifts + k) * kC * kC;
@@ -163,7 +189,9 @@ __global__ __launch_bounds__(256) void k_rows_cmajor(const __bf16 *__restrict__ 
 // Partial dW over R image rows (block b: rows b R .. b R + R - 1 of one image);
 // wave t = tap (ky, kx) accumulates all 64 x 64 (co, ci) outputs of its tap as
 // 4 x 4 tiles of v_mfma_f32_16x16x32_bf16.  DT = dZ channel-major [row][co][x],
-// XT = X channel-major with the three shifts [row][kx][ci][x].
+// XT = X channel-major with the three shifts [row][kx][ci][x].  The wave of the
+// centre tap (which reads every row) also sums its dZ fragments: the block's
+// bias partials follow its weight partials.  Row stride of part: C*9*C + C.
 __global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ DT,
                                                     const __bf16 *__restrict__ XT, int H, int R,
                                                     float *__restrict__ part) {
@@ -179,6 +207,7 @@ __global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ D
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int yy = 0; yy < R; ++yy) {
         const int y = y0 + yy, sy = y + ky - 1;
         if (sy < 0 || sy >= H) continue;
@@ -196,9 +225,25 @@ __global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ D
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (t == 4) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) bs[i] += static_cast<float>(a[i][e]);
+            }
         }
     }
-    float *out = part + static_cast<int64_t>(blockIdx.x) * kC * kK;
+    float *out = part + static_cast<int64_t>(blockIdx.x) * (kC * kK + kC);
+    if (t == 4) {
+        // lanes li, li + 16, li + 32, li + 48 hold pixel quarters of channel 16 i + li
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float v = bs[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (g == 0) out[kC * kK + 16 * i + li] = v;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -223,26 +268,6 @@ __global__ __launch_bounds__(256) void k_block_sum(const float *__restrict__ par
     s4[qt][kl] = acc;
     __syncthreads();
     if (qt == 0 && k < len) grad[k] = (s4[0][kl] + s4[1][kl]) + (s4[2][kl] + s4[3][kl]);
-}
-
-// bias gradient: grad[c] = sum over rows r of part[r][c] (64 channels), 16
-// contiguous segments of rows summed in order, then combined pairwise in a
-// fixed tree
-__global__ __launch_bounds__(1024) void k_bias_sum(const float *__restrict__ part, int n_rows,
-                                                   float *__restrict__ grad) {
-    __shared__ float s16[16][64];
-    const int c = threadIdx.x & 63, sg = threadIdx.x >> 6;
-    const int per = (n_rows + 15) / 16;
-    const int r0 = sg * per, r1 = min(n_rows, r0 + per);
-    float acc = 0.0f;
-    for (int r = r0; r < r1; ++r) acc += part[static_cast<int64_t>(r) * kC + c];
-    s16[sg][c] = acc;
-    __syncthreads();
-    for (int w = 8; w >= 1; w >>= 1) {
-        if (sg < w) s16[sg][c] = s16[sg][c] + s16[sg + w][c];
-        __syncthreads();
-    }
-    if (sg == 0) grad[c] = s16[0][c];
 }
 
 __global__ void k_to_bf16(const float *__restrict__ x, __bf16 *__restrict__ y, int64_t n) {
@@ -331,6 +356,19 @@ __global__ void k_weights_bf16(const float *__restrict__ w, __bf16 *__restrict__
 }
 
 // ---------------------------------------------------------------- launchers
+int conv_workgroups() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            n = cus;
+        else
+            n = 256;
+    }
+    return n;
+}
+
 template <int EP>
 static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
                          int W, __bf16 *ob, float *oz, float *osp, const __bf16 *mask,
@@ -343,8 +381,12 @@ static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, i
         if (e != hipSuccess) return e;
         raised = true;
     }
-    hipLaunchKernelGGL((k_conv3x3<EP>), dim3(static_cast<unsigned>(B * (H / 2))), dim3(256), lds,
-                       st, X, Wk, bias, H, W, ob, oz, osp, mask);
+    const int n_steps = B * ((H + kStepRows - 1) / kStepRows);
+    if (n_steps == 0) return hipSuccess;
+    // one workgroup per CU (the staged weights and rows take 129 KB of LDS)
+    const int grid = std::min(n_steps, conv_workgroups());
+    hipLaunchKernelGGL((k_conv3x3<EP>), dim3(static_cast<unsigned>(grid)), dim3(256), lds, st, X, Wk,
+                       bias, B, H, ob, oz, osp, mask);
     return hipGetLastError();
 }
 
@@ -364,26 +406,23 @@ hipError_t conv_masked(const __bf16 *X, const __bf16 *Wk, int B, int H, int W, c
 int wgrad_rows(int H) { return H % 8 == 0 ? 8 : (H % 4 == 0 ? 4 : 2); }
 
 hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt, float *dt,
-                      float *wpart, float *bpart, float *grad, hipStream_t st) {
+                      float *wpart, float *grad, hipStream_t st) {
     const int rows = B * H;
     if (rows == 0) return hipSuccess;
     __bf16 *XT = reinterpret_cast<__bf16 *>(xt);
     __bf16 *DT = reinterpret_cast<__bf16 *>(dt);
-    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, DZ, 1, DT, bpart);
+    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, DZ, 1, DT);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, X, 3, XT,
-                       static_cast<float *>(nullptr));
+    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, X, 3, XT);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int R = wgrad_rows(H);
     const int nb = rows / R;
     hipLaunchKernelGGL(k_wgrad_taps, dim3(static_cast<unsigned>(nb)), dim3(576), 0, st, DT, XT, H, R, wpart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t len = static_cast<int64_t>(kC) * kK;
+    const int64_t len = static_cast<int64_t>(kC) * kK + kC;
     hipLaunchKernelGGL(k_block_sum, dim3(static_cast<unsigned>((len + 63) / 64)), dim3(256), 0, st,
                        wpart, nb, len, grad);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bias_sum, dim3(1), dim3(1024), 0, st, bpart, rows, grad + len);
     return hipGetLastError();
 }
 
