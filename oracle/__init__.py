@@ -69,6 +69,8 @@ def _declare(lib):
         "or_data_term": (_D, [_I64, _P, _P]),
         "or_admm_flat": (_I, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _D, _I, _I, _I,
                               _P, _P, _P, _P]),
+        "or_admm_adaptive_flat": (_I, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _D, _I, _I, _I, _I,
+                                       _D, _D, _D, _D, _P, _P, _P, _P, _I, _P, _P, _P]),
         "or_objective_flat": (None, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
         "or_image_sweep_flat": (None, [_I64, _I, _I, _I, _P, _P, _P, _P, _P, _P, _D, _P, _P]),
         "or_plain_init_flat": (_D, [_I64, _I, _I, _I, _P, _P, _P, _P]),
@@ -263,6 +265,34 @@ def admm(prob, n_iter, f0=None, d0=None, c0=None, sweeps=None, beta=None, lam=No
     if st != 0:
         raise MemoryError("oracle allocation failed")
     return f, d, cc, (rep[:n_iter] if report else None)
+
+
+def admm_adaptive(prob, max_iter, check=10, eps_abs=1e-4, eps_rel=1e-3, mu=10.0, tau=2.0,
+                  f0=None, d0=None, c0=None, sweeps=None, beta=None, lam=None, w=None, grouping=0):
+    """ADMM with residual balancing and the residual stopping rule (Boyd et al.
+    2011, Sections 3.3, 3.4.1).  Returns (f, d, c, lam, hist, iterations,
+    converged), hist[m] = (iterations, r, s, eps_pri, eps_dual, lam after check m)."""
+    lib = _load()
+    J = prob.ny * prob.nx * prob.Q
+    rp, c, v = _csr(prob.rowptr, prob.col, prob.val)
+    y, r = _f64(prob.y), _f64(prob.r)
+    ww = _weights(w, prob.ny, prob.nx, prob.Q)
+    f = _f64(f0).copy() if f0 is not None else np.full(J, plain_init(prob), np.float64)
+    d = _f64(d0).copy() if d0 is not None else np.zeros(J * NDIR, np.float64)
+    cc = _f64(c0).copy() if c0 is not None else np.zeros(J * NDIR, np.float64)
+    max_checks = max_iter // max(check, 1) + 2
+    hist = np.zeros((max_checks, 6), np.float64)
+    n_checks, lam_out, conv = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+    k = lib.or_admm_adaptive_flat(prob.I, prob.ny, prob.nx, prob.Q, _ptr(rp), _ptr(c), _ptr(v),
+                                  _ptr(y), _ptr(r), _ptr(ww), float(prob.beta if beta is None else beta),
+                                  float(prob.rho if lam is None else lam), int(grouping), int(max_iter),
+                                  int(prob.sweeps if sweeps is None else sweeps), int(check), float(eps_abs),
+                                  float(eps_rel), float(mu), float(tau), _ptr(f), _ptr(d), _ptr(cc),
+                                  _ptr(hist), max_checks, ctypes.byref(n_checks), ctypes.byref(lam_out),
+                                  ctypes.byref(conv))
+    if k < 0:
+        raise MemoryError("oracle allocation failed")
+    return f, d, cc, lam_out.value, hist[:n_checks.value], k, bool(conv.value)
 
 
 # ---- warm-start network (NHWC images, weights [co][ky][kx][ci]) ---------------------------

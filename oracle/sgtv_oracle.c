@@ -352,6 +352,92 @@ int or_admm(const or_problem *P, int n_iter, int sweeps, double *f, double *d, d
     return 0;
 }
 
+/*
+ * ADMM with the penalty adapted by residual balancing and stopped by the
+ * primal/dual residual rule (Boyd et al., Distributed Optimization and
+ * Statistical Learning via ADMM, 2011: Sections 3.3 and 3.4.1), written for
+ * the constraint d = w.*G f of Eq. 3 and the scaled dual c of Eq. 6.
+ * Iterations run in chunks of `check` (the last one may be shorter); after
+ * each chunk, with r and s the primal and dual residuals of its last
+ * iteration (as in or_admm's report),
+ *   eps_pri  = sqrt(4J) eps_abs + eps_rel max(||w.*Gf||, ||d||)
+ *   eps_dual = sqrt(J)  eps_abs + eps_rel lam ||(w.*G)^T c||
+ * the run stops when r <= eps_pri and s <= eps_dual; otherwise
+ *   r > mu s:  lam <- tau lam, c <- c / tau
+ *   s > mu r:  lam <- lam / tau, c <- c tau
+ * (the unscaled dual lam c is unchanged; the curvature follows lam).
+ * At most max_iter iterations; returns the number done, -1 on allocation
+ * failure.  hist[6m .. 6m+5] for check m: iterations done, r, s, eps_pri,
+ * eps_dual, lam after the check; *n_checks = number of checks, *lam_out =
+ * final lam, *converged = 1 when the rule stopped the run.
+ */
+int or_admm_adaptive(const or_problem *P0, int max_iter, int sweeps, int check, double eps_abs,
+                     double eps_rel, double mu, double tau, double *f, double *d, double *c,
+                     double *hist, int max_checks, int *n_checks, double *lam_out, int *converged)
+{
+    or_problem P = *P0;
+    int64_t J = n_vox(&P), JN = J * NDIR;
+    double *g = malloc(sizeof(double) * (JN > 0 ? JN : 1));
+    double *t = malloc(sizeof(double) * (J > 0 ? J : 1));
+    double rep[5];
+    int k = 0, m = 0;
+    *converged = 0;
+    if (!g || !t)
+        return -1;
+    while (k < max_iter) {
+        int n = max_iter - k < check ? max_iter - k : check;
+        if (n > 1 && or_admm(&P, n - 1, sweeps, f, d, c, NULL) != 0)
+            return -1;
+        if (or_admm(&P, 1, sweeps, f, d, c, rep) != 0)
+            return -1;
+        k += n;
+        double r = rep[3], sd = rep[4];
+        double ngf = 0.0, nd = 0.0, ntc = 0.0;
+        or_diff(P.ny, P.nx, P.Q, P.w, f, g);
+        for (int64_t i = 0; i < JN; ++i) {
+            ngf += g[i] * g[i];
+            nd += d[i] * d[i];
+        }
+        or_diff_adj(P.ny, P.nx, P.Q, P.w, c, t);
+        for (int64_t j = 0; j < J; ++j)
+            ntc += t[j] * t[j];
+        double eps_pri = sqrt((double)JN) * eps_abs + eps_rel * fmax(sqrt(ngf), sqrt(nd));
+        double eps_dual = sqrt((double)J) * eps_abs + eps_rel * P.lam * sqrt(ntc);
+        int stop = r <= eps_pri && sd <= eps_dual;
+        if (!stop) {
+            double scale = 1.0;
+            if (r > mu * sd) {
+                P.lam *= tau;
+                scale = 1.0 / tau;
+            } else if (sd > mu * r) {
+                P.lam /= tau;
+                scale = tau;
+            }
+            if (scale != 1.0)
+                for (int64_t i = 0; i < JN; ++i)
+                    c[i] *= scale;
+        }
+        if (m < max_checks && hist) {
+            hist[6 * m + 0] = k;
+            hist[6 * m + 1] = r;
+            hist[6 * m + 2] = sd;
+            hist[6 * m + 3] = eps_pri;
+            hist[6 * m + 4] = eps_dual;
+            hist[6 * m + 5] = P.lam;
+        }
+        ++m;
+        if (stop) {
+            *converged = 1;
+            break;
+        }
+    }
+    *n_checks = m;
+    *lam_out = P.lam;
+    free(g);
+    free(t);
+    return k;
+}
+
 /* Flat-argument entry points for ctypes. */
 static or_problem make_problem(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
                                const int32_t *col, const double *val, const double *y,
@@ -373,6 +459,18 @@ int or_admm_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr, const 
 {
     or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, r, w, beta, lam, grouping);
     return or_admm(&P, n_iter, sweeps, f, d, c, report);
+}
+
+int or_admm_adaptive_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
+                          const int32_t *col, const double *val, const double *y, const double *r,
+                          const double *w, double beta, double lam, int grouping, int max_iter,
+                          int sweeps, int check, double eps_abs, double eps_rel, double mu, double tau,
+                          double *f, double *d, double *c, double *hist, int max_checks,
+                          int *n_checks, double *lam_out, int *converged)
+{
+    or_problem P = make_problem(I, ny, nx, Q, rowptr, col, val, y, r, w, beta, lam, grouping);
+    return or_admm_adaptive(&P, max_iter, sweeps, check, eps_abs, eps_rel, mu, tau, f, d, c, hist,
+                            max_checks, n_checks, lam_out, converged);
 }
 
 void or_objective_flat(int64_t I, int ny, int nx, int Q, const int64_t *rowptr,
