@@ -170,6 +170,45 @@ int sgtv_get_state(sgtv_ctx ctx, float *f, float *v, float *a, int64_t *k, int m
 int sgtv_set_state(sgtv_ctx ctx, const float *f, const float *v, const float *a, int64_t k,
                    int mem_kind);
 
+/*
+ * Penalty adaptation and stopping (Boyd, Parikh, Chu, Peleato, Eckstein,
+ * Distributed Optimization and Statistical Learning via ADMM, 2011:
+ * Sections 3.3 and 3.4.1), for the constraint d = w.*G f of Eq. 3.
+ *
+ * sgtv_set_penalty changes the penalty rho (lambda of Eq. 4) of the running
+ * iteration: the scaled dual c is rescaled so that rho * c is unchanged, d and
+ * f are kept, and the curvature and shrink threshold follow rho.
+ *
+ * sgtv_iterate_adaptive iterates in chunks of opt->check (the last may be
+ * shorter, at most max_iters in all); after each chunk, with r and s the
+ * primal and dual residuals of its last iteration (as sgtv_objective),
+ *   eps_pri  = sqrt(4 J) eps_abs + eps_rel max(||w.*G f||, ||d||)
+ *   eps_dual = sqrt(J)   eps_abs + eps_rel rho ||(w.*G)^T c||
+ * it stops when r <= eps_pri and s <= eps_dual; otherwise rho <- tau rho when
+ * r > mu s, rho <- rho / tau when s > mu r (tau = 1: fixed rho; eps = 0: no
+ * stopping).  checks[m] (up to max_checks) records check m; n_checks,
+ * iters_done and converged (1 when the rule stopped the run) may be NULL.
+ */
+typedef struct {
+    int32_t check;     /* iterations between checks, >= 1                          */
+    double eps_abs;    /* absolute tolerance, >= 0                                 */
+    double eps_rel;    /* relative tolerance, >= 0                                 */
+    double mu;         /* residual ratio that triggers a change, >= 1              */
+    double tau;        /* factor of a change, >= 1                                 */
+} sgtv_adaptive;
+
+typedef struct {
+    int64_t iter;      /* iterations of this call done at the check                */
+    double r_primal, r_dual, eps_primal, eps_dual;
+    double rho;        /* penalty after the check                                  */
+} sgtv_check;
+
+int sgtv_set_penalty(sgtv_ctx ctx, double rho);
+int sgtv_get_penalty(sgtv_ctx ctx, double *rho);
+int sgtv_iterate_adaptive(sgtv_ctx ctx, int64_t max_iters, const sgtv_adaptive *opt,
+                          sgtv_check *checks, int32_t max_checks, int32_t *n_checks,
+                          int64_t *iters_done, int *converged);
+
 /* Normalised backprojection x_in = (A^T y) / (A^T 1) (0 where A^T 1 = 0),
  * J floats, of the data currently set. */
 int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);

@@ -661,7 +661,7 @@ int ensure_partials(sgtv_ctx_s *c) {
     int sl = 0;
     while ((1 << sl) < S.Q && sl < 6) ++sl;
     const int64_t n2 = (S.S + (256 >> sl) - 1) / (256 >> sl);
-    const int64_t need = std::max<int64_t>({n1, 3 * n2, 4096, 16});
+    const int64_t need = std::max<int64_t>({n1, 6 * n2, 4096, 16});
     if (need > c->part_cap) {
         HIP_TRY(c->part.alloc(sizeof(double) * need));
         c->part_cap = need;
@@ -1018,6 +1018,28 @@ int sgtv_set_graphs(sgtv_ctx ctx, int enable) {
     return SGTV_OK;
 }
 
+namespace {
+
+// Reduced report terms of the current state: h = [R(w.*Gf), ||w.*Gf - d||^2,
+// ||(w.*G)^T (d - d_prev)||^2, ||w.*Gf||^2, ||d||^2, ||(w.*G)^T c||^2] (FP64).
+int report_terms(sgtv_ctx ctx, double *dev_out, double h[6]) {
+    const System &S = *ctx->sys;
+    double *part = ctx->part.as<double>();
+    int64_t n2 = 0;
+    HIP_TRY(sgtv::launch_report(ctx->f[ctx->fcur].as<float>(), ctx->v[ctx->vcur].as<float>(),
+                                ctx->a[ctx->vcur].as<float>(), ctx->v[ctx->vcur ^ 1].as<float>(),
+                                ctx->a[ctx->vcur ^ 1].as<float>(), S.grid, S.weights(),
+                                ctx->grouping, part, ctx->stream, &n2));
+    HIP_TRY(sgtv::launch_reduce(part, n2, 6, dev_out, ctx->stream));
+    if (h) {
+        HIP_TRY(hipMemcpyAsync(h, dev_out, sizeof(double) * 6, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    return SGTV_OK;
+}
+
+}  // namespace
+
 int sgtv_objective(sgtv_ctx ctx, sgtv_report *out) {
     if (int e = check_ready(ctx)) return e;
     if (!out) return fail(SGTV_EINVAL, "out is NULL");
@@ -1025,7 +1047,7 @@ int sgtv_objective(sgtv_ctx ctx, sgtv_report *out) {
     const System &S = *ctx->sys;
     double *part = ctx->part.as<double>();
     double *red = ctx->red.as<double>();
-    int64_t n1 = 0, n2 = 0;
+    int64_t n1 = 0;
     const float *x = S.vt == SGTV_F32 ? ctx->f[ctx->fcur].as<float>() : ctx->fs.as<float>();
     if (S.format == SGTV_FORMAT_TILED) {
         HIP_TRY(sgtv::launch_tiled(S.fwd.map, S.vt, x, S.fpart.as<float>(), ctx->stream));
@@ -1037,11 +1059,7 @@ int sgtv_objective(sgtv_ctx ctx, sgtv_report *out) {
                                            ctx->ratio.as<float>(), part, true, ctx->stream, &n1));
     }
     HIP_TRY(sgtv::launch_reduce(part, n1, 1, red, ctx->stream));
-    HIP_TRY(sgtv::launch_report(ctx->f[ctx->fcur].as<float>(), ctx->v[ctx->vcur].as<float>(),
-                                ctx->a[ctx->vcur].as<float>(), ctx->v[ctx->vcur ^ 1].as<float>(),
-                                ctx->a[ctx->vcur ^ 1].as<float>(), S.grid, S.weights(),
-                                ctx->grouping, part, ctx->stream, &n2));
-    HIP_TRY(sgtv::launch_reduce(part, n2, 3, red + 1, ctx->stream));
+    if (int e = report_terms(ctx, red + 1, nullptr)) return e;
     double h[4];
     HIP_TRY(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -1051,6 +1069,75 @@ int sgtv_objective(sgtv_ctx ctx, sgtv_report *out) {
     out->r_primal = std::sqrt(h[2]);
     out->r_dual = ctx->rho * std::sqrt(h[3]);
     out->iter = ctx->k;
+    return SGTV_OK;
+}
+
+int sgtv_set_penalty(sgtv_ctx ctx, double rho) {
+    if (int e = check_ready(ctx)) return e;
+    if (!(std::isfinite(rho) && rho > 0.0)) return fail(SGTV_EINVAL, "rho must be finite and > 0");
+    if (rho == ctx->rho) return SGTV_OK;
+    DeviceGuard g(ctx->device);
+    const float t = static_cast<float>(ctx->rho / rho);
+    HIP_TRY(sgtv::launch_rescale_dual(ctx->v[ctx->vcur].as<float>(), ctx->a[ctx->vcur].as<float>(),
+                                      ctx->sys->grid, ctx->grouping, t, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    drop_graphs(ctx);
+    ctx->rho = rho;
+    return SGTV_OK;
+}
+
+int sgtv_get_penalty(sgtv_ctx ctx, double *rho) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (!rho) return fail(SGTV_EINVAL, "rho is NULL");
+    *rho = ctx->rho;
+    return SGTV_OK;
+}
+
+int sgtv_iterate_adaptive(sgtv_ctx ctx, int64_t max_iters, const sgtv_adaptive *opt,
+                          sgtv_check *checks, int32_t max_checks, int32_t *n_checks,
+                          int64_t *iters_done, int *converged) {
+    if (int e = check_ready(ctx)) return e;
+    if (!opt) return fail(SGTV_EINVAL, "opt is NULL");
+    if (max_iters < 0) return fail(SGTV_EINVAL, "max_iters must be >= 0");
+    if (opt->check < 1) return fail(SGTV_EINVAL, "check must be >= 1");
+    if (!(opt->eps_abs >= 0.0 && opt->eps_rel >= 0.0 && std::isfinite(opt->eps_abs) && std::isfinite(opt->eps_rel)))
+        return fail(SGTV_EINVAL, "eps_abs and eps_rel must be finite and >= 0");
+    if (!(opt->mu >= 1.0 && std::isfinite(opt->mu)) || !(opt->tau >= 1.0 && std::isfinite(opt->tau)))
+        return fail(SGTV_EINVAL, "mu and tau must be finite and >= 1");
+    if (max_checks < 0 || (max_checks > 0 && !checks)) return fail(SGTV_EINVAL, "checks is NULL");
+    DeviceGuard g(ctx->device);
+    const System &S = *ctx->sys;
+    const double sq_p = std::sqrt(4.0 * static_cast<double>(S.J));
+    const double sq_n = std::sqrt(static_cast<double>(S.J));
+    int64_t k = 0;
+    int32_t m = 0;
+    int conv = 0;
+    while (k < max_iters) {
+        const int n = static_cast<int>(std::min<int64_t>(opt->check, max_iters - k));
+        if (int e = sgtv_iterate(ctx, n)) return e;
+        k += n;
+        double h[6];
+        if (int e = report_terms(ctx, ctx->red.as<double>() + 8, h)) return e;
+        const double r = std::sqrt(h[1]), sd = ctx->rho * std::sqrt(h[2]);
+        const double eps_pri = sq_p * opt->eps_abs + opt->eps_rel * std::max(std::sqrt(h[3]), std::sqrt(h[4]));
+        const double eps_dual = sq_n * opt->eps_abs + opt->eps_rel * ctx->rho * std::sqrt(h[5]);
+        const bool stop = r <= eps_pri && sd <= eps_dual;
+        if (!stop) {
+            double rho = ctx->rho;
+            if (r > opt->mu * sd) rho *= opt->tau;
+            else if (sd > opt->mu * r) rho /= opt->tau;
+            if (int e = sgtv_set_penalty(ctx, rho)) return e;
+        }
+        if (m < max_checks) checks[m] = sgtv_check{k, r, sd, eps_pri, eps_dual, ctx->rho};
+        ++m;
+        if (stop) {
+            conv = 1;
+            break;
+        }
+    }
+    if (n_checks) *n_checks = m;
+    if (iters_done) *iters_done = k;
+    if (converged) *converged = conv;
     return SGTV_OK;
 }
 

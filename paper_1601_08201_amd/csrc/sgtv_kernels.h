@@ -123,6 +123,9 @@ hipError_t launch_consistent_split(const float *f, float *v, float *a, const Gri
 hipError_t launch_report(const float *f, const float *v, const float *a, const float *v_prev,
                          const float *a_prev, const Grid &grid, const Weights &w, int grouping,
                          double *partials, hipStream_t st, int64_t *n_blocks);
+// lam -> lam / t with lam c unchanged: c <- t c on the state (v, a), d kept
+hipError_t launch_rescale_dual(float *v, float *a, const Grid &grid, int grouping, float t,
+                               hipStream_t st);
 hipError_t launch_reduce(const double *partials, int64_t n, int n_quant, double *out,
                          hipStream_t st);
 hipError_t launch_sum_f32(const float *a, int64_t n, double *partials, hipStream_t st,

@@ -149,7 +149,9 @@ __global__ __launch_bounds__(kBlock) void k_consistent_split(const float *__rest
 
 // ---------------------------------------------------------------- report
 // FP64 partials per block: [0] R(w.*G f), [1] ||w.*G f - d||^2,
-// [2] ||(w.*G)^T (d - d_prev)||^2 with d = a v, d_prev = a_prev v_prev.
+// [2] ||(w.*G)^T (d - d_prev)||^2 with d = a v, d_prev = a_prev v_prev,
+// [3] ||w.*G f||^2, [4] ||d||^2, [5] ||(w.*G)^T c||^2 with c = v - d (the
+// norms of the residual stopping rule).
 template <int GROUPING>
 __global__ __launch_bounds__(kBlock) void k_report(
     const float *__restrict__ f, const float *__restrict__ v, const float *__restrict__ a,
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_report(
     const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock >> seg_log2) + (threadIdx.x >> seg_log2);
     const int ls = threadIdx.x & (G - 1);
     const int Q = grid.Q;
-    double tv = 0.0, grp = 0.0, rp = 0.0, rd = 0.0;
+    double tv = 0.0, grp = 0.0, rp = 0.0, rd = 0.0, gf2 = 0.0, d2 = 0.0, tc2 = 0.0;
     if (s < grid.S) {
         const int iy = static_cast<int>(s / grid.nx), ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
         int64_t nb[4];
@@ -169,29 +171,36 @@ __global__ __launch_bounds__(kBlock) void k_report(
             const float fs = f[s * Q + q];
             const float as = GROUPING == 0 ? a[s] : a[s * Q + q];
             const float aps = GROUPING == 0 ? a_prev[s] : a_prev[s * Q + q];
-            double sq = 0.0, dual = 0.0;
+            double sq = 0.0, dual = 0.0, tc = 0.0;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const float fn = nb[p] >= 0 ? f[nb[p] * Q + q] : 0.0f;
                 const float wp = weight(wts, grid, s, p, q);
                 const float df = wp * (fs - fn);
                 const int64_t o = (s * 4 + p) * Q + q;
-                const float d = as * v[o];
+                const float vo = v[o];
+                const float d = as * vo;
                 const double pr = static_cast<double>(df) - d;
                 sq += static_cast<double>(df) * df;
                 rp += pr * pr;
+                d2 += static_cast<double>(d) * d;
                 dual += static_cast<double>(wp) * (static_cast<double>(d) - static_cast<double>(aps * v_prev[o]));
+                tc += static_cast<double>(wp) * static_cast<double>(vo - d);
                 if (nb[p] >= 0) {
                     const int pb = p ^ 1;
                     const int64_t o2 = (nb[p] * 4 + pb) * Q + q;
                     const float an = GROUPING == 0 ? a[nb[p]] : a[nb[p] * Q + q];
                     const float apn = GROUPING == 0 ? a_prev[nb[p]] : a_prev[nb[p] * Q + q];
                     const float wn = weight(wts, grid, nb[p], pb, q);
+                    const float v2 = v[o2];
                     dual -= static_cast<double>(wn) *
-                            (static_cast<double>(an * v[o2]) - static_cast<double>(apn * v_prev[o2]));
+                            (static_cast<double>(an * v2) - static_cast<double>(apn * v_prev[o2]));
+                    tc -= static_cast<double>(wn) * static_cast<double>(v2 - an * v2);
                 }
             }
             rd += dual * dual;
+            tc2 += tc * tc;
+            gf2 += sq;
             if (GROUPING == 0) grp += sq;
             else tv += sqrt(sq);
         }
@@ -205,6 +214,34 @@ __global__ __launch_bounds__(kBlock) void k_report(
     block_sum_store(rp, part + n_blocks + blockIdx.x);
     __syncthreads();
     block_sum_store(rd, part + 2 * n_blocks + blockIdx.x);
+    __syncthreads();
+    block_sum_store(gf2, part + 3 * n_blocks + blockIdx.x);
+    __syncthreads();
+    block_sum_store(d2, part + 4 * n_blocks + blockIdx.x);
+    __syncthreads();
+    block_sum_store(tc2, part + 5 * n_blocks + blockIdx.x);
+}
+
+// Penalty change lam -> lam / t with the unscaled dual lam c kept: c <- t c,
+// d unchanged.  Per group, m = a + t (1 - a) > 0; v <- m v, then a <- a / m.
+template <int GROUPING>
+__global__ void k_rescale_v(float *__restrict__ v, const float *__restrict__ a, Grid grid, float t) {
+    const int64_t n = grid.J * 4;
+    for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < n;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = o / (4 * static_cast<int64_t>(grid.Q));
+        const int64_t gidx = GROUPING == 0 ? s : s * grid.Q + o % grid.Q;
+        const float ag = a[gidx];
+        v[o] *= ag + t * (1.0f - ag);
+    }
+}
+
+__global__ void k_rescale_a(float *__restrict__ a, int64_t n, float t) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const float ag = a[i];
+        a[i] = ag / (ag + t * (1.0f - ag));
+    }
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -381,6 +418,22 @@ hipError_t launch_report(const float *f, const float *v, const float *a, const f
     else
         hipLaunchKernelGGL(k_report<1>, dim3(nb), dim3(kBlock), 0, st, f, v, a, v_prev, a_prev,
                            grid, w, sl, partials, static_cast<int64_t>(nb));
+    return hipGetLastError();
+}
+
+hipError_t launch_rescale_dual(float *v, float *a, const Grid &grid, int grouping, float t,
+                               hipStream_t st) {
+    if (grid.J == 0) return hipSuccess;
+    if (grouping == 0)
+        hipLaunchKernelGGL(k_rescale_v<0>, dim3(grid_stride_blocks(grid.J * 4)), dim3(kBlock), 0, st, v, a,
+                           grid, t);
+    else
+        hipLaunchKernelGGL(k_rescale_v<1>, dim3(grid_stride_blocks(grid.J * 4)), dim3(kBlock), 0, st, v, a,
+                           grid, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t ng = grouping == 0 ? grid.S : grid.J;
+    hipLaunchKernelGGL(k_rescale_a, dim3(grid_stride_blocks(ng)), dim3(kBlock), 0, st, a, ng, t);
     return hipGetLastError();
 }
 

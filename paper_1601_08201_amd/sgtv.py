@@ -31,6 +31,19 @@ class SgtvError(RuntimeError):
         self.code = code
 
 
+class Adaptive(ctypes.Structure):
+    _fields_ = [("check", ctypes.c_int32), ("eps_abs", ctypes.c_double), ("eps_rel", ctypes.c_double),
+                ("mu", ctypes.c_double), ("tau", ctypes.c_double)]
+
+
+class Check(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int64), ("r_primal", ctypes.c_double), ("r_dual", ctypes.c_double),
+                ("eps_primal", ctypes.c_double), ("eps_dual", ctypes.c_double), ("rho", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Report(ctypes.Structure):
     _fields_ = [("total", ctypes.c_double), ("data", ctypes.c_double), ("tv", ctypes.c_double),
                 ("r_primal", ctypes.c_double), ("r_dual", ctypes.c_double), ("iter", ctypes.c_int64)]
@@ -107,6 +120,10 @@ def lib():
             "wsnet_adam_step": (_I, [_P, _D, _D, _D, _D]),
             "wsnet_reset_adam": (_I, [_P]),
             "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
+            "sgtv_set_penalty": (_I, [_P, _D]),
+            "sgtv_get_penalty": (_I, [_P, ctypes.POINTER(_D)]),
+            "sgtv_iterate_adaptive": (_I, [_P, _I64, ctypes.POINTER(Adaptive), ctypes.POINTER(Check), _I32,
+                                           ctypes.POINTER(_I32), ctypes.POINTER(_I64), ctypes.POINTER(_I)]),
             "sgtv_get_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_kernel_times": (_I, [_P, _P, _P]),
         }
@@ -242,6 +259,27 @@ def sgtv_get_split(ctx):
     return d, c
 
 
+def sgtv_set_penalty(ctx, rho):
+    _check(lib().sgtv_set_penalty(ctx, float(rho)))
+
+
+def sgtv_get_penalty(ctx):
+    r = _D()
+    _check(lib().sgtv_get_penalty(ctx, ctypes.byref(r)))
+    return r.value
+
+
+def sgtv_iterate_adaptive(ctx, max_iters, check=10, eps_abs=1e-4, eps_rel=1e-3, mu=10.0, tau=2.0):
+    opt = Adaptive(int(check), float(eps_abs), float(eps_rel), float(mu), float(tau))
+    cap = int(max_iters) // max(int(check), 1) + 2
+    arr = (Check * cap)()
+    n, k, conv = _I32(), _I64(), _I()
+    _check(lib().sgtv_iterate_adaptive(ctx, int(max_iters), ctypes.byref(opt), arr, cap, ctypes.byref(n),
+                                       ctypes.byref(k), ctypes.byref(conv)))
+    return {"iterations": k.value, "converged": bool(conv.value),
+            "checks": [arr[i].as_dict() for i in range(min(n.value, cap))]}
+
+
 def sgtv_get_state(ctx):
     n_img, n_split, n_gr = sgtv_state_sizes(ctx)
     f, v, a = np.empty(n_img, np.float32), np.empty(n_split, np.float32), np.empty(n_gr, np.float32)
@@ -358,6 +396,18 @@ class Reconstructor:
 
     def state(self):
         return sgtv_get_state(self._ctx)
+
+    def set_penalty(self, rho):
+        sgtv_set_penalty(self._ctx, rho)
+        return self
+
+    def penalty(self):
+        return sgtv_get_penalty(self._ctx)
+
+    def iterate_adaptive(self, max_iters, check=10, eps_abs=1e-4, eps_rel=1e-3, mu=10.0, tau=2.0):
+        """Residual balancing and the residual stopping rule; returns
+        {"iterations", "converged", "checks": [...]}."""
+        return sgtv_iterate_adaptive(self._ctx, max_iters, check, eps_abs, eps_rel, mu, tau)
 
     def set_state(self, f, v, a, k):
         sgtv_set_state(self._ctx, f, v, a, k)
