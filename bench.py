@@ -102,8 +102,9 @@ def _gen_batch_scan(args):
 
 
 def batch_main(args):
-    """Batch of uneven scans: batched launches (one graph per call) against the
-    same scans iterated one after another."""
+    """Batch of uneven scans: batched launches (one graph per call, the batch
+    schedule) against the same scans iterated one after another, each with its
+    own single-scan schedule."""
     import concurrent.futures as cf
     import multiprocessing as mp
 
@@ -134,13 +135,24 @@ def batch_main(args):
     b.record(stream)
     torch.cuda.synchronize()
     ms_batched = a.elapsed_time(b)
-    B.iterate_sequential(args.warmup)
+    B.close()
+    # the same scans one after another, each with its own single-scan schedule
+    # (tuned when cached): a scan launched alone has to fill the GPU by itself
+    Bs = sgtv.Batch(stream=stream.cuda_stream)
+    t0 = time.time()
+    scheds = [autotune.cached_schedule(p) for p in probs]
+    with cf.ThreadPoolExecutor(8) as ex:
+        list(ex.map(lambda ps: Bs.add_scan(ps[0], ps[1]), zip(probs, scheds)))
+    log("sequential reference built in %.1fs (%d scans with tuned schedules)"
+        % (time.time() - t0, sum(x is not None for x in scheds)))
+    Bs.iterate_sequential(args.warmup)
     torch.cuda.synchronize()
     a.record(stream)
-    B.iterate_sequential(args.steps)
+    Bs.iterate_sequential(args.steps)
     b.record(stream)
     torch.cuda.synchronize()
     ms_seq = a.elapsed_time(b)
+    Bs.close()
     alg = sum(sum(algorithmic_bytes(p, 4, "tiled").values()) for p in probs)
     scan_its = len(probs) * args.steps
     out = {
@@ -164,7 +176,6 @@ def batch_main(args):
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
-    B.close()
 
 
 def sweep_main(args):
@@ -253,6 +264,58 @@ def sweep_main(args):
     print(json.dumps(out), flush=True)
     B.close()
     Bs.close()
+
+
+def adaptive_main(args):
+    """Fixed penalty against residual balancing on the paper-scale scan: both
+    run until the residual stopping rule holds (checked every 10 iterations)."""
+    import torch
+    from paper_1601_08201_amd import autotune, datagen, sgtv
+
+    torch.cuda.set_device(0)
+    prob = datagen.make_problem("paper", args.seed)
+    stream = torch.cuda.current_stream()
+    R = sgtv.Reconstructor(stream=stream.cuda_stream)
+    tuned = autotune.cached_schedule(prob)
+    if tuned:
+        R.set_schedule(**tuned)
+    R.set_problem(prob)
+    opt = dict(check=10, eps_abs=args.eps_abs, eps_rel=args.eps_rel, mu=10.0)
+    R.set_init(None)
+    R.iterate_adaptive(20, tau=1.0, eps_abs=0.0, eps_rel=0.0, check=10, mu=10.0)   # warm-up, graphs
+    res = {}
+    for name, tau in (("fixed", 1.0), ("adaptive", 2.0)):
+        R.set_penalty(prob.rho)
+        R.set_init(None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = R.iterate_adaptive(args.max_iters, tau=tau, **opt)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        rep = R.objective()
+        res[name] = {"iterations": out["iterations"], "converged": out["converged"], "seconds": sec,
+                     "rho_final": R.penalty(), "objective": rep["total"],
+                     "rho_changes": sum(1 for a, b in zip([prob.rho] + [c["rho"] for c in out["checks"]],
+                                                         [c["rho"] for c in out["checks"]]) if a != b)}
+        log("%-8s %5d iterations, converged %s, %.3f s, rho %g, objective %.6f"
+            % (name, out["iterations"], out["converged"], sec, R.penalty(), rep["total"]))
+    out = {
+        "metric": "time to the residual stopping rule, fixed vs adaptive penalty (paper-scale scan)",
+        "value": res["fixed"]["seconds"] / res["adaptive"]["seconds"],
+        "unit": "x speedup (fixed / adaptive)",
+        "n_gpus": 1, "steps": res["adaptive"]["iterations"], "warmup": 20,
+        "ms_per_step": 1e3 * res["adaptive"]["seconds"] / max(res["adaptive"]["iterations"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded phantom, random coded-mask system matrix, Poisson counts)",
+        "config": {"workload": "paper-scale scan 128x128x128, I=1048576, 64 nnz/col; stop when r <= eps_pri and "
+                               "s <= eps_dual (eps_abs %g, eps_rel %g, checked every 10), mu 10, tau 2"
+                               % (args.eps_abs, args.eps_rel),
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "runs": res,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    R.close()
 
 
 def warmstart_main(args):
@@ -372,10 +435,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart", "sweep"],
+    ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart", "sweep", "adaptive"],
                     help="scan: the paper-scale scan (default); batch: 64 uneven scans; "
                          "warmstart: learned start vs plain start; sweep: beta sweep of both "
-                         "regularisers on the paper-shaped scan in one batch")
+                         "regularisers on the paper-shaped scan in one batch; adaptive: fixed vs "
+                         "adaptive penalty to the residual stopping rule")
+    ap.add_argument("--eps-abs", type=float, default=1e-5)
+    ap.add_argument("--eps-rel", type=float, default=1e-3)
+    ap.add_argument("--max-iters", type=int, default=4000)
     ap.add_argument("--betas", default="0.01,0.02,0.05,0.1,0.2,0.5,1,2")
     ap.add_argument("--train-scans", type=int, default=2000)
     ap.add_argument("--eval-scans", type=int, default=200)
@@ -404,6 +471,8 @@ def main():
         return batch_main(args)
     if args.workload == "warmstart":
         return warmstart_main(args)
+    if args.workload == "adaptive":
+        return adaptive_main(args)
     if args.workload == "sweep":
         if args.steps == 200:
             args.steps = 1000
