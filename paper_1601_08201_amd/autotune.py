@@ -38,7 +38,7 @@ def candidates(I, J, waves=16, per_side=10):
     def side(n_rows, n_cols):
         out = []
         for rw in (64, 128, 256, 512, 1024):
-            for cb in (4096, 8192, 16384):
+            for cb in (4096, 8192, 16380):
                 cb_eff = min(cb, max(4, 1 << (max(n_cols, 4) - 1).bit_length()))
                 if lds_bytes(waves, rw, cb_eff) > MAX_LDS:
                     continue
@@ -65,7 +65,7 @@ def candidates(I, J, waves=16, per_side=10):
 
 def _auto_slabs(n_cols):
     """Slab count of the automatic schedule (slab of the gathered vector <= 2 MiB)."""
-    cb = min(16384, max(4, 1 << (max(n_cols, 4) - 1).bit_length()))
+    cb = min(16380, max(4, 1 << (max(n_cols, 4) - 1).bit_length()))
     n_cb = -(-n_cols // cb)
     want = 1 << max(0, (-(-(n_cols * 4) // 2 ** 21) - 1).bit_length())
     return max(1, min(want, 8, n_cb))

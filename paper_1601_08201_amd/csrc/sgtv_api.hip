@@ -147,7 +147,7 @@ void pack_sell(int64_t n_lines, const std::vector<int64_t> &lptr, const std::vec
 }
 
 struct Tiled {
-    DBuf pk, val, goff;
+    DBuf pk, val, goff, poff;
     sgtv::TileMap map{};
 };
 
@@ -162,14 +162,16 @@ int64_t next_pow2(int64_t v) {
     return p;
 }
 
-// Automatic schedule: column blocks of up to 16K entries, slabs so that one
+// Automatic schedule: column blocks of up to 16380 entries, slabs so that one
 // slab of the gathered vector is at most 2 MiB (an XCD's 4 MiB L2 keeps it
 // next to the streamed entries), and
 // rows per wave so that the grid has at least 256 workgroups (one per CU).
 TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int cb, int ns) {
     TileParams t;
     t.waves = waves > 0 ? waves : 16;
-    t.cb = cb > 0 ? cb : static_cast<int>(std::min<int64_t>(16384, std::max<int64_t>(4, next_pow2(n_cols))));
+    // 16380 = the widest block of the 24-bit index format (a multiple of 4
+    // below 2^14, leaving one code for the zero slot)
+    t.cb = cb > 0 ? cb : static_cast<int>(std::min<int64_t>(16380, std::max<int64_t>(4, next_pow2(n_cols))));
     const int64_t ncb = (n_cols + t.cb - 1) / t.cb;
     if (ns > 0) {
         t.ns = ns;
@@ -191,7 +193,7 @@ TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int c
 size_t tile_lds_bytes(const TileParams &t) {
     size_t a = static_cast<size_t>(t.waves) * (t.rw + 1) * 4;
     a = (a + 15) / 16 * 16;
-    return a + static_cast<size_t>(t.cb) * 4;
+    return a + static_cast<size_t>(t.cb) * 4 + 16;   // + the zero slot of the 24-bit format
 }
 
 // Host packing of one tiled product from CSR-like lines (rows of M in order,
@@ -199,8 +201,13 @@ size_t tile_lds_bytes(const TileParams &t) {
 template <class V>
 int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
-                std::vector<int32_t> &pk, std::vector<V> &pv, std::vector<int32_t> &goff,
-                sgtv::TileMap &map) {
+                bool idx24, std::vector<int32_t> &pk, std::vector<V> &pv, std::vector<int32_t> &goff,
+                std::vector<int32_t> &poff, sgtv::TileMap &map) {
+    // 24-bit indices: row in 10 bits, column in 14 with the code cb left for
+    // the zero slot; padding entries take a row unused in their group (so a
+    // wave needs at least 64 rows) and read the zero slot
+    idx24 = idx24 && t.rw >= 64 && t.rw <= 1024 && t.cb % 4 == 0 && t.cb <= 16380;
+    const int row_shift = idx24 ? 14 : 16;
     const int64_t RB = static_cast<int64_t>(t.waves) * t.rw;
     const int64_t n_rb = (n_rows + RB - 1) / RB;
     const int64_t ncb = (n_cols + t.cb - 1) / t.cb;
@@ -244,7 +251,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     goff[n_lists] = static_cast<int32_t>(total);
     // one extra all-padding batch at the end: the kernel streams it in place of
     // a batch past the end of a list
-    pk.assign(static_cast<size_t>(total * 64 + 256), t.rw << 16);
+    pk.assign(static_cast<size_t>(total * 64 + 256), t.rw << row_shift);
     pv.assign(static_cast<size_t>(total * 64 + 256), V(0));
     std::fill(count.begin(), count.end(), 0);   // reuse as cursor
     for (int64_t r = 0; r < n_rows; ++r) {
@@ -259,15 +266,93 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             const int64_t base = static_cast<int64_t>(goff[L]) * 64;
             const int64_t pos = g < nb4 * 4 ? base + (g / 4) * 256 + lane * 4 + (g % 4)
                                             : base + nb4 * 256 + (g - nb4 * 4) * 64 + lane;
-            pk[pos] = static_cast<int32_t>((rl << 16) | (c % t.cb));
+            pk[pos] = static_cast<int32_t>((rl << row_shift) | (c % t.cb));
             pv[pos] = vals[k];
         }
     }
+    poff.clear();
+    if (idx24) {
+        // padding lanes: distinct rows absent from the group, column = zero slot
+        std::vector<uint8_t> used(static_cast<size_t>(t.rw));
+        for (int64_t L = 0; L < n_lists; ++L) {
+            const int64_t ng = ngr[L], nb4 = ng / 4;
+            const int64_t base = static_cast<int64_t>(goff[L]) * 64;
+            for (int64_t g = 0; g < ng; ++g) {
+                auto at = [&](int64_t lane) -> int32_t & {
+                    return pk[g < nb4 * 4 ? base + (g / 4) * 256 + lane * 4 + (g % 4)
+                                          : base + nb4 * 256 + (g - nb4 * 4) * 64 + lane];
+                };
+                std::fill(used.begin(), used.end(), 0);
+                for (int64_t lane = 0; lane < 64; ++lane) {
+                    const int32_t v = at(lane);
+                    if ((v >> row_shift) < t.rw) used[v >> row_shift] = 1;
+                }
+                int free_row = 0;
+                for (int64_t lane = 0; lane < 64; ++lane) {
+                    int32_t &v = at(lane);
+                    if ((v >> row_shift) < t.rw) continue;
+                    while (used[free_row]) ++free_row;
+                    used[free_row] = 1;
+                    v = (free_row << row_shift) | t.cb;
+                }
+            }
+        }
+        // repack: per list, whole batches as three dwords per lane (a plane of
+        // 64 dword pairs, then a plane of 64 dwords), then the remaining groups
+        // one dword per entry
+        poff.assign(static_cast<size_t>(n_lists + 1), 0);
+        int64_t words = 0;
+        for (int64_t L = 0; L < n_lists; ++L) {
+            poff[L] = static_cast<int32_t>(words);
+            const int64_t ng = ngr[L], nb4 = ng / 4;
+            words += nb4 * 3 * 64 + (ng - nb4 * 4) * 64;   // super-batches take 3 dwords per batch too
+        }
+        poff[n_lists] = static_cast<int32_t>(words);
+        std::vector<int32_t> p24(static_cast<size_t>(words));
+        for (int64_t L = 0; L < n_lists; ++L) {
+            const int64_t ng = ngr[L], nb4 = ng / 4;
+            const int64_t base = static_cast<int64_t>(goff[L]) * 64;
+            uint32_t *dst = reinterpret_cast<uint32_t *>(p24.data()) + poff[L];
+            const int64_t nsb = nb4 / 4;
+            for (int64_t b = 0; b < nb4; ++b)
+                for (int64_t lane = 0; lane < 64; ++lane) {
+                    const uint32_t *e = reinterpret_cast<const uint32_t *>(pk.data()) + base + b * 256 + lane * 4;
+                    const uint32_t w0 = e[0] | (e[1] << 24);
+                    const uint32_t w1 = (e[1] >> 8) | (e[2] << 16);
+                    const uint32_t w2 = (e[2] >> 16) | (e[3] << 8);
+                    if (b < nsb * 4) {
+                        // super-batch sb: words 3t .. 3t + 2 of batch t = b % 4, word i in
+                        // plane i / 4, slot i % 4 of the lane's 16 bytes
+                        uint32_t *sbp = dst + (b / 4) * 768;
+                        const int64_t i0 = 3 * (b % 4);
+                        const uint32_t w[3] = {w0, w1, w2};
+                        for (int64_t k = 0; k < 3; ++k) {
+                            const int64_t i = i0 + k;
+                            sbp[(i / 4) * 256 + lane * 4 + (i % 4)] = w[k];
+                        }
+                    } else {
+                        uint32_t *bp = dst + nsb * 768 + (b - nsb * 4) * 192;
+                        bp[lane * 2] = w0;
+                        bp[lane * 2 + 1] = w1;
+                        bp[128 + lane] = w2;
+                    }
+                }
+            for (int64_t g = nb4 * 4; g < ng; ++g)
+                for (int64_t lane = 0; lane < 64; ++lane)
+                    dst[nb4 * 192 + (g - nb4 * 4) * 64 + lane] =
+                        static_cast<uint32_t>(pk[base + nb4 * 256 + (g - nb4 * 4) * 64 + lane]);
+        }
+        // keep the all-padding batch of the 32-bit layout after the repacked
+        // lists (the simple loop that reads 24-bit indices never streams it)
+        p24.insert(p24.end(), pk.end() - 256, pk.end());
+        pk.swap(p24);
+    }
     map = sgtv::TileMap{};
+    map.idx24 = idx24 ? 1 : 0;
     map.n_rows = n_rows;
     map.n_cols = n_cols;
     map.n_rb = n_rb;
-    map.pad = total * 64;
+    map.pad = idx24 ? static_cast<int64_t>(pk.size()) - 256 : total * 64;
     map.rw = t.rw;
     map.waves = t.waves;
     map.cb = t.cb;
@@ -280,16 +365,19 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
 
 template <class V>
 int upload_tiled(Tiled &T, int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
-                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t) {
-    std::vector<int32_t> pk, goff;
+                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
+                 bool idx24) {
+    std::vector<int32_t> pk, goff, poff;
     std::vector<V> pv;
-    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, pk, pv, goff, T.map)) return e;
+    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, idx24, pk, pv, goff, poff, T.map)) return e;
     HIP_TRY(upload(T.pk, pk));
     HIP_TRY(upload(T.val, pv));
     HIP_TRY(upload(T.goff, goff));
+    if (!poff.empty()) HIP_TRY(upload(T.poff, poff));
     T.map.pk = T.pk.as<int32_t>();
     T.map.val = T.val.p;
     T.map.goff = T.goff.as<int32_t>();
+    T.map.poff = poff.empty() ? nullptr : T.poff.as<int32_t>();
     return SGTV_OK;
 }
 
@@ -558,16 +646,19 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
                 cidx[pos] = static_cast<int32_t>(i);
                 csrc[pos] = k;
             }
+        // the simple loop (variant 1) and the prefetching loop (variant 4) read
+        // 24-bit indices where the tile fits them
+        const bool i24 = S->sched.variant == 1 || S->sched.variant == 4;
         if (vt == SGTV_F32) {
-            if (int e = upload_tiled(S->fwd, I, J, rp, ci, av, tf)) return e;
+            if (int e = upload_tiled(S->fwd, I, J, rp, ci, av, tf, i24)) return e;
             std::vector<float> cv(static_cast<size_t>(nnz));
             for (int64_t k = 0; k < nnz; ++k) cv[k] = av[csrc[k]];
-            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb)) return e;
+            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb, i24)) return e;
         } else {
-            if (int e = upload_tiled(S->fwd, I, J, rp, ci, codes, tf)) return e;
+            if (int e = upload_tiled(S->fwd, I, J, rp, ci, codes, tf, i24)) return e;
             std::vector<uint16_t> cv(static_cast<size_t>(nnz));
             for (int64_t k = 0; k < nnz; ++k) cv[k] = codes[csrc[k]];
-            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb)) return e;
+            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb, i24)) return e;
         }
         S->fwd.map.variant = S->sched.variant - 1;
         S->back.map.variant = S->sched.variant - 1;
@@ -1244,7 +1335,7 @@ int sgtv_set_schedule(sgtv_ctx ctx, const sgtv_schedule *s) {
     if (!ctx || !s) return fail(SGTV_EINVAL, "null argument");
     if (s->format != SGTV_FORMAT_TILED && s->format != SGTV_FORMAT_SELL) return fail(SGTV_EINVAL, "unknown format");
     if (s->waves < 0 || s->waves > 16) return fail(SGTV_EINVAL, "waves must be in [1, 16] (0: automatic)");
-    if (s->variant < 0 || s->variant > 3) return fail(SGTV_EINVAL, "variant must be in [1, 3] (0: automatic)");
+    if (s->variant < 0 || s->variant > 4) return fail(SGTV_EINVAL, "variant must be in [1, 4] (0: automatic)");
     const int32_t rws[2] = {s->fwd_rows_per_wave, s->back_rows_per_wave};
     const int32_t cbs[2] = {s->fwd_block_cols, s->back_block_cols};
     const int32_t nss[2] = {s->fwd_slabs, s->back_slabs};

@@ -47,6 +47,9 @@ struct TileMap {
     const int32_t *pk;      // packed (row in wave, column in block), padding: row = rw
     const void *val;        // values or 16-bit codes, padding: 0
     const int32_t *goff;    // group offset of every list, n_lists + 1 entries
+    const int32_t *poff;    // 24-bit indices: offset (in dwords) of every list's indices
+    int idx24;              // 1: indices row << 14 | column, three dwords per lane and batch;
+                            // padding: a row unused in its group, column cb (a zero in LDS)
     int64_t n_rows, n_cols;
     int64_t n_rb;           // row blocks
     int64_t pad;            // entry offset of one all-padding batch (256 entries)
@@ -56,7 +59,7 @@ struct TileMap {
     size_t lds_bytes() const {
         size_t a = static_cast<size_t>(waves) * (rw + 1) * 4;
         a = (a + 15) / 16 * 16;
-        return a + static_cast<size_t>(cb) * 4;
+        return a + static_cast<size_t>(cb) * 4 + (idx24 ? 16 : 0);
     }
 };
 

@@ -90,6 +90,15 @@ SCHEDULES = {
                         back_rows_per_wave=32, back_block_cols=512, back_slabs=2),
     "tiles-one-wave": dict(format=0, waves=1, fwd_rows_per_wave=100, fwd_block_cols=4092, fwd_slabs=1,
                            back_rows_per_wave=300, back_block_cols=12, back_slabs=5),
+    # 16384-column blocks: the 32-bit index format of the simple loop
+    "tiles-32bit-index": dict(format=0, waves=4, fwd_rows_per_wave=512, fwd_block_cols=16384, fwd_slabs=1,
+                              back_rows_per_wave=1024, back_block_cols=16384, back_slabs=1),
+    "tiles-pipelined": dict(format=0, waves=8, fwd_rows_per_wave=128, fwd_block_cols=2048, fwd_slabs=2,
+                            back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=2),
+    "tiles-prefetch": dict(format=0, waves=8, fwd_rows_per_wave=128, fwd_block_cols=2048, fwd_slabs=2,
+                           back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=3),
+    "tiles-lookahead": dict(format=0, waves=8, fwd_rows_per_wave=128, fwd_block_cols=2048, fwd_slabs=2,
+                            back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=4),
 }
 
 

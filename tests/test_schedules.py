@@ -16,7 +16,7 @@ def test_auto_slabs_keep_slab_at_most_2mib():
         ns = autotune._auto_slabs(n)
         assert 1 <= ns <= 8 and ns & (ns - 1) == 0
         if ns < 8:
-            assert n * 4 / ns <= 2 ** 21 or -(-n // 16384) == ns
+            assert n * 4 / ns <= 2 ** 21 or -(-n // 16380) == ns
 
 
 def test_batch_schedule_prefers_long_tiles_for_big_batches():
