@@ -225,11 +225,9 @@ int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);
  *     straight from memory (no other field applies).
  *   variant: inner loop of the tiled products: 1 one batch of entries in
  *     flight per wave, 2 two batches, 3 two batches plus the next column block
- *     read ahead into registers, 4 as 1 with the next column block and the
- *     first entries of the next list read ahead before each block barrier
- *     (0: automatic).  Variants 1 and 4 store the entries' indices in 24 bits
- *     (three bytes per entry instead of four) when 64 <= rows_per_wave <=
- *     1024 and block_cols <= 16380; variant 4 falls back to 1 otherwise.
+ *     read ahead into registers (0: automatic).  Variant 1 stores the
+ *     entries' indices in 24 bits (three bytes per entry instead of four)
+ *     when 64 <= rows_per_wave <= 1024 and block_cols <= 16380.
  * Limits: waves in [1, 16]; rows_per_wave in [1, 32767]; block_cols a
  * multiple of 4 in [4, 65536]; slabs in [1, 16]; the LDS of one workgroup,
  * 4 * (waves * (rows_per_wave + 1) rounded up to 4 + block_cols) + 16 bytes,

@@ -204,8 +204,9 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 bool idx24, std::vector<int32_t> &pk, std::vector<V> &pv, std::vector<int32_t> &goff,
                 std::vector<int32_t> &poff, sgtv::TileMap &map) {
     // 24-bit indices: row in 10 bits, column in 14 with the code cb left for
-    // the zero slot; padding entries take a row unused in their group (so a
-    // wave needs at least 64 rows) and read the zero slot
+    // the zero slot.  Their lists are lane-owned: all entries of a row within a
+    // list sit in one lane, in row order, so a lane can read every accumulator
+    // of a window of entries at once (no other lane touches its rows)
     idx24 = idx24 && t.rw >= 64 && t.rw <= 1024 && t.cb % 4 == 0 && t.cb <= 16380;
     const int row_shift = idx24 ? 14 : 16;
     const int64_t RB = static_cast<int64_t>(t.waves) * t.rw;
@@ -238,11 +239,91 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             last[L] = r;
             maxrun[L] = std::max(maxrun[L], run[L]);
         }
+    // idx24: the entries (indices into ci / vals) of every list, in row order
+    std::vector<int64_t> lstart, lent;
+    std::vector<int16_t> lrow;   // row within the wave of every listed entry
+    if (idx24) {
+        lstart.assign(static_cast<size_t>(n_lists + 1), 0);
+        for (int64_t L = 0; L < n_lists; ++L) lstart[L + 1] = lstart[L] + count[L];
+        lent.resize(static_cast<size_t>(lstart[n_lists]));
+        lrow.resize(static_cast<size_t>(lstart[n_lists]));
+        std::vector<int64_t> cur(lstart.begin(), lstart.end() - 1);
+        for (int64_t r = 0; r < n_rows; ++r)
+            for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+                const int64_t at = cur[list_of(r, ci[k])]++;
+                lent[at] = k;
+                lrow[at] = static_cast<int16_t>((r % RB) % t.rw);
+            }
+    }
+    // Lane-owned layout of list L: runs of equal rows, longest first (ties in
+    // row order), each to the least-loaded lane (ties: lowest lane); a lane
+    // keeps its runs in row order.  Fills lane_load[64] and, in lane order,
+    // seq (the entries of lane 0, then lane 1, ...) with lane_begin[65];
+    // returns the largest load.
+    std::vector<int64_t> run_start, run_len, run_order, seq;
+    std::vector<int32_t> run_lane, len_count;
+    int32_t lane_load[64];
+    int64_t lane_begin[65];
+    auto lane_owned = [&](int64_t L) -> int64_t {
+        const int64_t b0 = lstart[L], n = lstart[L + 1] - b0;
+        run_start.clear();
+        run_len.clear();
+        int64_t maxlen = 0;
+        for (int64_t i = 0; i < n;) {
+            int64_t j = i + 1;
+            while (j < n && lrow[b0 + j] == lrow[b0 + i]) ++j;
+            run_start.push_back(i);
+            run_len.push_back(j - i);
+            maxlen = std::max(maxlen, j - i);
+            i = j;
+        }
+        const int64_t nr = static_cast<int64_t>(run_start.size());
+        // counting sort of the runs by decreasing length (stable)
+        len_count.assign(static_cast<size_t>(maxlen + 2), 0);
+        for (int64_t q = 0; q < nr; ++q) len_count[maxlen - run_len[q] + 1]++;
+        for (int64_t v = 1; v <= maxlen + 1; ++v) len_count[v] += len_count[v - 1];
+        run_order.resize(static_cast<size_t>(nr));
+        for (int64_t q = 0; q < nr; ++q) run_order[len_count[maxlen - run_len[q]]++] = q;
+        // least-loaded lane by a binary heap on key = load * 64 + lane
+        int64_t heap[64];
+        for (int l = 0; l < 64; ++l) heap[l] = l;
+        run_lane.resize(static_cast<size_t>(nr));
+        for (int64_t q : run_order) {
+            const int64_t top = heap[0];
+            const int lane = static_cast<int>(top & 63);
+            run_lane[q] = lane;
+            heap[0] = top + run_len[q] * 64;
+            for (int h = 0;;) {   // sift down
+                int m = h, c1 = 2 * h + 1, c2 = 2 * h + 2;
+                if (c1 < 64 && heap[c1] < heap[m]) m = c1;
+                if (c2 < 64 && heap[c2] < heap[m]) m = c2;
+                if (m == h) break;
+                std::swap(heap[h], heap[m]);
+                h = m;
+            }
+        }
+        for (int l = 0; l < 64; ++l) lane_load[l] = 0;
+        for (int64_t q = 0; q < nr; ++q) lane_load[run_lane[q]] += static_cast<int32_t>(run_len[q]);
+        lane_begin[0] = 0;
+        int64_t ng = 0;
+        for (int l = 0; l < 64; ++l) {
+            lane_begin[l + 1] = lane_begin[l] + lane_load[l];
+            ng = std::max<int64_t>(ng, lane_load[l]);
+        }
+        seq.resize(static_cast<size_t>(n));
+        int64_t fill[64];
+        for (int l = 0; l < 64; ++l) fill[l] = lane_begin[l];
+        for (int64_t q = 0; q < nr; ++q)
+            for (int64_t u = 0; u < run_len[q]; ++u) seq[fill[run_lane[q]]++] = b0 + run_start[q] + u;
+        return ng;
+    };
     goff.assign(static_cast<size_t>(n_lists + 1), 0);
     int64_t total = 0;
     std::vector<int32_t> ngr(static_cast<size_t>(n_lists));
     for (int64_t L = 0; L < n_lists; ++L) {
-        const int64_t ng = count[L] ? std::max<int64_t>((count[L] + 63) / 64, maxrun[L]) : 0;
+        const int64_t ng = count[L] == 0 ? 0
+                           : idx24     ? lane_owned(L)
+                                       : std::max<int64_t>((count[L] + 63) / 64, maxrun[L]);
         ngr[L] = static_cast<int32_t>(ng);
         goff[L] = static_cast<int32_t>(total);
         total += ng;
@@ -253,48 +334,59 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     // a batch past the end of a list
     pk.assign(static_cast<size_t>(total * 64 + 256), t.rw << row_shift);
     pv.assign(static_cast<size_t>(total * 64 + 256), V(0));
-    std::fill(count.begin(), count.end(), 0);   // reuse as cursor
-    for (int64_t r = 0; r < n_rows; ++r) {
-        const int64_t rl = (r % RB) % t.rw;
-        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
-            const int32_t c = ci[k];
-            const int64_t L = list_of(r, c);
-            const int64_t kk = count[L]++;
-            const int64_t ng = ngr[L];
-            const int64_t g = kk % ng, lane = kk / ng;
-            const int64_t nb4 = ng / 4;
-            const int64_t base = static_cast<int64_t>(goff[L]) * 64;
-            const int64_t pos = g < nb4 * 4 ? base + (g / 4) * 256 + lane * 4 + (g % 4)
-                                            : base + nb4 * 256 + (g - nb4 * 4) * 64 + lane;
-            pk[pos] = static_cast<int32_t>((rl << row_shift) | (c % t.cb));
-            pv[pos] = vals[k];
+    auto slot = [&](int64_t L, int64_t g, int64_t lane) -> int64_t {
+        const int64_t ng = ngr[L], nb4 = ng / 4;
+        const int64_t base = static_cast<int64_t>(goff[L]) * 64;
+        return g < nb4 * 4 ? base + (g / 4) * 256 + lane * 4 + (g % 4)
+                           : base + nb4 * 256 + (g - nb4 * 4) * 64 + lane;
+    };
+    if (!idx24) {
+        // round robin over the groups: consecutive entries of a row (one list)
+        // fall into consecutive groups, so every group holds distinct rows
+        std::fill(count.begin(), count.end(), 0);   // reuse as cursor
+        for (int64_t r = 0; r < n_rows; ++r) {
+            const int64_t rl = (r % RB) % t.rw;
+            for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+                const int32_t c = ci[k];
+                const int64_t L = list_of(r, c);
+                const int64_t kk = count[L]++;
+                const int64_t ng = ngr[L];
+                const int64_t pos = slot(L, kk % ng, kk / ng);
+                pk[pos] = static_cast<int32_t>((rl << row_shift) | (c % t.cb));
+                pv[pos] = vals[k];
+            }
         }
     }
     poff.clear();
     if (idx24) {
-        // padding lanes: distinct rows absent from the group, column = zero slot
-        std::vector<uint8_t> used(static_cast<size_t>(t.rw));
+        // lane-owned placement: lane l's i-th entry in group i; a lane shorter
+        // than the list repeats its last row with value 0 (its running sum is
+        // unchanged), an empty lane takes a row absent from the list; padding
+        // reads the zero slot (column code cb)
+        std::vector<uint8_t> present(static_cast<size_t>(t.rw));
         for (int64_t L = 0; L < n_lists; ++L) {
-            const int64_t ng = ngr[L], nb4 = ng / 4;
-            const int64_t base = static_cast<int64_t>(goff[L]) * 64;
-            for (int64_t g = 0; g < ng; ++g) {
-                auto at = [&](int64_t lane) -> int32_t & {
-                    return pk[g < nb4 * 4 ? base + (g / 4) * 256 + lane * 4 + (g % 4)
-                                          : base + nb4 * 256 + (g - nb4 * 4) * 64 + lane];
-                };
-                std::fill(used.begin(), used.end(), 0);
-                for (int64_t lane = 0; lane < 64; ++lane) {
-                    const int32_t v = at(lane);
-                    if ((v >> row_shift) < t.rw) used[v >> row_shift] = 1;
+            if (count[L] == 0) continue;
+            const int64_t ng = lane_owned(L);
+            std::fill(present.begin(), present.end(), 0);
+            for (int64_t i = lstart[L]; i < lstart[L + 1]; ++i) present[lrow[i]] = 1;
+            int free_row = 0;
+            for (int l = 0; l < 64; ++l) {
+                int32_t last = -1;
+                for (int64_t i = 0; i < lane_load[l]; ++i) {
+                    const int64_t at = seq[lane_begin[l] + i];
+                    const int64_t k = lent[at];
+                    last = lrow[at];
+                    const int64_t pos = slot(L, i, l);
+                    pk[pos] = static_cast<int32_t>((last << row_shift) | (ci[k] % t.cb));
+                    pv[pos] = vals[k];
                 }
-                int free_row = 0;
-                for (int64_t lane = 0; lane < 64; ++lane) {
-                    int32_t &v = at(lane);
-                    if ((v >> row_shift) < t.rw) continue;
-                    while (used[free_row]) ++free_row;
-                    used[free_row] = 1;
-                    v = (free_row << row_shift) | t.cb;
+                if (last < 0) {
+                    while (present[free_row]) ++free_row;
+                    present[free_row] = 1;
+                    last = free_row;
                 }
+                for (int64_t i = lane_load[l]; i < ng; ++i)
+                    pk[slot(L, i, l)] = static_cast<int32_t>((last << row_shift) | t.cb);
             }
         }
         // repack: per list, whole batches as three dwords per lane (a plane of
@@ -646,9 +738,8 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
                 cidx[pos] = static_cast<int32_t>(i);
                 csrc[pos] = k;
             }
-        // the simple loop (variant 1) and the prefetching loop (variant 4) read
-        // 24-bit indices where the tile fits them
-        const bool i24 = S->sched.variant == 1 || S->sched.variant == 4;
+        // the simple loop (variant 1) reads 24-bit indices where the tile fits them
+        const bool i24 = S->sched.variant == 1;
         if (vt == SGTV_F32) {
             if (int e = upload_tiled(S->fwd, I, J, rp, ci, av, tf, i24)) return e;
             std::vector<float> cv(static_cast<size_t>(nnz));
@@ -1335,7 +1426,7 @@ int sgtv_set_schedule(sgtv_ctx ctx, const sgtv_schedule *s) {
     if (!ctx || !s) return fail(SGTV_EINVAL, "null argument");
     if (s->format != SGTV_FORMAT_TILED && s->format != SGTV_FORMAT_SELL) return fail(SGTV_EINVAL, "unknown format");
     if (s->waves < 0 || s->waves > 16) return fail(SGTV_EINVAL, "waves must be in [1, 16] (0: automatic)");
-    if (s->variant < 0 || s->variant > 4) return fail(SGTV_EINVAL, "variant must be in [1, 4] (0: automatic)");
+    if (s->variant < 0 || s->variant > 3) return fail(SGTV_EINVAL, "variant must be in [1, 3] (0: automatic)");
     const int32_t rws[2] = {s->fwd_rows_per_wave, s->back_rows_per_wave};
     const int32_t cbs[2] = {s->fwd_block_cols, s->back_block_cols};
     const int32_t nss[2] = {s->fwd_slabs, s->back_slabs};

@@ -46,20 +46,63 @@ __device__ __forceinline__ void tile_batch(const v4i p, const typename Code<VT>:
     t = xs[p.w & 0xFFFF]; my[p.w >> 16] = fmaf(Code<VT>::dec(a.w), t, my[p.w >> 16]);
 }
 
-// Products of one batch with 24-bit indices.
+// A lane's window of N entries with 24-bit indices (lane-owned lists: no
+// other lane touches these rows, and equal rows are adjacent): all gathers and
+// accumulator reads are issued first, then the running sum of each row is
+// carried in a register across adjacent entries and written once per run (the
+// sums keep their order: entry after entry).
+template <int VT, int N>
+__device__ __forceinline__ void window24(const uint32_t (&e)[N], const typename Code<VT>::T (&a)[N],
+                                         const float *xs, float *my) {
+    float t[N], m[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = xs[e[i] & 0x3FFF];
+#pragma unroll
+    for (int i = 0; i < N; ++i) m[i] = my[e[i] >> 14];
+    float run = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint32_t row = e[i] >> 14;
+        const bool cont = i > 0 && row == (e[i - 1] >> 14);
+        run = fmaf(Code<VT>::dec(a[i]), t[i], cont ? run : m[i]);
+        if (i + 1 == N || (e[i + 1] >> 14) != row) my[row] = run;
+    }
+}
+
+__device__ __forceinline__ void unpack4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t *e) {
+    e[0] = w0 & 0xFFFFFFu;
+    e[1] = ((w0 >> 24) | (w1 << 8)) & 0xFFFFFFu;
+    e[2] = ((w1 >> 16) | (w2 << 16)) & 0xFFFFFFu;
+    e[3] = w2 >> 8;
+}
+
+// one batch (4 entries per lane)
 template <int VT>
 __device__ __forceinline__ void tile_batch24(uint32_t w0, uint32_t w1, uint32_t w2,
                                              const typename Code<VT>::V4 a, const float *xs,
                                              float *my) {
-    const uint32_t e0 = w0 & 0xFFFFFFu;
-    const uint32_t e1 = ((w0 >> 24) | (w1 << 8)) & 0xFFFFFFu;
-    const uint32_t e2 = ((w1 >> 16) | (w2 << 16)) & 0xFFFFFFu;
-    const uint32_t e3 = w2 >> 8;
-    float t;
-    t = xs[e0 & 0x3FFF]; my[e0 >> 14] = fmaf(Code<VT>::dec(a.x), t, my[e0 >> 14]);
-    t = xs[e1 & 0x3FFF]; my[e1 >> 14] = fmaf(Code<VT>::dec(a.y), t, my[e1 >> 14]);
-    t = xs[e2 & 0x3FFF]; my[e2 >> 14] = fmaf(Code<VT>::dec(a.z), t, my[e2 >> 14]);
-    t = xs[e3 & 0x3FFF]; my[e3 >> 14] = fmaf(Code<VT>::dec(a.w), t, my[e3 >> 14]);
+    uint32_t e[4];
+    unpack4(w0, w1, w2, e);
+    const typename Code<VT>::T av[4] = {a.x, a.y, a.z, a.w};
+    window24<VT, 4>(e, av, xs, my);
+}
+
+// one super-batch (16 entries per lane: three 16-byte index planes, four value batches)
+template <int VT, class U4>
+__device__ __forceinline__ void tile_super24(const U4 A, const U4 B, const U4 C,
+                                             const typename Code<VT>::V4 a0,
+                                             const typename Code<VT>::V4 a1,
+                                             const typename Code<VT>::V4 a2,
+                                             const typename Code<VT>::V4 a3, const float *xs,
+                                             float *my) {
+    uint32_t e[16];
+    unpack4(A.x, A.y, A.z, e);
+    unpack4(A.w, B.x, B.y, e + 4);
+    unpack4(B.z, B.w, C.x, e + 8);
+    unpack4(C.y, C.z, C.w, e + 12);
+    const typename Code<VT>::T av[16] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
+                                         a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+    window24<VT, 16>(e, av, xs, my);
 }
 
 // MODE 0: one batch at a time, the next column block staged after the
@@ -144,10 +187,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
                 const V4 a1 = __builtin_nontemporal_load(v4 + (4 * sb + 1) * kWave);
                 const V4 a2 = __builtin_nontemporal_load(v4 + (4 * sb + 2) * kWave);
                 const V4 a3 = __builtin_nontemporal_load(v4 + (4 * sb + 3) * kWave);
-                tile_batch24<VT>(A.x, A.y, A.z, a0, xs, my);
-                tile_batch24<VT>(A.w, B.x, B.y, a1, xs, my);
-                tile_batch24<VT>(B.z, B.w, C.x, a2, xs, my);
-                tile_batch24<VT>(C.y, C.z, C.w, a3, xs, my);
+                tile_super24<VT>(A, B, C, a0, a1, a2, a3, xs, my);
             }
             const uint32_t *q2 = p3 + static_cast<int64_t>(nsb) * 12 * kWave;
             const v2u *qa = reinterpret_cast<const v2u *>(q2) + lane;
@@ -230,164 +270,13 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     }
 }
 
-// MODE 3 (24-bit indices): before the barrier that ends a column block, every
-// thread loads its share of the next block of the gathered vector and then
-// the first super-batch of its wave's next list into registers, so that the
-// memory latency of both overlaps the barrier (the in-order load counter lets
-// the staging wait for the vector alone, which was issued first).
-template <int VT>
-__device__ __forceinline__ void tiled_body24p(const TileMap &M, int64_t tile,
-                                              const int32_t *__restrict__ pk,
-                                              const typename Code<VT>::T *__restrict__ val,
-                                              const int32_t *__restrict__ goff,
-                                              const float *__restrict__ x,
-                                              float *__restrict__ part) {
-    typedef typename Code<VT>::T T;
-    typedef typename Code<VT>::V4 V4;
-    extern __shared__ float lds[];
-    const int rw1 = M.rw + 1;
-    float *acc = lds;
-    const size_t acc_floats = (static_cast<size_t>(M.waves) * rw1 + 3) / 4 * 4;
-    float *xs = lds + acc_floats;
-
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int lane = tid & (kWave - 1);
-    const int slab = static_cast<int>(tile % M.ns);
-    const int64_t rb = tile / M.ns;
-    float *my = acc + w * rw1;
-
-    for (int i = tid; i < M.waves * rw1; i += nthr) acc[i] = 0.0f;
-    if (tid < 4) xs[M.cb + tid] = 0.0f;
-
-    const int cb0 = M.slab_begin[slab];
-    const int ncbs = M.slab_begin[slab + 1] - cb0;
-    const int64_t list0 = ((rb * M.ns + slab) * M.cbs_max) * M.waves + w;
-    const bool fits = M.cb <= kXPrefetch * 4 * nthr;
-
-    v4u PA = {0, 0, 0, 0}, PB = PA, PC = PA;
-    V4 P0{}, P1{}, P2{}, P3{};
-    auto prefetch = [&](int c) {
-        const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
-        const int g0 = goff[L];
-        const int ng = goff[L + 1] - g0;
-        if (ng >= 16) {
-            const v4u *qs = reinterpret_cast<const v4u *>(pk + M.poff[L]) + lane;
-            PA = __builtin_nontemporal_load(qs);
-            PB = __builtin_nontemporal_load(qs + kWave);
-            PC = __builtin_nontemporal_load(qs + 2 * kWave);
-            const V4 *v4 = reinterpret_cast<const V4 *>(val + static_cast<int64_t>(g0) * kWave) + lane;
-            P0 = __builtin_nontemporal_load(v4);
-            P1 = __builtin_nontemporal_load(v4 + kWave);
-            P2 = __builtin_nontemporal_load(v4 + 2 * kWave);
-            P3 = __builtin_nontemporal_load(v4 + 3 * kWave);
-        }
-    };
-
-    if (ncbs > 0) {
-        const int64_t col0 = static_cast<int64_t>(cb0) * M.cb;
-        const int64_t rem = M.n_cols - col0;
-        const int ncols = rem < M.cb ? static_cast<int>(rem) : M.cb;
-        for (int i4 = tid * 4; i4 < ncols; i4 += nthr * 4)
-            *reinterpret_cast<v4f *>(xs + i4) = *reinterpret_cast<const v4f *>(x + col0 + i4);
-        prefetch(0);
-    }
-    __syncthreads();
-
-    for (int c = 0; c < ncbs; ++c) {
-        const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
-        const int g0 = goff[L];
-        const int ng = goff[L + 1] - g0;
-        const int nb4 = ng >> 2, nsb = nb4 >> 2;
-        const uint32_t *p3 = reinterpret_cast<const uint32_t *>(pk + M.poff[L]);
-        const int64_t base = static_cast<int64_t>(g0) * kWave;
-        const V4 *v4 = reinterpret_cast<const V4 *>(val + base) + lane;
-        if (nsb > 0) {
-            tile_batch24<VT>(PA.x, PA.y, PA.z, P0, xs, my);
-            tile_batch24<VT>(PA.w, PB.x, PB.y, P1, xs, my);
-            tile_batch24<VT>(PB.z, PB.w, PC.x, P2, xs, my);
-            tile_batch24<VT>(PC.y, PC.z, PC.w, P3, xs, my);
-        }
-        const v4u *qs = reinterpret_cast<const v4u *>(p3) + lane;
-        for (int sb = 1; sb < nsb; ++sb) {
-            const v4u A = __builtin_nontemporal_load(qs + sb * 3 * kWave);
-            const v4u B = __builtin_nontemporal_load(qs + sb * 3 * kWave + kWave);
-            const v4u C = __builtin_nontemporal_load(qs + sb * 3 * kWave + 2 * kWave);
-            const V4 a0 = __builtin_nontemporal_load(v4 + (4 * sb) * kWave);
-            const V4 a1 = __builtin_nontemporal_load(v4 + (4 * sb + 1) * kWave);
-            const V4 a2 = __builtin_nontemporal_load(v4 + (4 * sb + 2) * kWave);
-            const V4 a3 = __builtin_nontemporal_load(v4 + (4 * sb + 3) * kWave);
-            tile_batch24<VT>(A.x, A.y, A.z, a0, xs, my);
-            tile_batch24<VT>(A.w, B.x, B.y, a1, xs, my);
-            tile_batch24<VT>(B.z, B.w, C.x, a2, xs, my);
-            tile_batch24<VT>(C.y, C.z, C.w, a3, xs, my);
-        }
-        const uint32_t *q2 = p3 + static_cast<int64_t>(nsb) * 12 * kWave;
-        const v2u *qa = reinterpret_cast<const v2u *>(q2) + lane;
-        const uint32_t *qb = q2 + 2 * kWave + lane;
-        for (int b = nsb * 4; b < nb4; ++b) {
-            const int rb4 = b - nsb * 4;
-            const v2u w01 = __builtin_nontemporal_load(qa + rb4 * (3 * kWave / 2));
-            const uint32_t w2 = __builtin_nontemporal_load(qb + rb4 * 3 * kWave);
-            const V4 a = __builtin_nontemporal_load(v4 + b * kWave);
-            tile_batch24<VT>(w01.x, w01.y, w2, a, xs, my);
-        }
-        const uint32_t *pt = p3 + static_cast<int64_t>(nb4) * 3 * kWave + lane;
-        const int64_t tail = base + static_cast<int64_t>(nb4) * 4 * kWave + lane;
-        for (int g = nb4 * 4; g < ng; ++g) {
-            const uint32_t p = __builtin_nontemporal_load(pt + (g - nb4 * 4) * kWave);
-            const T a = __builtin_nontemporal_load(val + tail + static_cast<int64_t>(g - nb4 * 4) * kWave);
-            const float t = xs[p & 0x3FFF];
-            my[p >> 14] = fmaf(Code<VT>::dec(a), t, my[p >> 14]);
-        }
-        if (c + 1 < ncbs) {
-            const int64_t ncol0 = static_cast<int64_t>(cb0 + c + 1) * M.cb;
-            const int64_t nrem = M.n_cols - ncol0;
-            const int nncols = nrem < M.cb ? static_cast<int>(nrem) : M.cb;
-            v4f xr[kXPrefetch];
-            if (fits) {
-#pragma unroll
-                for (int k = 0; k < kXPrefetch; ++k) {
-                    const int i4 = (k * nthr + tid) * 4;
-                    xr[k] = *reinterpret_cast<const v4f *>(x + ncol0 + (i4 < nncols ? i4 : 0));
-                }
-            }
-            prefetch(c + 1);
-            __syncthreads();   // every wave is done with this block
-            if (fits) {
-#pragma unroll
-                for (int k = 0; k < kXPrefetch; ++k) {
-                    const int i4 = (k * nthr + tid) * 4;
-                    if (i4 < nncols) *reinterpret_cast<v4f *>(xs + i4) = xr[k];
-                }
-            } else {
-                for (int i4 = tid * 4; i4 < nncols; i4 += nthr * 4)
-                    *reinterpret_cast<v4f *>(xs + i4) = *reinterpret_cast<const v4f *>(x + ncol0 + i4);
-            }
-            __syncthreads();
-        }
-    }
-    __syncthreads();
-    const int64_t rb_rows = static_cast<int64_t>(M.waves) * M.rw;
-    const int64_t row0 = rb * rb_rows;
-    float *out = part + static_cast<int64_t>(slab) * M.n_rows;
-    for (int64_t i = tid; i < rb_rows; i += nthr) {
-        const int64_t row = row0 + i;
-        if (row < M.n_rows) out[row] = acc[(i / M.rw) * rw1 + (i % M.rw)];
-    }
-}
-
 template <int VT, int MODE>
 __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__restrict__ pk,
                                                 const typename Code<VT>::T *__restrict__ val,
                                                 const int32_t *__restrict__ goff,
                                                 const float *__restrict__ x,
                                                 float *__restrict__ part) {
-    if (MODE == 3)
-        tiled_body24p<VT>(M, blockIdx.x, pk, val, goff, x, part);
-    else
-        tiled_body<VT, MODE == 3 ? 0 : MODE>(M, blockIdx.x, pk, val, goff, x, part);
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
 }
 
 // Many scans in one launch: workgroup b runs tile tiles[b].local of scan
@@ -402,12 +291,8 @@ __global__ __launch_bounds__(1024) void k_tiled_batch(const BatchTile *__restric
     // a reference, not a copy: fields (and the slab table indexed at run time)
     // are read with scalar loads instead of living in scratch memory
     const TileMap &M = maps[bt.scan];
-    if (MODE == 3 && M.idx24)
-        tiled_body24p<VT>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
-                          M.goff, xs[bt.scan], parts[bt.scan]);
-    else
-        tiled_body<VT, MODE == 3 ? 0 : MODE>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
-                                             M.goff, xs[bt.scan], parts[bt.scan]);
+    tiled_body<VT, MODE>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
+                         M.goff, xs[bt.scan], parts[bt.scan]);
 }
 
 // ratio_i = y_i / (sum_k part[k][i] + r_i), with optional FP64 partials of
@@ -498,7 +383,6 @@ static hipError_t launch_tiled_v(const TileMap &M, const float *x, float *part, 
     const bool fits = M.cb <= kXPrefetch * 4 * M.waves * kWave;
     if (M.variant == 1) return launch_tiled_t<VT, 1>(M, x, part, st);
     if (M.variant == 2 && fits) return launch_tiled_t<VT, 2>(M, x, part, st);
-    if (M.variant == 3 && M.idx24) return launch_tiled_t<VT, 3>(M, x, part, st);
     return launch_tiled_t<VT, 0>(M, x, part, st);
 }
 
@@ -531,8 +415,6 @@ hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const Til
     if (n_tiles == 0) return hipSuccess;
     if (variant == 1)
         return launch_tiled_batch_t<1>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
-    if (variant == 3)
-        return launch_tiled_batch_t<3>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
     return launch_tiled_batch_t<0>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
 }
 

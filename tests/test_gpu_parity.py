@@ -97,8 +97,6 @@ SCHEDULES = {
                             back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=2),
     "tiles-prefetch": dict(format=0, waves=8, fwd_rows_per_wave=128, fwd_block_cols=2048, fwd_slabs=2,
                            back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=3),
-    "tiles-lookahead": dict(format=0, waves=8, fwd_rows_per_wave=128, fwd_block_cols=2048, fwd_slabs=2,
-                            back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=4),
 }
 
 
