@@ -209,6 +209,15 @@ int sgtv_iterate_adaptive(sgtv_ctx ctx, int64_t max_iters, const sgtv_adaptive *
                           sgtv_check *checks, int32_t max_checks, int32_t *n_checks,
                           int64_t *iters_done, int *converged);
 
+/* Device memory: sgtv_workspace_bytes estimates (within about 25 % for
+ * random matrices of evenly spread entries; -1 for invalid arguments) what one context
+ * allocates for a system of I measurements, J hyper-voxels and nnz entries
+ * with the automatic schedule (both tiled copies of A, state, data, partial
+ * sums); sgtv_device_bytes reports what the context holds now.  The library
+ * allocates this memory itself at sgtv_set_system / sgtv_set_data. */
+int64_t sgtv_workspace_bytes(int64_t I, int64_t J, int64_t nnz, int storage_dtype);
+int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes);
+
 /* Normalised backprojection x_in = (A^T y) / (A^T 1) (0 where A^T 1 = 0),
  * J floats, of the data currently set. */
 int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);
@@ -322,6 +331,12 @@ void wsnet_destroy(wsnet net);
 int64_t wsnet_param_count(int32_t layers, int32_t channels);
 int wsnet_set_params(wsnet net, const float *params, int64_t n, int mem_kind);
 int wsnet_get_params(wsnet net, float *params, int64_t n, int mem_kind);
+/* Parameters to / from a file: a 24-byte header ("WSNT", version 1, layers,
+ * channels, parameter count as int32, int32, int32, int32, int64) and the FP32
+ * parameters; the Adam moments are not stored.  load requires a file of the
+ * same shape and resets Adam as set_params does. */
+int wsnet_save(wsnet net, const char *path);
+int wsnet_load(wsnet net, const char *path);
 /* x0 = network(x_in) for `batch` images (FP32 NHWC in and out). */
 int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int mem_kind);
 /* Start images for the reconstruction (the learned warm start).  For each of

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -1351,6 +1352,53 @@ int sgtv_get_split(sgtv_ctx ctx, float *d, float *c, int mem_kind) {
     return SGTV_OK;
 }
 
+int64_t sgtv_workspace_bytes(int64_t I, int64_t J, int64_t nnz, int storage_dtype) {
+    if (I < 0 || J < 0 || nnz < 0) return -1;
+    if (storage_dtype != SGTV_F32 && storage_dtype != SGTV_BF16 && storage_dtype != SGTV_F16) return -1;
+    const int64_t vb = storage_dtype == SGTV_F32 ? 4 : 2;
+    // one tiled copy with the automatic schedule: a list (rows of one wave x
+    // one column block) of E entries takes max(E / 64 + 1, longest row run)
+    // groups of 64, the run estimated for rows with lam entries per block
+    auto copy_bytes = [&](int64_t n_rows, int64_t n_cols, int64_t *slabs) -> double {
+        const TileParams t = choose_tiles(n_rows, n_cols, 16, 0, 0, 0);
+        *slabs = t.ns;
+        if (n_rows == 0 || n_cols == 0) return 0.0;
+        const double n_rb = std::ceil(static_cast<double>(n_rows) / (16.0 * t.rw));
+        const double ncb = std::ceil(static_cast<double>(n_cols) / t.cb);
+        const double lists = n_rb * ncb * 16.0;
+        const double lam = static_cast<double>(nnz) / n_rows * std::min<double>(t.cb, n_cols) / n_cols;
+        const double e = static_cast<double>(nnz) / lists;
+        const double groups = std::max(std::ceil(e / 64.0) + 1.0, std::ceil(lam + 2.5 * std::sqrt(lam) + 1.0));
+        const double stored = std::min(lists * 64.0 * groups, 64.0 * static_cast<double>(nnz) + 256.0);
+        const double idx_bytes = (t.rw >= 64 && t.rw <= 1024 && t.cb <= 16380) ? 3.0 : 4.0;
+        return stored * (idx_bytes + vb) + lists * 8.0;
+    };
+    int64_t ns_f = 1, ns_b = 1;
+    const double matrix = copy_bytes(I, J, &ns_f) + copy_bytes(J, I, &ns_b);
+    const int64_t vectors = 4 * (3 * J + 2 * 4 * J + 2 * J + 2 * J)   // f x2, fs, v x2, a x2, sens, H
+                            + 4 * 3 * I                                   // y, r, ratio
+                            + 4 * (ns_f * I + ns_b * J)                   // partial sums
+                            + (storage_dtype == SGTV_F32 ? 0 : 4 * J);    // column scales
+    return static_cast<int64_t>(matrix) + vectors + (1 << 20);
+}
+
+int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes) {
+    if (!ctx || !bytes) return fail(SGTV_EINVAL, "null argument");
+    int64_t b = 0;
+    for (const DBuf *d : {&ctx->y, &ctx->r, &ctx->ratio, &ctx->f[0], &ctx->f[1], &ctx->v[0], &ctx->v[1],
+                          &ctx->a[0], &ctx->a[1], &ctx->fs, &ctx->part, &ctx->red})
+        b += static_cast<int64_t>(d->bytes);
+    if (ctx->sys) {
+        const System &S = *ctx->sys;
+        for (const DBuf *d : {&S.rs_ptr, &S.rs_idx, &S.rs_val, &S.cs_ptr, &S.cs_idx, &S.cs_val, &S.colscale,
+                              &S.sens, &S.H, &S.wbuf, &S.fpart, &S.bpart, &S.fwd.pk, &S.fwd.val, &S.fwd.goff,
+                              &S.fwd.poff, &S.back.pk, &S.back.val, &S.back.goff, &S.back.poff})
+            b += static_cast<int64_t>(d->bytes);
+    }
+    *bytes = b;
+    return SGTV_OK;
+}
+
 int sgtv_state_sizes(sgtv_ctx ctx, int64_t *n_image, int64_t *n_split, int64_t *n_gr) {
     if (!ctx) return fail(SGTV_EINVAL, "null context");
     if (!ctx->sys) return fail(SGTV_ESTATE, "no system set");
@@ -1939,6 +1987,51 @@ int wsnet_get_params(wsnet net, float *params, int64_t n, int mem_kind) {
     HIP_TRY(hipMemcpyAsync(params, net->params.p, sizeof(float) * n, to_caller(mem_kind), net->stream));
     HIP_TRY(hipStreamSynchronize(net->stream));
     return SGTV_OK;
+}
+
+namespace {
+struct WsnetFileHeader {
+    char magic[4];          // "WSNT"
+    int32_t version;        // 1
+    int32_t layers, channels;
+    int64_t n_params;       // FP32 values that follow, little endian
+};
+}  // namespace
+
+int wsnet_save(wsnet net, const char *path) {
+    if (!net || !path) return fail(SGTV_EINVAL, "null argument");
+    if (!net->have_params) return fail(SGTV_ESTATE, "no parameters set (call wsnet_set_params)");
+    std::vector<float> h(static_cast<size_t>(net->n_param));
+    if (int e = wsnet_get_params(net, h.data(), net->n_param, SGTV_HOST)) return e;
+    WsnetFileHeader hd{{'W', 'S', 'N', 'T'}, 1, net->L, net->C, net->n_param};
+    std::FILE *fp = std::fopen(path, "wb");
+    if (!fp) return fail(SGTV_EINVAL, "cannot open the file for writing");
+    const bool ok = std::fwrite(&hd, sizeof(hd), 1, fp) == 1 &&
+                    std::fwrite(h.data(), sizeof(float), h.size(), fp) == h.size();
+    const bool closed = std::fclose(fp) == 0;
+    if (!ok || !closed) return fail(SGTV_EINVAL, "writing the file failed");
+    return SGTV_OK;
+}
+
+int wsnet_load(wsnet net, const char *path) {
+    if (!net || !path) return fail(SGTV_EINVAL, "null argument");
+    std::FILE *fp = std::fopen(path, "rb");
+    if (!fp) return fail(SGTV_EINVAL, "cannot open the file for reading");
+    WsnetFileHeader hd{};
+    std::vector<float> h;
+    bool ok = std::fread(&hd, sizeof(hd), 1, fp) == 1 && std::memcmp(hd.magic, "WSNT", 4) == 0 &&
+              hd.version == 1;
+    if (ok && (hd.layers != net->L || hd.channels != net->C || hd.n_params != net->n_param)) {
+        std::fclose(fp);
+        return fail(SGTV_ESHAPE, "the file holds a network of another shape");
+    }
+    if (ok) {
+        h.resize(static_cast<size_t>(hd.n_params));
+        ok = std::fread(h.data(), sizeof(float), h.size(), fp) == h.size();
+    }
+    std::fclose(fp);
+    if (!ok) return fail(SGTV_EINVAL, "not a network file, or truncated");
+    return wsnet_set_params(net, h.data(), net->n_param, SGTV_HOST);
 }
 
 int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int mem_kind) {

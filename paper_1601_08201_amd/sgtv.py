@@ -121,6 +121,10 @@ def lib():
             "wsnet_reset_adam": (_I, [_P]),
             "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_set_penalty": (_I, [_P, _D]),
+            "sgtv_workspace_bytes": (_I64, [_I64, _I64, _I64, _I]),
+            "sgtv_device_bytes": (_I, [_P, ctypes.POINTER(_I64)]),
+            "wsnet_save": (_I, [_P, ctypes.c_char_p]),
+            "wsnet_load": (_I, [_P, ctypes.c_char_p]),
             "sgtv_get_penalty": (_I, [_P, ctypes.POINTER(_D)]),
             "sgtv_iterate_adaptive": (_I, [_P, _I64, ctypes.POINTER(Adaptive), ctypes.POINTER(Check), _I32,
                                            ctypes.POINTER(_I32), ctypes.POINTER(_I64), ctypes.POINTER(_I)]),
@@ -257,6 +261,17 @@ def sgtv_get_split(ctx):
     d, c = np.empty(n_split, np.float32), np.empty(n_split, np.float32)
     _check(lib().sgtv_get_split(ctx, d.ctypes.data_as(_P), c.ctypes.data_as(_P), SGTV_HOST))
     return d, c
+
+
+def sgtv_workspace_bytes(I, J, nnz, storage="f32"):
+    return int(lib().sgtv_workspace_bytes(int(I), int(J), int(nnz), STORAGE[storage]
+                                          if isinstance(storage, str) else int(storage)))
+
+
+def sgtv_device_bytes(ctx):
+    b = _I64()
+    _check(lib().sgtv_device_bytes(ctx, ctypes.byref(b)))
+    return b.value
 
 
 def sgtv_set_penalty(ctx, rho):
@@ -400,6 +415,9 @@ class Reconstructor:
     def set_penalty(self, rho):
         sgtv_set_penalty(self._ctx, rho)
         return self
+
+    def device_bytes(self):
+        return sgtv_device_bytes(self._ctx)
 
     def penalty(self):
         return sgtv_get_penalty(self._ctx)
@@ -634,6 +652,14 @@ class WarmStartNet:
         if out is None:
             out = np.empty((b,) + self.shape, np.float32) if not _is_torch_cuda(x_in) else x_in.new_empty(x_in.shape)
         return wsnet_forward(self._n, x_in, b, out)
+
+    def save(self, path):
+        _check(lib().wsnet_save(self._n, os.fsencode(path)))
+        return self
+
+    def load(self, path):
+        _check(lib().wsnet_load(self._n, os.fsencode(path)))
+        return self
 
     def start(self, f, mode="ratio", c_out=1.0, out=None):
         """Start images x0 from images f (see wsnet_start): mode "ratio" gives

@@ -45,3 +45,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sgtv, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         sgtv.lib()
+
+
+def test_workspace_query_runs_on_the_host():
+    from paper_1601_08201_amd import sgtv
+    small = sgtv.sgtv_workspace_bytes(4096, 8192, 131072, "f32")
+    big = sgtv.sgtv_workspace_bytes(1 << 20, 1 << 21, 1 << 27, "f32")
+    half = sgtv.sgtv_workspace_bytes(1 << 20, 1 << 21, 1 << 27, "bf16")
+    assert 0 < small < big and half < big
+    # the two tiled copies of A dominate the paper-scale scan: about 2 x 1.08 x nnz x 7 bytes
+    assert 1.9e9 < big < 2.6e9
+    assert sgtv.sgtv_workspace_bytes(-1, 1, 1, "f32") == -1
+    assert sgtv.sgtv_workspace_bytes(1, 1, 1, 7) == -1

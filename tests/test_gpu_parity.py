@@ -360,3 +360,18 @@ def test_dual_consistent_start_is_near_fixed_point(sg):
     print("moved: consistent", moved_dual, "zero", moved_zero, flush=True)
     assert moved_dual < 0.1 * moved_zero
     assert abs(phi_dual - phi_star) <= 1e-5 * phi_star
+
+
+@pytest.mark.parametrize("cfg,storage", [("small", "f32"), ("warmstart", "f32"), ("warmstart", "bf16")])
+def test_workspace_estimate_and_device_bytes(sg, cfg, storage):
+    prob = datagen.make_problem(cfg, 2)
+    est = sg.sgtv_workspace_bytes(prob.I, prob.J, prob.nnz, storage)
+    R = sg.Reconstructor()
+    R.set_problem(prob, storage=storage)
+    held = R.device_bytes()
+    print("workspace", cfg, storage, "estimate", est, "held", held, flush=True)
+    assert held > 0
+    if cfg != "small":     # the fixed 1 MiB of scratch dominates tiny systems
+        assert abs(est - held) <= 0.25 * held
+    assert sg.sgtv_workspace_bytes(-1, 1, 1) == -1
+    R.close()

@@ -205,3 +205,22 @@ def test_start_rejects_bad_arguments(sg):
         N.start(f, "ratio", float("nan"))
     with pytest.raises(sg.SgtvError):
         N.start(np.ones((3, 8, 64, 64), np.float32), "ratio", 1.0)
+
+
+def test_save_and_load_round_trip(sg, tmp_path):
+    p = layer_params(sg, 2, 9)
+    N = sg.WarmStartNet(layers=2, height=8, max_batch=2).set_params(p)
+    path = tmp_path / "net.bin"
+    N.save(path)
+    assert path.stat().st_size == 24 + 4 * p.size
+    M = sg.WarmStartNet(layers=2, height=8, max_batch=2)
+    M.load(path)
+    np.testing.assert_array_equal(M.params(), p)
+    x, _ = data(12, B=2)
+    np.testing.assert_array_equal(M.forward(x), N.forward(x))
+    with pytest.raises(sg.SgtvError):
+        sg.WarmStartNet(layers=3, height=8, max_batch=2).load(path)     # other shape
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a network")
+    with pytest.raises(sg.SgtvError):
+        M.load(bad)
