@@ -165,8 +165,8 @@ int64_t next_pow2(int64_t v) {
 
 // Automatic schedule: column blocks of up to 16380 entries, slabs so that one
 // slab of the gathered vector is at most 2 MiB (an XCD's 4 MiB L2 keeps it
-// next to the streamed entries), and
-// rows per wave so that the grid has at least 256 workgroups (one per CU).
+// next to the streamed entries), then more slabs and fewer rows per wave until
+// the grid has at least 256 workgroups (one per CU).
 TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int cb, int ns) {
     TileParams t;
     t.waves = waves > 0 ? waves : 16;
@@ -184,8 +184,16 @@ TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int c
     if (rw > 0) {
         t.rw = rw;
     } else {
+        // until there is a tile for every CU: more slabs first (up to 8, each
+        // slab keeps its XCDs and its slice of the vector in L2), then shorter
+        // tiles (long lists keep the packing dense)
         int r = 1024;
-        while (r > 64 && ((n_rows + int64_t(t.waves) * r - 1) / (int64_t(t.waves) * r)) * t.ns < 256) r >>= 1;
+        auto tiles = [&](int rr) { return ((n_rows + int64_t(t.waves) * rr - 1) / (int64_t(t.waves) * rr)) * t.ns; };
+        while (tiles(r) < 256) {
+            if (ns <= 0 && t.ns < 8 && 2 * t.ns <= ncb) t.ns *= 2;
+            else if (r > 64) r >>= 1;
+            else break;
+        }
         t.rw = r;
     }
     return t;
