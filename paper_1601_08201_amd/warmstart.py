@@ -165,7 +165,7 @@ def training_targets(xin, tgt, mode):
 
 
 def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, lr_min=1e-5, seed=0,
-          log=None, device=0):
+          log=None, device=0, layers=6):
     """Adam on the mean squared error of the scaled targets; cosine learning rate."""
     import torch
     dev = torch.device("cuda", device)
@@ -177,8 +177,8 @@ def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, 
     N = X.shape[0]
     H, W, C = X.shape[1:]
     net = sgtv.WarmStartNet(device=device, stream=torch.cuda.current_stream(dev).cuda_stream,
-                            layers=6, height=H, width=W, channels=C, max_batch=batch)
-    net.set_params(sgtv.init_params(6, C, seed))
+                            layers=layers, height=H, width=W, channels=C, max_batch=batch)
+    net.set_params(sgtv.init_params(layers, C, seed))
     rng = np.random.default_rng(seed)
     steps = epochs * (N // batch)
     step = 0
@@ -199,7 +199,7 @@ def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, 
         history.append(tot / max(N // batch, 1))
         if log and (ep + 1) % 5 == 0:
             log("train: epoch %d / %d, loss %.5f (%.1fs)" % (ep + 1, epochs, history[-1], time.time() - t0))
-    model = Model(net.params(), c_out, mode, int(input_iters))
+    model = Model(net.params(), c_out, mode, int(input_iters), int(layers))
     return model, net, history
 
 
