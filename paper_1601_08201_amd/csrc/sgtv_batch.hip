@@ -27,14 +27,20 @@ __global__ __launch_bounds__(kBlock) void k_voxel_batch(const BatchBlock *__rest
     const ScanDev &S = scans[bb.scan];
     const int64_t j = bb.start + threadIdx.x;
     if (j >= S.grid.J) return;
-    float e = S.bpart[j];
-    for (int k = 1; k < S.ns_b; ++k) e += S.bpart[static_cast<int64_t>(k) * S.grid.J + j];
+    auto e = [&]() {
+        float s = S.bpart[j];
+        for (int k = 1; k < S.ns_b; ++k) s += S.bpart[static_cast<int64_t>(k) * S.grid.J + j];
+        return s;
+    };
+    const float *g = S.f[fcur], *v = S.v[vcur], *a = S.a[vcur];
+    float gnew;
     if (S.grouping == 0)
-        S.f[fcur ^ 1][j] = voxel_update_value<0>(j, e, S.f[fcur], S.v[vcur], S.a[vcur], S.sens, S.H,
-                                                 S.grid, S.wts, S.lam);
+        gnew = S.wts.full ? voxel_update_value<0, true>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam)
+                          : voxel_update_value<0, false>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam);
     else
-        S.f[fcur ^ 1][j] = voxel_update_value<1>(j, e, S.f[fcur], S.v[vcur], S.a[vcur], S.sens, S.H,
-                                                 S.grid, S.wts, S.lam);
+        gnew = S.wts.full ? voxel_update_value<1, true>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam)
+                          : voxel_update_value<1, false>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam);
+    S.f[fcur ^ 1][j] = gnew;
 }
 
 // split and dual update, one segment of 2^seg_log2 lanes per spatial bin
@@ -46,12 +52,16 @@ __global__ __launch_bounds__(kBlock) void k_split_batch(const BatchBlock *__rest
     const int sl = S.seg_log2;
     const int64_t s = bb.start + (threadIdx.x >> sl);
     const int ls = threadIdx.x & ((1 << sl) - 1);
-    if (S.grouping == 0)
-        split_bin<0>(s, s < S.grid.S, ls, sl, S.f[fcur], S.v[vcur], S.a[vcur], S.v[vcur ^ 1],
-                     S.a[vcur ^ 1], S.grid, S.wts, S.thr);
-    else
-        split_bin<1>(s, s < S.grid.S, ls, sl, S.f[fcur], S.v[vcur], S.a[vcur], S.v[vcur ^ 1],
-                     S.a[vcur ^ 1], S.grid, S.wts, S.thr);
+    const float *f = S.f[fcur], *v = S.v[vcur], *a = S.a[vcur];
+    float *vn = S.v[vcur ^ 1], *an = S.a[vcur ^ 1];
+    const bool act = s < S.grid.S;
+    if (S.grouping == 0) {
+        if (S.wts.full) split_bin<0, true>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+        else split_bin<0, false>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+    } else {
+        if (S.wts.full) split_bin<1, true>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+        else split_bin<1, false>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+    }
 }
 
 hipError_t launch_ratio_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,

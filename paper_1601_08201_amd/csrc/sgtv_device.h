@@ -75,6 +75,38 @@ __device__ __forceinline__ float weight(const Weights &w, const Grid &g, int64_t
     return w.full ? w.full[(s * 4 + p) * g.Q + q] : w.w[p];
 }
 
+// The same with the kind of weights fixed at compile time (no branch).
+template <bool WFULL>
+__device__ __forceinline__ float weight_t(const Weights &w, const Grid &g, int64_t s, int p, int q) {
+    return WFULL ? w.full[(s * 4 + p) * g.Q + q] : w.w[p];
+}
+
+// Spatial bin s = j / Q, spectral bin q and grid position (iy, ix) of
+// hyper-voxel j; 32-bit divisions whenever the grid allows them.
+struct VoxelPos {
+    int64_t s;
+    int q, iy, ix;
+};
+
+__device__ __forceinline__ VoxelPos voxel_pos(int64_t j, const Grid &g) {
+    VoxelPos r;
+    if (g.J <= 0x7FFFFFFF) {
+        const uint32_t jj = static_cast<uint32_t>(j);
+        const uint32_t Q = static_cast<uint32_t>(g.Q), nx = static_cast<uint32_t>(g.nx);
+        const uint32_t s = jj / Q, iy = s / nx;
+        r.s = s;
+        r.q = static_cast<int>(jj - s * Q);
+        r.iy = static_cast<int>(iy);
+        r.ix = static_cast<int>(s - iy * nx);
+    } else {
+        r.s = j / g.Q;
+        r.q = static_cast<int>(j - r.s * g.Q);
+        r.iy = static_cast<int>(r.s / g.nx);
+        r.ix = static_cast<int>(r.s - static_cast<int64_t>(r.iy) * g.nx);
+    }
+    return r;
+}
+
 // Nonnegative root of H t^2 + B t - C = 0, C >= 0, H > 0; branch chosen so
 // neither form subtracts nearly equal numbers.
 __device__ __forceinline__ float voxel_root(float H, float B, float C) {
@@ -87,40 +119,46 @@ __device__ __forceinline__ float voxel_root(float H, float B, float C) {
 //   gamma = lam * (D^T t)_j, t = w.*G g - d + c = w.*G g + v - 2 a v   (z = d - c)
 //   B = sens_j + gamma - lam H0_j g_j,  C = g_j e
 // the new value is the nonnegative root of (lam H0_j) t^2 + B t - C.
-template <int GROUPING>
-__device__ __forceinline__ float voxel_update_value(int64_t j, float e, const float *__restrict__ g,
+// Every load is issued whatever the position of the voxel: a neighbour outside
+// the grid reads the voxel's own bin and its terms are then discarded, so the
+// loads need no branches.  e = (A^T ratio)_j comes from the callable E, called
+// after the stencil loads are issued so that its own loads overlap them.
+template <int GROUPING, bool WFULL, class E>
+__device__ __forceinline__ float voxel_update_value(int64_t j, E e_of, const float *__restrict__ g,
                                                     const float *__restrict__ v,
                                                     const float *__restrict__ a,
                                                     const float *__restrict__ sens,
                                                     const float *__restrict__ H, const Grid &grid,
                                                     const Weights &wts, float lam) {
     const int Q = grid.Q;
-    const int64_t s = j / Q;
-    const int q = static_cast<int>(j - s * Q);
-    const int iy = static_cast<int>(s / grid.nx), ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
+    const VoxelPos P = voxel_pos(j, grid);
+    const int64_t s = P.s;
+    const int q = P.q;
     const float gs = g[j];
     const float as = GROUPING == 0 ? a[s] : a[j];
     float dt = 0.0f;   // (D^T t)_j
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        const int64_t nb = neighbour(grid, s, iy, ix, p);
-        const float gn = nb >= 0 ? g[nb * Q + q] : 0.0f;
-        const float wp = weight(wts, grid, s, p, q);
+        const int64_t nb = neighbour(grid, s, P.iy, P.ix, p);
+        const bool in = nb >= 0;
+        const int64_t nc = in ? nb : s;
+        const float gl = g[nc * Q + q];
+        const float gn = in ? gl : 0.0f;
+        const float wp = weight_t<WFULL>(wts, grid, s, p, q);
         const float vs = v[(s * 4 + p) * Q + q];
         const float ds = as * vs;
         dt = fmaf(wp, fmaf(wp, gs - gn, vs - 2.0f * ds), dt);
-        if (nb >= 0) {
-            const int pb = p ^ 1;   // direction from the neighbour back to s
-            const float wn = weight(wts, grid, nb, pb, q);
-            const float vn = v[(nb * 4 + pb) * Q + q];
-            const float an = GROUPING == 0 ? a[nb] : a[nb * Q + q];
-            const float dn = an * vn;
-            dt = fmaf(-wn, fmaf(wn, gn - gs, vn - 2.0f * dn), dt);
-        }
+        const int pb = p ^ 1;   // direction from the neighbour back to s
+        const float wn = weight_t<WFULL>(wts, grid, nc, pb, q);
+        const float vn = v[(nc * 4 + pb) * Q + q];
+        const float an = GROUPING == 0 ? a[nc] : a[nc * Q + q];
+        const float dn = an * vn;
+        const float dtn = fmaf(-wn, fmaf(wn, gn - gs, vn - 2.0f * dn), dt);
+        dt = in ? dtn : dt;
     }
     const float h = lam * H[j];
     const float B = sens[j] + lam * dt - h * gs;
-    const float C = gs * e;
+    const float C = gs * e_of();
     return voxel_root(h, B, C);
 }
 
@@ -133,7 +171,7 @@ __device__ __forceinline__ float shrink_factor(float nrm, float thr) {
 // then the shrink factor of the group (Eq. 5).  Every lane of the wave must
 // call this (the segment reduction shuffles), with active = false for bins
 // past the end.
-template <int GROUPING>
+template <int GROUPING, bool WFULL>
 __device__ __forceinline__ void split_bin(int64_t s, bool active, int ls, int seg_log2,
                                           const float *__restrict__ f,
                                           const float *__restrict__ v_old,
@@ -144,22 +182,40 @@ __device__ __forceinline__ void split_bin(int64_t s, bool active, int ls, int se
     const int Q = grid.Q;
     float ss = 0.0f;
     if (active) {
-        const int iy = static_cast<int>(s / grid.nx), ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
-        int64_t nb[4];
+        int iy, ix;
+        if (grid.S <= 0x7FFFFFFF) {
+            const uint32_t s32 = static_cast<uint32_t>(s), nx = static_cast<uint32_t>(grid.nx);
+            const uint32_t y = s32 / nx;
+            iy = static_cast<int>(y);
+            ix = static_cast<int>(s32 - y * nx);
+        } else {
+            iy = static_cast<int>(s / grid.nx);
+            ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
+        }
+        // a neighbour outside the grid reads the bin itself; its value is then
+        // replaced by 0, so the loads need no branches
+        int64_t nc[4];
+        bool in[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) nb[p] = neighbour(grid, s, iy, ix, p);
+        for (int p = 0; p < 4; ++p) {
+            const int64_t nb = neighbour(grid, s, iy, ix, p);
+            in[p] = nb >= 0;
+            nc[p] = in[p] ? nb : s;
+        }
         const float ag = GROUPING == 0 ? a_old[s] : 0.0f;
+#pragma unroll 2
         for (int q = ls; q < Q; q += G) {
             const float fs = f[s * Q + q];
             const float aq = GROUPING == 0 ? ag : a_old[s * Q + q];
             float sq = 0.0f;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const float fn = nb[p] >= 0 ? f[nb[p] * Q + q] : 0.0f;
+                const float fl = f[nc[p] * Q + q];
+                const float fn = in[p] ? fl : 0.0f;
                 const int64_t o = (s * 4 + p) * Q + q;
                 const float vo = v_old[o];
                 const float c_old = vo - aq * vo;
-                const float vn = fmaf(weight(wts, grid, s, p, q), fs - fn, c_old);
+                const float vn = fmaf(weight_t<WFULL>(wts, grid, s, p, q), fs - fn, c_old);
                 v_new[o] = vn;
                 sq = fmaf(vn, vn, sq);
             }

@@ -117,7 +117,10 @@ __global__ __launch_bounds__(kBlock) void k_back_update(
     const int64_t j = slice * kWave + lane;
     if (j >= grid.J) return;
     if (VT != 0) e *= scale[j];
-    const float gnew = voxel_update_value<GROUPING>(j, e, g, v, a, sens, H, grid, wts, lam);
+    auto e_of = [e]() { return e; };
+    const float gnew = wts.full
+        ? voxel_update_value<GROUPING, true>(j, e_of, g, v, a, sens, H, grid, wts, lam)
+        : voxel_update_value<GROUPING, false>(j, e_of, g, v, a, sens, H, grid, wts, lam);
     g_next[j] = gnew;
     if (VT != 0) gs_next[j] = gnew * scale[j];
 }
@@ -127,14 +130,15 @@ __global__ __launch_bounds__(kBlock) void k_back_update(
 // v_new = w.*G f + c_old with c_old = v_old - a_old v_old; then the shrink
 // factor of the group.  Spectral grouping reduces over the segment; the
 // standard grouping keeps one factor per (s, q).
-template <int GROUPING>
+template <int GROUPING, bool WFULL>
 __global__ __launch_bounds__(kBlock) void k_split_update(
     const float *__restrict__ f, const float *__restrict__ v_old, const float *__restrict__ a_old,
     float *__restrict__ v_new, float *__restrict__ a_new, Grid grid, Weights wts, float thr,
     int seg_log2) {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock >> seg_log2) + (threadIdx.x >> seg_log2);
     const int ls = threadIdx.x & ((1 << seg_log2) - 1);
-    split_bin<GROUPING>(s, s < grid.S, ls, seg_log2, f, v_old, a_old, v_new, a_new, grid, wts, thr);
+    split_bin<GROUPING, WFULL>(s, s < grid.S, ls, seg_log2, f, v_old, a_old, v_new, a_new, grid, wts,
+                               thr);
 }
 
 template <int GROUPING>
@@ -385,12 +389,10 @@ hipError_t launch_split_update(const float *f, const float *v_old, const float *
     const int sl = seg_log2_for(grid.Q);
     const unsigned nb = blocks_for(grid.S, kBlock >> sl);
     if (nb == 0) return hipSuccess;
-    if (grouping == 0)
-        hipLaunchKernelGGL(k_split_update<0>, dim3(nb), dim3(kBlock), 0, st, f, v_old, a_old,
-                           v_new, a_new, grid, w, thr, sl);
-    else
-        hipLaunchKernelGGL(k_split_update<1>, dim3(nb), dim3(kBlock), 0, st, f, v_old, a_old,
-                           v_new, a_new, grid, w, thr, sl);
+    auto kern = grouping == 0 ? (w.full ? k_split_update<0, true> : k_split_update<0, false>)
+                              : (w.full ? k_split_update<1, true> : k_split_update<1, false>);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, f, v_old, a_old, v_new, a_new, grid, w,
+                       thr, sl);
     return hipGetLastError();
 }
 

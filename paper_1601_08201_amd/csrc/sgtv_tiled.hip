@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_back_combine(const float *__restrict
     }
 }
 
-template <int GROUPING>
+template <int GROUPING, bool WFULL>
 __global__ __launch_bounds__(kBlock) void k_voxel_update(
     const float *__restrict__ part, int ns, const float *__restrict__ scale,
     const float *__restrict__ g, float *__restrict__ g_next, float *__restrict__ gs_next,
@@ -341,10 +341,12 @@ __global__ __launch_bounds__(kBlock) void k_voxel_update(
     const int64_t n = grid.J;
     for (int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * kBlock) {
-        float e = part[j];
-        for (int k = 1; k < ns; ++k) e += part[static_cast<int64_t>(k) * n + j];
-        if (scale) e *= scale[j];
-        const float gnew = voxel_update_value<GROUPING>(j, e, g, v, a, sens, H, grid, wts, lam);
+        auto e_of = [&]() {
+            float e = part[j];
+            for (int k = 1; k < ns; ++k) e += part[static_cast<int64_t>(k) * n + j];
+            return scale ? e * scale[j] : e;
+        };
+        const float gnew = voxel_update_value<GROUPING, WFULL>(j, e_of, g, v, a, sens, H, grid, wts, lam);
         g_next[j] = gnew;
         if (gs_next) gs_next[j] = gnew * scale[j];
     }
@@ -444,12 +446,10 @@ hipError_t launch_voxel_update(const float *part, int ns, const float *scale, co
                                const float *sens, const float *H, const Grid &grid,
                                const Weights &w, int grouping, float lam, hipStream_t st) {
     const unsigned nb = stride_blocks(grid.J);
-    if (grouping == 0)
-        hipLaunchKernelGGL(k_voxel_update<0>, dim3(nb), dim3(kBlock), 0, st, part, ns, scale, g,
-                           g_next, gs_next, v, a, sens, H, grid, w, lam);
-    else
-        hipLaunchKernelGGL(k_voxel_update<1>, dim3(nb), dim3(kBlock), 0, st, part, ns, scale, g,
-                           g_next, gs_next, v, a, sens, H, grid, w, lam);
+    auto kern = grouping == 0 ? (w.full ? k_voxel_update<0, true> : k_voxel_update<0, false>)
+                              : (w.full ? k_voxel_update<1, true> : k_voxel_update<1, false>);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, part, ns, scale, g, g_next, gs_next, v,
+                       a, sens, H, grid, w, lam);
     return hipGetLastError();
 }
 
