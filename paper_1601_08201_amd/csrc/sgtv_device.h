@@ -82,28 +82,22 @@ __device__ __forceinline__ float weight_t(const Weights &w, const Grid &g, int64
 }
 
 // Spatial bin s = j / Q, spectral bin q and grid position (iy, ix) of
-// hyper-voxel j; 32-bit divisions whenever the grid allows them.
+// hyper-voxel j, with 32-bit divisions: J < 2^31 is checked when the system
+// is set.
 struct VoxelPos {
     int64_t s;
     int q, iy, ix;
 };
 
 __device__ __forceinline__ VoxelPos voxel_pos(int64_t j, const Grid &g) {
+    const uint32_t jj = static_cast<uint32_t>(j);
+    const uint32_t Q = static_cast<uint32_t>(g.Q), nx = static_cast<uint32_t>(g.nx);
+    const uint32_t s = jj / Q, iy = s / nx;
     VoxelPos r;
-    if (g.J <= 0x7FFFFFFF) {
-        const uint32_t jj = static_cast<uint32_t>(j);
-        const uint32_t Q = static_cast<uint32_t>(g.Q), nx = static_cast<uint32_t>(g.nx);
-        const uint32_t s = jj / Q, iy = s / nx;
-        r.s = s;
-        r.q = static_cast<int>(jj - s * Q);
-        r.iy = static_cast<int>(iy);
-        r.ix = static_cast<int>(s - iy * nx);
-    } else {
-        r.s = j / g.Q;
-        r.q = static_cast<int>(j - r.s * g.Q);
-        r.iy = static_cast<int>(r.s / g.nx);
-        r.ix = static_cast<int>(r.s - static_cast<int64_t>(r.iy) * g.nx);
-    }
+    r.s = s;
+    r.q = static_cast<int>(jj - s * Q);
+    r.iy = static_cast<int>(iy);
+    r.ix = static_cast<int>(s - iy * nx);
     return r;
 }
 
@@ -182,16 +176,11 @@ __device__ __forceinline__ void split_bin(int64_t s, bool active, int ls, int se
     const int Q = grid.Q;
     float ss = 0.0f;
     if (active) {
-        int iy, ix;
-        if (grid.S <= 0x7FFFFFFF) {
-            const uint32_t s32 = static_cast<uint32_t>(s), nx = static_cast<uint32_t>(grid.nx);
-            const uint32_t y = s32 / nx;
-            iy = static_cast<int>(y);
-            ix = static_cast<int>(s32 - y * nx);
-        } else {
-            iy = static_cast<int>(s / grid.nx);
-            ix = static_cast<int>(s - static_cast<int64_t>(iy) * grid.nx);
-        }
+        // 32-bit division: J < 2^31 is checked when the system is set
+        const uint32_t s32 = static_cast<uint32_t>(s), nx = static_cast<uint32_t>(grid.nx);
+        const uint32_t y = s32 / nx;
+        const int iy = static_cast<int>(y);
+        const int ix = static_cast<int>(s32 - y * nx);
         // a neighbour outside the grid reads the bin itself; its value is then
         // replaced by 0, so the loads need no branches
         int64_t nc[4];
