@@ -61,6 +61,20 @@ __device__ __forceinline__ void block_sum_store(double v, double *out) {
     }
 }
 
+// ---------------------------------------------------------------- block order
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  This
+// renumbers them so that the workgroups of one XCD cover one contiguous range
+// of the grid: stencil neighbours (the next spatial bin, the next grid row)
+// are then read through the same L2 instead of being fetched again by another
+// XCD.  A bijection of [0, gridDim.x) for any grid size.
+constexpr unsigned kXcds = 8;
+
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned n = gridDim.x, b = blockIdx.x;
+    const unsigned x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // ---------------------------------------------------------------- geometry
 __device__ __forceinline__ int64_t neighbour(const Grid &g, int64_t s, int iy, int ix, int p) {
     switch (p) {

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_split_update(
     const float *__restrict__ f, const float *__restrict__ v_old, const float *__restrict__ a_old,
     float *__restrict__ v_new, float *__restrict__ a_new, Grid grid, Weights wts, float thr,
     int seg_log2) {
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock >> seg_log2) + (threadIdx.x >> seg_log2);
+    const int64_t s = static_cast<int64_t>(xcd_block()) * (kBlock >> seg_log2) + (threadIdx.x >> seg_log2);
     const int ls = threadIdx.x & ((1 << seg_log2) - 1);
     split_bin<GROUPING, WFULL>(s, s < grid.S, ls, seg_log2, f, v_old, a_old, v_new, a_new, grid, wts,
                                thr);

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_voxel_update(
     const float *__restrict__ v, const float *__restrict__ a, const float *__restrict__ sens,
     const float *__restrict__ H, Grid grid, Weights wts, float lam) {
     const int64_t n = grid.J;
-    for (int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; j < n;
+    for (int64_t j = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * kBlock) {
         auto e_of = [&]() {
             float e = part[j];
