@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kBlock) void k_ratio_batch(const BatchBlock *__rest
 __global__ __launch_bounds__(kBlock) void k_voxel_batch(const BatchBlock *__restrict__ blocks,
                                                         const ScanDev *__restrict__ scans,
                                                         int fcur, int vcur) {
-    const BatchBlock bb = blocks[xcd_block()];
+    const BatchBlock bb = blocks[blockIdx.x];
     const ScanDev &S = scans[bb.scan];
     const int64_t j = bb.start + threadIdx.x;
     if (j >= S.grid.J) return;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_voxel_batch(const BatchBlock *__rest
 __global__ __launch_bounds__(kBlock) void k_split_batch(const BatchBlock *__restrict__ blocks,
                                                         const ScanDev *__restrict__ scans,
                                                         int fcur, int vcur) {
-    const BatchBlock bb = blocks[xcd_block()];
+    const BatchBlock bb = blocks[blockIdx.x];
     const ScanDev &S = scans[bb.scan];
     const int sl = S.seg_log2;
     const int64_t s = bb.start + (threadIdx.x >> sl);

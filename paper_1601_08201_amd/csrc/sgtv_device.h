@@ -66,7 +66,9 @@ __device__ __forceinline__ void block_sum_store(double v, double *out) {
 // renumbers them so that the workgroups of one XCD cover one contiguous range
 // of the grid: stencil neighbours (the next spatial bin, the next grid row)
 // are then read through the same L2 instead of being fetched again by another
-// XCD.  A bijection of [0, gridDim.x) for any grid size.
+// XCD.  A bijection of [0, gridDim.x) for any grid size.  Used by the
+// single-scan image and split updates; the batched ones, whose grids are
+// twenty times longer, run faster in dispatch order.
 constexpr unsigned kXcds = 8;
 
 __device__ __forceinline__ unsigned xcd_block() {
