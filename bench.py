@@ -127,6 +127,7 @@ def batch_main(args):
         list(ex.map(lambda p: B.add_scan(p, sched), probs))
     log("batch built in %.1fs (schedule %s)" % (time.time() - t0, sched))
     B.iterate(args.warmup)
+    B.prepare(args.steps)   # graph capture outside the timed region
     torch.cuda.synchronize()
     ev = lambda: torch.cuda.Event(enable_timing=True)
     a, b = ev(), ev()
@@ -146,6 +147,7 @@ def batch_main(args):
     log("sequential reference built in %.1fs (%d scans with tuned schedules)"
         % (time.time() - t0, sum(x is not None for x in scheds)))
     Bs.iterate_sequential(args.warmup)
+    Bs.prepare(args.steps, sequential=True)
     torch.cuda.synchronize()
     a.record(stream)
     Bs.iterate_sequential(args.steps)
@@ -201,6 +203,7 @@ def sweep_main(args):
             B.add_scan(prob, w=w, grouping=g, beta=b)
         it = B.iterate_sequential if sequential else B.iterate
         it(args.warmup)
+        B.prepare(args.steps, sequential=sequential)   # graph capture outside the timed region
         torch.cuda.synchronize()
         a, e = ev(), ev()
         a.record(stream)
@@ -501,6 +504,7 @@ def main():
     log("system and data set in %.1fs" % (time.time() - t0))
 
     R.iterate(args.warmup)
+    R.prepare(args.steps)   # graph capture outside the timed region
     torch.cuda.synchronize()
     log("warmup done")
 

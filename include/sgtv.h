@@ -139,6 +139,16 @@ int sgtv_set_init_dual(sgtv_ctx ctx, const float *x0, int mem_kind);
 /* Run n_iters >= 0 ADMM iterations (Eqs. 4-6) asynchronously on the stream. */
 int sgtv_iterate(sgtv_ctx ctx, int n_iters);
 
+/* Capture and instantiate now the graph that sgtv_iterate(ctx, n_iters) would
+ * replay from the current state, without running it, so that the next such
+ * call only launches the graph (for callers that time or serve the iterations
+ * and want the capture outside that call).  Leaves the state unchanged.  No
+ * effect when graphs are off, kernel timing is on or n_iters < 2.  The graph
+ * is dropped, like every captured graph, by calls that change the system,
+ * data, parameters or state.  Errors: SGTV_EINVAL for n_iters < 0, SGTV_ESTATE
+ * before system and data are set, SGTV_EDEVICE if capture fails. */
+int sgtv_prepare(sgtv_ctx ctx, int n_iters);
+
 /* Graph replay of sgtv_iterate (default on): the launch sequence of n
  * iterations is captured once into a HIP graph per (n, buffer parity) and
  * replayed on the context stream; captured graphs are dropped by every call
@@ -300,6 +310,15 @@ int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t
 int sgtv_batch_size(sgtv_batch b, int32_t *n_scans);
 /* n_iters iterations of every scan in batched launches (graph replay). */
 int sgtv_batch_iterate(sgtv_batch b, int n_iters);
+
+/* Capture and instantiate now, without running them, the graphs that the
+ * next call with n_iters replays: sequential = 0, the graph of
+ * sgtv_batch_iterate (building the batch tables first if scans were added);
+ * sequential = 1, each scan's own graph of sgtv_batch_iterate_sequential (as
+ * sgtv_prepare per scan).  The state is unchanged.  No effect for an empty
+ * batch or n_iters = 0.  Errors as sgtv_prepare, and SGTV_EINVAL for a
+ * sequential other than 0 or 1. */
+int sgtv_batch_prepare(sgtv_batch b, int n_iters, int sequential);
 /* The same iterations scan after scan, each with its own graph: the
  * reference the batched launch is measured against. */
 int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters);

@@ -1147,21 +1147,14 @@ int sgtv_set_init_dual(sgtv_ctx ctx, const float *x0, int mem_kind) {
     return SGTV_OK;
 }
 
-int sgtv_iterate(sgtv_ctx ctx, int n_iters) {
-    if (int e = check_ready(ctx)) return e;
-    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
-    DeviceGuard g(ctx->device);
-    if (!ctx->use_graphs || ctx->profiling || n_iters < 2) {
-        for (int it = 0; it < n_iters; ++it)
-            if (int e = step(ctx)) return e;
-        return SGTV_OK;
-    }
+namespace {
+
+// The graph of n_iters iterations from the current buffer parity: found in the
+// cache or captured (not run) and instantiated.  The state is left unchanged.
+int context_graph(sgtv_ctx ctx, int n_iters, Context::Graph *out) {
     for (auto &gr : ctx->graphs)
         if (gr.n == n_iters && gr.fcur == ctx->fcur && gr.vcur == ctx->vcur) {
-            HIP_TRY(hipGraphLaunch(gr.exec, ctx->stream));
-            ctx->fcur = gr.fcur_after;
-            ctx->vcur = gr.vcur_after;
-            ctx->k += n_iters;
+            *out = gr;
             return SGTV_OK;
         }
     // capture the launch sequence on the context's own stream
@@ -1194,11 +1187,37 @@ int sgtv_iterate(sgtv_ctx ctx, int n_iters) {
         ctx->graphs.erase(ctx->graphs.begin());
     }
     ctx->graphs.push_back(gr);
+    *out = gr;
+    return SGTV_OK;
+}
+
+}  // namespace
+
+int sgtv_iterate(sgtv_ctx ctx, int n_iters) {
+    if (int e = check_ready(ctx)) return e;
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    DeviceGuard g(ctx->device);
+    if (!ctx->use_graphs || ctx->profiling || n_iters < 2) {
+        for (int it = 0; it < n_iters; ++it)
+            if (int e = step(ctx)) return e;
+        return SGTV_OK;
+    }
+    Context::Graph gr{};
+    if (int e = context_graph(ctx, n_iters, &gr)) return e;
     HIP_TRY(hipGraphLaunch(gr.exec, ctx->stream));
     ctx->fcur = gr.fcur_after;
     ctx->vcur = gr.vcur_after;
     ctx->k += n_iters;
     return SGTV_OK;
+}
+
+int sgtv_prepare(sgtv_ctx ctx, int n_iters) {
+    if (int e = check_ready(ctx)) return e;
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    if (!ctx->use_graphs || ctx->profiling || n_iters < 2) return SGTV_OK;
+    DeviceGuard g(ctx->device);
+    Context::Graph gr{};
+    return context_graph(ctx, n_iters, &gr);
 }
 
 int sgtv_set_graphs(sgtv_ctx ctx, int enable) {
@@ -1758,19 +1777,16 @@ int sgtv_batch_size(sgtv_batch b, int32_t *n_scans) {
     return SGTV_OK;
 }
 
-int sgtv_batch_iterate(sgtv_batch b, int n_iters) {
-    if (!b) return fail(SGTV_EINVAL, "null batch");
-    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
-    if (b->scans.empty() || n_iters == 0) return SGTV_OK;
-    DeviceGuard g(b->device);
+namespace {
+
+// The graph of n_iters batched iterations from the current buffer parity:
+// found in the cache or captured (not run) and instantiated.
+int batch_graph(sgtv_batch b, int n_iters, sgtv_ctx_s::Graph *out) {
     if (b->dirty)
         if (int e = batch_tables(b)) return e;
     for (auto &gr : b->graphs)
         if (gr.n == n_iters && gr.fcur == b->fcur && gr.vcur == b->vcur) {
-            HIP_TRY(hipGraphLaunch(gr.exec, b->stream));
-            b->fcur = gr.fcur_after;
-            b->vcur = gr.vcur_after;
-            batch_sync_scans(b, n_iters);
+            *out = gr;
             return SGTV_OK;
         }
     if (!b->cap) HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
@@ -1800,11 +1816,39 @@ int sgtv_batch_iterate(sgtv_batch b, int n_iters) {
         b->graphs.erase(b->graphs.begin());
     }
     b->graphs.push_back(gr);
+    *out = gr;
+    return SGTV_OK;
+}
+
+}  // namespace
+
+int sgtv_batch_iterate(sgtv_batch b, int n_iters) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    if (b->scans.empty() || n_iters == 0) return SGTV_OK;
+    DeviceGuard g(b->device);
+    sgtv_ctx_s::Graph gr{};
+    if (int e = batch_graph(b, n_iters, &gr)) return e;
     HIP_TRY(hipGraphLaunch(gr.exec, b->stream));
     b->fcur = gr.fcur_after;
     b->vcur = gr.vcur_after;
     batch_sync_scans(b, n_iters);
     return SGTV_OK;
+}
+
+int sgtv_batch_prepare(sgtv_batch b, int n_iters, int sequential) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
+    if (sequential != 0 && sequential != 1) return fail(SGTV_EINVAL, "sequential must be 0 or 1");
+    if (sequential) {
+        for (auto *c : b->scans)
+            if (int e = sgtv_prepare(c, n_iters)) return e;
+        return SGTV_OK;
+    }
+    if (b->scans.empty() || n_iters == 0) return SGTV_OK;
+    DeviceGuard g(b->device);
+    sgtv_ctx_s::Graph gr{};
+    return batch_graph(b, n_iters, &gr);
 }
 
 int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters) {

@@ -91,6 +91,7 @@ def lib():
             "sgtv_set_init": (_I, [_P, _P, _I]),
             "sgtv_set_init_dual": (_I, [_P, _P, _I]),
             "sgtv_iterate": (_I, [_P, _I]),
+            "sgtv_prepare": (_I, [_P, _I]),
             "sgtv_objective": (_I, [_P, ctypes.POINTER(Report)]),
             "sgtv_get_image": (_I, [_P, _P, _I]),
             "sgtv_get_split": (_I, [_P, _P, _P, _I]),
@@ -106,6 +107,7 @@ def lib():
                                          _D, _D, _I, ctypes.POINTER(Schedule), _I, ctypes.POINTER(_I32)]),
             "sgtv_batch_size": (_I, [_P, ctypes.POINTER(_I32)]),
             "sgtv_batch_iterate": (_I, [_P, _I]),
+            "sgtv_batch_prepare": (_I, [_P, _I, _I]),
             "sgtv_batch_iterate_sequential": (_I, [_P, _I]),
             "sgtv_batch_objective": (_I, [_P, _I32, ctypes.POINTER(Report)]),
             "sgtv_batch_get_image": (_I, [_P, _I32, _P, _I]),
@@ -222,6 +224,10 @@ def sgtv_set_init_dual(ctx, x0):
 
 def sgtv_iterate(ctx, n_iters):
     _check(lib().sgtv_iterate(ctx, int(n_iters)))
+
+
+def sgtv_prepare(ctx, n_iters):
+    _check(lib().sgtv_prepare(ctx, int(n_iters)))
 
 
 def sgtv_objective(ctx):
@@ -400,6 +406,11 @@ class Reconstructor:
         sgtv_iterate(self._ctx, n)
         return self
 
+    def prepare(self, n):
+        """Capture the graph of iterate(n) now, without running it."""
+        sgtv_prepare(self._ctx, n)
+        return self
+
     def objective(self):
         return sgtv_objective(self._ctx)
 
@@ -492,6 +503,10 @@ def sgtv_batch_iterate(b, n_iters):
     _check(lib().sgtv_batch_iterate(b, int(n_iters)))
 
 
+def sgtv_batch_prepare(b, n_iters, sequential=False):
+    _check(lib().sgtv_batch_prepare(b, int(n_iters), int(bool(sequential))))
+
+
 def sgtv_batch_iterate_sequential(b, n_iters):
     _check(lib().sgtv_batch_iterate_sequential(b, int(n_iters)))
 
@@ -539,6 +554,12 @@ class Batch:
 
     def iterate(self, n):
         sgtv_batch_iterate(self._b, n)
+        return self
+
+    def prepare(self, n, sequential=False):
+        """Capture now, without running them, the graphs of iterate(n)
+        (sequential=False) or of iterate_sequential(n) (sequential=True)."""
+        sgtv_batch_prepare(self._b, n, sequential)
         return self
 
     def iterate_sequential(self, n):

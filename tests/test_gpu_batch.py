@@ -80,3 +80,31 @@ def test_add_scan_after_iterating_is_refused(sg):
         B.add_scan(probs[1])
     assert ei.value.code == sg.SGTV_ESTATE
     assert len(B) == 1
+
+
+def test_batch_prepare_both_modes(sg):
+    """prepare(n) and prepare(n, sequential=True) capture without running; the
+    iterations after them equal those of a batch that was not prepared."""
+    import ctypes
+    probs = scans()[:3]
+    runs = []
+    for prepared in (False, True):
+        B = sg.Batch()
+        for p in probs:
+            B.add_scan(p, schedule=SCHED)
+        if prepared:
+            B.prepare(9)
+            B.prepare(9, sequential=True)
+            for i in range(len(probs)):
+                assert B.objective(i)["iter"] == 0
+        B.iterate(9)
+        B.iterate_sequential(9)
+        runs.append([B.image(i) for i in range(len(probs))])
+        if prepared:
+            with pytest.raises(sg.SgtvError):
+                B.prepare(-1)
+            assert sg.lib().sgtv_batch_prepare(B._b, 4, ctypes.c_int(2)) != 0
+        B.close()
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
