@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sgtv.h"
@@ -148,7 +150,7 @@ void pack_sell(int64_t n_lines, const std::vector<int64_t> &lptr, const std::vec
 }
 
 struct Tiled {
-    DBuf pk, val, goff, poff;
+    DBuf pk, val, goff, poff, slot;
     sgtv::TileMap map{};
 };
 
@@ -211,7 +213,7 @@ template <class V>
 int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
                 bool idx24, std::vector<int32_t> &pk, std::vector<V> &pv, std::vector<int32_t> &goff,
-                std::vector<int32_t> &poff, sgtv::TileMap &map) {
+                std::vector<int32_t> &poff, std::vector<uint16_t> &slot_of, sgtv::TileMap &map) {
     // 24-bit indices: row in 10 bits, column in 14 with the code cb left for
     // the zero slot.  Their lists are lane-owned: all entries of a row within a
     // list sit in one lane, in row order, so a lane can read every accumulator
@@ -230,9 +232,112 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     for (int k = 0; k < ns; ++k)
         for (int b = slab_begin[k]; b < slab_begin[k + 1]; ++b) slab_of[b] = k;
     const int64_t n_lists = n_rb * ns * cbs_max * t.waves;
-    auto list_of = [&](int64_t r, int32_t c) -> int64_t {
+    // 24-bit lists: in every tile (row block, slab) the rows of the row block
+    // are dealt to the waves so that each wave's share of every column block is
+    // as even as possible (every block ends at a barrier, where all waves wait
+    // for the longest list).  Greedy: rows by decreasing entry count, each to
+    // the wave with room whose loads on the row's blocks are smallest (ties:
+    // smaller total, then lower wave).  slot_of[tile * RB + i] is the slot
+    // w * rw + l of row offset i (the kernel writes the row sums out in row
+    // order through it).  The 32-bit lists, and schedules whose per-row-block
+    // counts would pass 2^22 (tiny column blocks of a large matrix), keep row
+    // offset i in slot i.
+    slot_of.clear();
+    const bool balance = idx24 && static_cast<int64_t>(ns) * RB * cbs_max <= (int64_t(1) << 22);
+    if (balance) {
+        slot_of.assign(static_cast<size_t>(n_rb * ns * RB), 0);
+        // row blocks are independent: a few host threads take every nth one
+        std::atomic<bool> failed{false};
+        auto deal = [&](int64_t first, int64_t step) {
+          try {
+            std::vector<int32_t> cnt(static_cast<size_t>(ns) * RB * cbs_max), tot(static_cast<size_t>(RB));
+            std::vector<int32_t> order(static_cast<size_t>(RB)), bucket;
+            std::vector<int64_t> load(static_cast<size_t>(t.waves) * cbs_max), wtot(t.waves);
+            std::vector<int32_t> filled(t.waves);
+            std::vector<int32_t> nzc, nzn;
+            for (int64_t rb = first; rb < n_rb; rb += step) {
+                std::fill(cnt.begin(), cnt.end(), 0);
+                for (int64_t i = 0; i < RB && rb * RB + i < n_rows; ++i)
+                    for (int64_t k = rp[rb * RB + i]; k < rp[rb * RB + i + 1]; ++k) {
+                        const int64_t cbi = ci[k] / t.cb;
+                        const int slab = slab_of[cbi];
+                        cnt[(static_cast<size_t>(slab) * RB + i) * cbs_max + (cbi - slab_begin[slab])]++;
+                    }
+                for (int slab = 0; slab < ns; ++slab) {
+                    const int32_t *n = cnt.data() + static_cast<size_t>(slab) * RB * cbs_max;
+                    int32_t tmax = 0;
+                    for (int64_t i = 0; i < RB; ++i) {
+                        int32_t v = 0;
+                        for (int c = 0; c < cbs_max; ++c) v += n[i * cbs_max + c];
+                        tot[i] = v;
+                        tmax = std::max(tmax, v);
+                    }
+                    // counting sort by decreasing total, stable in row order
+                    bucket.assign(static_cast<size_t>(tmax) + 2, 0);
+                    for (int64_t i = 0; i < RB; ++i) bucket[tmax - tot[i] + 1]++;
+                    for (int32_t v = 1; v <= tmax + 1; ++v) bucket[v] += bucket[v - 1];
+                    for (int64_t i = 0; i < RB; ++i) order[bucket[tmax - tot[i]]++] = static_cast<int32_t>(i);
+                    std::fill(load.begin(), load.end(), 0);
+                    std::fill(wtot.begin(), wtot.end(), 0);
+                    std::fill(filled.begin(), filled.end(), 0);
+                    const int64_t tile = rb * ns + slab;
+                    for (int64_t o = 0; o < RB; ++o) {
+                        const int64_t i = order[o];
+                        nzc.clear();
+                        nzn.clear();
+                        for (int c = 0; c < cbs_max; ++c)
+                            if (n[i * cbs_max + c]) {
+                                nzc.push_back(c);
+                                nzn.push_back(n[i * cbs_max + c]);
+                            }
+                        int best = -1;
+                        int64_t best_key = 0;
+                        for (int w = 0; w < t.waves; ++w) {
+                            if (filled[w] == t.rw) continue;
+                            int64_t key = 0;
+                            const int64_t *lw = load.data() + static_cast<size_t>(w) * cbs_max;
+                            for (size_t u = 0; u < nzc.size(); ++u) key += lw[nzc[u]] * nzn[u];
+                            if (best < 0 || key < best_key || (key == best_key && wtot[w] < wtot[best])) {
+                                best = w;
+                                best_key = key;
+                            }
+                        }
+                        const int64_t slot = static_cast<int64_t>(best) * t.rw + filled[best]++;
+                        slot_of[static_cast<size_t>(tile * RB + i)] = static_cast<uint16_t>(slot);
+                        int64_t *lw = load.data() + static_cast<size_t>(best) * cbs_max;
+                        for (size_t u = 0; u < nzc.size(); ++u) lw[nzc[u]] += nzn[u];
+                        wtot[best] += tot[i];
+                    }
+                }
+            }
+          } catch (...) {
+            failed = true;
+          }
+        };
+        const int64_t nth = std::max<int64_t>(1, std::min<int64_t>({8, n_rb, static_cast<int64_t>(
+                                                     std::thread::hardware_concurrency())}));
+        std::vector<std::thread> pool;
+        for (int64_t k = 1; k < nth; ++k) {
+            try {
+                pool.emplace_back(deal, k, nth);
+            } catch (...) {
+                deal(k, nth);   // no thread: deal its row blocks here
+            }
+        }
+        deal(0, nth);
+        for (auto &th : pool) th.join();
+        if (failed) throw std::bad_alloc();
+    }
+    // slot (wave * rw + row in the wave) of row r in the tile of column c
+    auto slot_in_tile = [&](int64_t r, int32_t c) -> int64_t {
         const int64_t rb = r / RB, i = r - rb * RB;
-        const int64_t w = i / t.rw;
+        if (!balance) return i;
+        const int slab = slab_of[c / t.cb];
+        return slot_of[static_cast<size_t>((rb * ns + slab) * RB + i)];
+    };
+    auto list_of = [&](int64_t r, int32_t c) -> int64_t {
+        const int64_t rb = r / RB;
+        const int64_t w = slot_in_tile(r, c) / t.rw;
         const int64_t cbi = c / t.cb;
         const int slab = slab_of[cbi];
         return ((rb * ns + slab) * cbs_max + (cbi - slab_begin[slab])) * t.waves + w;
@@ -261,7 +366,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
                 const int64_t at = cur[list_of(r, ci[k])]++;
                 lent[at] = k;
-                lrow[at] = static_cast<int16_t>((r % RB) % t.rw);
+                lrow[at] = static_cast<int16_t>(slot_in_tile(r, ci[k]) % t.rw);
             }
     }
     // Lane-owned layout of list L: runs of equal rows, longest first (ties in
@@ -469,16 +574,20 @@ int upload_tiled(Tiled &T, int64_t n_rows, int64_t n_cols, const std::vector<int
                  const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
                  bool idx24) {
     std::vector<int32_t> pk, goff, poff;
+    std::vector<uint16_t> slot;
     std::vector<V> pv;
-    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, idx24, pk, pv, goff, poff, T.map)) return e;
+    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, idx24, pk, pv, goff, poff, slot, T.map))
+        return e;
     HIP_TRY(upload(T.pk, pk));
     HIP_TRY(upload(T.val, pv));
     HIP_TRY(upload(T.goff, goff));
     if (!poff.empty()) HIP_TRY(upload(T.poff, poff));
+    if (!slot.empty()) HIP_TRY(upload(T.slot, slot));
     T.map.pk = T.pk.as<int32_t>();
     T.map.val = T.val.p;
     T.map.goff = T.goff.as<int32_t>();
     T.map.poff = poff.empty() ? nullptr : T.poff.as<int32_t>();
+    T.map.slot = slot.empty() ? nullptr : T.slot.as<uint16_t>();
     return SGTV_OK;
 }
 
@@ -942,7 +1051,7 @@ extern "C" {
 
 const char *sgtv_last_error(void) { return g_err.c_str(); }
 
-const char *sgtv_version(void) { return "sgtv 0.1 (gfx950, sliced-ELL FP32/BF16/FP16)"; }
+const char *sgtv_version(void) { return "sgtv 0.2 (gfx950; tiled and sliced-ELL formats; FP32, BF16, FP16 values)"; }
 
 int sgtv_create(sgtv_ctx *out, int device, void *hip_stream) {
     if (!out) return fail(SGTV_EINVAL, "out is NULL");
@@ -1397,8 +1506,11 @@ int64_t sgtv_workspace_bytes(int64_t I, int64_t J, int64_t nnz, int storage_dtyp
         const double e = static_cast<double>(nnz) / lists;
         const double groups = std::max(std::ceil(e / 64.0) + 1.0, std::ceil(lam + 2.5 * std::sqrt(lam) + 1.0));
         const double stored = std::min(lists * 64.0 * groups, 64.0 * static_cast<double>(nnz) + 256.0);
-        const double idx_bytes = (t.rw >= 64 && t.rw <= 1024 && t.cb <= 16380) ? 3.0 : 4.0;
-        return stored * (idx_bytes + vb) + lists * 8.0;
+        const bool i24 = t.rw >= 64 && t.rw <= 1024 && t.cb <= 16380;
+        const double idx_bytes = i24 ? 3.0 : 4.0;
+        // 24-bit lists also keep the row order of every tile (2 bytes per row and slab)
+        const double order = i24 ? 2.0 * n_rb * 16.0 * t.rw * t.ns : 0.0;
+        return stored * (idx_bytes + vb) + lists * 8.0 + order;
     };
     int64_t ns_f = 1, ns_b = 1;
     const double matrix = copy_bytes(I, J, &ns_f) + copy_bytes(J, I, &ns_b);
@@ -1419,7 +1531,8 @@ int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes) {
         const System &S = *ctx->sys;
         for (const DBuf *d : {&S.rs_ptr, &S.rs_idx, &S.rs_val, &S.cs_ptr, &S.cs_idx, &S.cs_val, &S.colscale,
                               &S.sens, &S.H, &S.wbuf, &S.fpart, &S.bpart, &S.fwd.pk, &S.fwd.val, &S.fwd.goff,
-                              &S.fwd.poff, &S.back.pk, &S.back.val, &S.back.goff, &S.back.poff})
+                              &S.fwd.poff, &S.fwd.slot, &S.back.pk, &S.back.val, &S.back.goff,
+                              &S.back.poff, &S.back.slot})
             b += static_cast<int64_t>(d->bytes);
     }
     *bytes = b;

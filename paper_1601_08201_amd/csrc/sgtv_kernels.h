@@ -48,6 +48,8 @@ struct TileMap {
     const void *val;        // values or 16-bit codes, padding: 0
     const int32_t *goff;    // group offset of every list, n_lists + 1 entries
     const int32_t *poff;    // 24-bit indices: offset (in dwords) of every list's indices
+    const uint16_t *slot;   // 24-bit indices: per tile, the slot w * rw + l (wave w, row l
+                            // in the wave) of every row of the row block; nullptr: identity
     int idx24;              // 1: indices row << 14 | column, three dwords per lane and batch;
                             // padding: a row unused in its group, column cb (a zero in LDS)
     int64_t n_rows, n_cols;

@@ -264,9 +264,10 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     const int64_t rb_rows = static_cast<int64_t>(M.waves) * M.rw;
     const int64_t row0 = rb * rb_rows;
     float *out = part + static_cast<int64_t>(slab) * M.n_rows;
-    for (int64_t i = tid; i < rb_rows; i += nthr) {
-        const int64_t row = row0 + i;
-        if (row < M.n_rows) out[row] = acc[(i / M.rw) * rw1 + (i % M.rw)];
+    const uint16_t *sl = M.slot ? M.slot + (rb * M.ns + slab) * rb_rows : nullptr;
+    for (int64_t i = tid; i < rb_rows && row0 + i < M.n_rows; i += nthr) {
+        const int64_t s = sl ? static_cast<int64_t>(sl[i]) : i;
+        out[row0 + i] = acc[(s / M.rw) * rw1 + (s % M.rw)];
     }
 }
 
