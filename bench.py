@@ -51,10 +51,25 @@ def algorithmic_bytes(prob, value_bytes, fmt):
     return out
 
 
+def kernel_fingerprint():
+    """SHA-256 of the product kernels' sources (sgtv_tiled.hip, sgtv_device.h,
+    sgtv_kernels.h) with comments and white space removed: a counter summary
+    stays valid across edits of comments only."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1601_08201_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, storage, fmt, config):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when there is none for this workload or the kernel sources changed since."""
-    import hashlib
+    when there is none for this workload or the kernel code changed since."""
     import re
     if storage != "f32" or fmt != "tiled" or config != "paper" or kernel not in ("forward", "back"):
         return None
@@ -65,11 +80,7 @@ def measured_traffic(kernel, storage, fmt, config):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    h = hashlib.sha256()
-    for f in ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h"):
-        with open(os.path.join(ROOT, "paper_1601_08201_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec.get("kernel_source_sha256"):
+    if kernel_fingerprint() != rec.get("kernel_source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"].get(kernel)
 

@@ -35,8 +35,10 @@ struct Sell {
 
 // LDS-tiled sparse product y = M x with per-slab partial outputs.
 // Rows of M are cut into row blocks of waves * rw rows (one workgroup each;
-// wave w owns rows [w*rw, (w+1)*rw) of the block and keeps their sums in
-// LDS), columns into blocks of cb columns (staged in LDS one at a time) and
+// every wave owns rw rows of the block and keeps their sums in LDS: rows
+// [w*rw, (w+1)*rw) for 32-bit indices, rows chosen per tile to even out the
+// waves' work in every column block for 24-bit indices, see slot), columns
+// into blocks of cb columns (staged in LDS one at a time) and
 // the column blocks into ns slabs.  Workgroup b works on row block b / ns and
 // slab b % ns, so all workgroups of a slab land on the same XCD and its
 // slice of x stays in that XCD's L2.  Entries of one (row block, slab,
