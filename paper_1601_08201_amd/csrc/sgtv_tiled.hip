@@ -159,6 +159,10 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     }
     __syncthreads();
 
+    // the next column block is read into registers before the block barrier
+    // (so its latency overlaps the wait there): MODE 2, and the simple loop on
+    // 24-bit lists when the block fits the prefetch registers
+    const bool pre = MODE == 2 || (MODE == 0 && M.idx24 && M.cb <= kXPrefetch * 4 * nthr);
     for (int c = 0; c < ncbs; ++c) {
         const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
         const int g0 = goff[L];
@@ -220,7 +224,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
                 tile_batch<VT>(pB, aB, xs, my);
             }
         }
-        if (MODE == 2) {
+        if (pre && c + 1 < ncbs) {
 #pragma unroll
             for (int k = 0; k < kXPrefetch; ++k) {
                 const int i4 = (k * nthr + tid) * 4;
@@ -247,7 +251,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
         }
         if (c + 1 < ncbs) {
             __syncthreads();   // every wave is done with this block
-            if (MODE == 2) {
+            if (pre) {
 #pragma unroll
                 for (int k = 0; k < kXPrefetch; ++k) {
                     const int i4 = (k * nthr + tid) * 4;
