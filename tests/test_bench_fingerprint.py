@@ -1,0 +1,46 @@
+"""The committed HBM counter summary is keyed on the product kernels' code:
+an edit of comments or white space keeps it valid, an edit of code does not
+(CPU only)."""
+import importlib.util
+import os
+import shutil
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FILES = ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h")
+
+
+@pytest.fixture()
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def copy_tree(tmp_path):
+    dst = tmp_path / "paper_1601_08201_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for f in FILES:
+        shutil.copy(os.path.join(ROOT, "paper_1601_08201_amd", "csrc", f), dst / f)
+    return dst
+
+
+def test_committed_summary_matches_current_kernels(bench):
+    for k in ("forward", "back"):
+        t = bench.measured_traffic(k, "f32", "tiled", "paper")
+        assert t is not None and 0.8e9 < t < 1.2e9
+
+
+def test_comments_do_not_change_the_fingerprint(bench, tmp_path, monkeypatch):
+    ref = bench.kernel_fingerprint()
+    dst = copy_tree(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_fingerprint() == ref
+    p = dst / "sgtv_kernels.h"
+    p.write_text("// a new comment line\n/* and a block\n   comment */\n" + p.read_text().replace("\n", "\n\n"))
+    assert bench.kernel_fingerprint() == ref
+    p = dst / "sgtv_tiled.hip"
+    p.write_text(p.read_text().replace("kXPrefetch = 4", "kXPrefetch = 2"))
+    assert bench.kernel_fingerprint() != ref
