@@ -29,7 +29,7 @@ def hipcc() -> str:
 
 def compile_flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-            # packed FP32 instructions stay off (see the build notes in DESIGN)
+            # no packed FP32 instructions: the kernels are written for scalar FP32 arithmetic
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
