@@ -209,6 +209,36 @@ size_t tile_lds_bytes(const TileParams &t) {
 
 // Host packing of one tiled product from CSR-like lines (rows of M in order,
 // column indices ascending within a row).  V is float or a 16-bit code.
+// Calls work(first, step) on up to 8 host threads, first = 0 .. n - 1 and
+// step = n, so that each worker takes every nth item of its own loop over
+// n_items items; an exception in any worker (an allocation that failed) is
+// rethrown as std::bad_alloc once all have finished.  Workers that cannot be
+// started run in the caller.
+template <class Fn>
+void on_threads(int64_t n_items, Fn work) {
+    const int64_t nth = std::max<int64_t>(
+        1, std::min<int64_t>({8, n_items, static_cast<int64_t>(std::thread::hardware_concurrency())}));
+    std::atomic<bool> failed{false};
+    auto run = [&](int64_t first) {
+        try {
+            work(first, nth);
+        } catch (...) {
+            failed = true;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int64_t k = 1; k < nth; ++k) {
+        try {
+            pool.emplace_back(run, k);
+        } catch (...) {
+            run(k);
+        }
+    }
+    run(0);
+    for (auto &th : pool) th.join();
+    if (failed) throw std::bad_alloc();
+}
+
 template <class V>
 int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
@@ -246,10 +276,8 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     const bool balance = idx24 && static_cast<int64_t>(ns) * RB * cbs_max <= (int64_t(1) << 22);
     if (balance) {
         slot_of.assign(static_cast<size_t>(n_rb * ns * RB), 0);
-        // row blocks are independent: a few host threads take every nth one
-        std::atomic<bool> failed{false};
-        auto deal = [&](int64_t first, int64_t step) {
-          try {
+        // row blocks are independent: each worker takes every nth one
+        on_threads(n_rb, [&](int64_t first, int64_t step) {
             std::vector<int32_t> cnt(static_cast<size_t>(ns) * RB * cbs_max), tot(static_cast<size_t>(RB));
             std::vector<int32_t> order(static_cast<size_t>(RB)), bucket;
             std::vector<int64_t> load(static_cast<size_t>(t.waves) * cbs_max), wtot(t.waves);
@@ -310,23 +338,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                     }
                 }
             }
-          } catch (...) {
-            failed = true;
-          }
-        };
-        const int64_t nth = std::max<int64_t>(1, std::min<int64_t>({8, n_rb, static_cast<int64_t>(
-                                                     std::thread::hardware_concurrency())}));
-        std::vector<std::thread> pool;
-        for (int64_t k = 1; k < nth; ++k) {
-            try {
-                pool.emplace_back(deal, k, nth);
-            } catch (...) {
-                deal(k, nth);   // no thread: deal its row blocks here
-            }
-        }
-        deal(0, nth);
-        for (auto &th : pool) th.join();
-        if (failed) throw std::bad_alloc();
+        });
     }
     // slot (wave * rw + row in the wave) of row r in the tile of column c
     auto slot_in_tile = [&](int64_t r, int32_t c) -> int64_t {
@@ -345,14 +357,18 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     std::vector<int32_t> count(static_cast<size_t>(n_lists), 0), run(static_cast<size_t>(n_lists), 0),
         maxrun(static_cast<size_t>(n_lists), 0);
     std::vector<int64_t> last(static_cast<size_t>(n_lists), -1);
-    for (int64_t r = 0; r < n_rows; ++r)
-        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
-            const int64_t L = list_of(r, ci[k]);
-            count[L]++;
-            run[L] = last[L] == r ? run[L] + 1 : 1;
-            last[L] = r;
-            maxrun[L] = std::max(maxrun[L], run[L]);
-        }
+    // the lists of a row block hold only its rows: workers take whole row blocks
+    on_threads(n_rb, [&](int64_t first, int64_t step) {
+        for (int64_t rb = first; rb < n_rb; rb += step)
+            for (int64_t r = rb * RB; r < std::min(n_rows, (rb + 1) * RB); ++r)
+                for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+                    const int64_t L = list_of(r, ci[k]);
+                    count[L]++;
+                    run[L] = last[L] == r ? run[L] + 1 : 1;
+                    last[L] = r;
+                    maxrun[L] = std::max(maxrun[L], run[L]);
+                }
+    });
     // idx24: the entries (indices into ci / vals) of every list, in row order
     std::vector<int64_t> lstart, lent;
     std::vector<int16_t> lrow;   // row within the wave of every listed entry
@@ -362,23 +378,33 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         lent.resize(static_cast<size_t>(lstart[n_lists]));
         lrow.resize(static_cast<size_t>(lstart[n_lists]));
         std::vector<int64_t> cur(lstart.begin(), lstart.end() - 1);
-        for (int64_t r = 0; r < n_rows; ++r)
-            for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
-                const int64_t at = cur[list_of(r, ci[k])]++;
-                lent[at] = k;
-                lrow[at] = static_cast<int16_t>(slot_in_tile(r, ci[k]) % t.rw);
-            }
+        on_threads(n_rb, [&](int64_t first, int64_t step) {
+            for (int64_t rb = first; rb < n_rb; rb += step)
+                for (int64_t r = rb * RB; r < std::min(n_rows, (rb + 1) * RB); ++r)
+                    for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+                        const int64_t at = cur[list_of(r, ci[k])]++;
+                        lent[at] = k;
+                        lrow[at] = static_cast<int16_t>(slot_in_tile(r, ci[k]) % t.rw);
+                    }
+        });
     }
     // Lane-owned layout of list L: runs of equal rows, longest first (ties in
     // row order), each to the least-loaded lane (ties: lowest lane); a lane
     // keeps its runs in row order.  Fills lane_load[64] and, in lane order,
     // seq (the entries of lane 0, then lane 1, ...) with lane_begin[65];
-    // returns the largest load.
-    std::vector<int64_t> run_start, run_len, run_order, seq;
-    std::vector<int32_t> run_lane, len_count;
-    int32_t lane_load[64];
-    int64_t lane_begin[65];
-    auto lane_owned = [&](int64_t L) -> int64_t {
+    // returns the largest load.  Scratch of one worker:
+    struct LaneScratch {
+        std::vector<int64_t> run_start, run_len, run_order, seq;
+        std::vector<int32_t> run_lane, len_count;
+        int32_t lane_load[64];
+        int64_t lane_begin[65];
+    };
+    auto lane_owned = [&](int64_t L, LaneScratch &S) -> int64_t {
+        std::vector<int64_t> &run_start = S.run_start, &run_len = S.run_len, &run_order = S.run_order,
+                             &seq = S.seq;
+        std::vector<int32_t> &run_lane = S.run_lane, &len_count = S.len_count;
+        int32_t *lane_load = S.lane_load;
+        int64_t *lane_begin = S.lane_begin;
         const int64_t b0 = lstart[L], n = lstart[L + 1] - b0;
         run_start.clear();
         run_len.clear();
@@ -431,16 +457,27 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             for (int64_t u = 0; u < run_len[q]; ++u) seq[fill[run_lane[q]]++] = b0 + run_start[q] + u;
         return ng;
     };
+    // lists are packed independently: workers take chunks of 256 lists
+    const int64_t n_chunks = (n_lists + 255) / 256;
+    auto chunk_lists = [&](int64_t first, int64_t step, auto &&fn) {
+        for (int64_t ch = first; ch < n_chunks; ch += step)
+            for (int64_t L = ch * 256; L < std::min(n_lists, (ch + 1) * 256); ++L) fn(L);
+    };
+    std::vector<int32_t> ngr(static_cast<size_t>(n_lists));
+    on_threads(n_chunks, [&](int64_t first, int64_t step) {
+        LaneScratch S;
+        chunk_lists(first, step, [&](int64_t L) {
+            const int64_t ng = count[L] == 0 ? 0
+                               : idx24     ? lane_owned(L, S)
+                                           : std::max<int64_t>((count[L] + 63) / 64, maxrun[L]);
+            ngr[L] = static_cast<int32_t>(std::min<int64_t>(ng, int64_t(1) << 30));
+        });
+    });
     goff.assign(static_cast<size_t>(n_lists + 1), 0);
     int64_t total = 0;
-    std::vector<int32_t> ngr(static_cast<size_t>(n_lists));
     for (int64_t L = 0; L < n_lists; ++L) {
-        const int64_t ng = count[L] == 0 ? 0
-                           : idx24     ? lane_owned(L)
-                                       : std::max<int64_t>((count[L] + 63) / 64, maxrun[L]);
-        ngr[L] = static_cast<int32_t>(ng);
         goff[L] = static_cast<int32_t>(total);
-        total += ng;
+        total += ngr[L];
         if (total * 64 >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "tiled matrix exceeds 2^31 stored entries");
     }
     goff[n_lists] = static_cast<int32_t>(total);
@@ -458,18 +495,21 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         // round robin over the groups: consecutive entries of a row (one list)
         // fall into consecutive groups, so every group holds distinct rows
         std::fill(count.begin(), count.end(), 0);   // reuse as cursor
-        for (int64_t r = 0; r < n_rows; ++r) {
-            const int64_t rl = (r % RB) % t.rw;
-            for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
-                const int32_t c = ci[k];
-                const int64_t L = list_of(r, c);
-                const int64_t kk = count[L]++;
-                const int64_t ng = ngr[L];
-                const int64_t pos = slot(L, kk % ng, kk / ng);
-                pk[pos] = static_cast<int32_t>((rl << row_shift) | (c % t.cb));
-                pv[pos] = vals[k];
-            }
-        }
+        on_threads(n_rb, [&](int64_t first, int64_t step) {
+            for (int64_t rb = first; rb < n_rb; rb += step)
+                for (int64_t r = rb * RB; r < std::min(n_rows, (rb + 1) * RB); ++r) {
+                    const int64_t rl = (r % RB) % t.rw;
+                    for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+                        const int32_t c = ci[k];
+                        const int64_t L = list_of(r, c);
+                        const int64_t kk = count[L]++;
+                        const int64_t ng = ngr[L];
+                        const int64_t pos = slot(L, kk % ng, kk / ng);
+                        pk[pos] = static_cast<int32_t>((rl << row_shift) | (c % t.cb));
+                        pv[pos] = vals[k];
+                    }
+                }
+        });
     }
     poff.clear();
     if (idx24) {
@@ -477,10 +517,15 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         // than the list repeats its last row with value 0 (its running sum is
         // unchanged), an empty lane takes a row absent from the list; padding
         // reads the zero slot (column code cb)
-        std::vector<uint8_t> present(static_cast<size_t>(t.rw));
-        for (int64_t L = 0; L < n_lists; ++L) {
-            if (count[L] == 0) continue;
-            const int64_t ng = lane_owned(L);
+        on_threads(n_chunks, [&](int64_t first, int64_t step) {
+          LaneScratch S;
+          std::vector<uint8_t> present(static_cast<size_t>(t.rw));
+          const int32_t *lane_load = S.lane_load;
+          const int64_t *lane_begin = S.lane_begin;
+          const std::vector<int64_t> &seq = S.seq;
+          chunk_lists(first, step, [&](int64_t L) {
+            if (count[L] == 0) return;
+            const int64_t ng = lane_owned(L, S);
             std::fill(present.begin(), present.end(), 0);
             for (int64_t i = lstart[L]; i < lstart[L + 1]; ++i) present[lrow[i]] = 1;
             int free_row = 0;
@@ -502,7 +547,8 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 for (int64_t i = lane_load[l]; i < ng; ++i)
                     pk[slot(L, i, l)] = static_cast<int32_t>((last << row_shift) | t.cb);
             }
-        }
+          });
+        });
         // repack: per list, whole batches as three dwords per lane (a plane of
         // 64 dword pairs, then a plane of 64 dwords), then the remaining groups
         // one dword per entry
@@ -515,7 +561,8 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         }
         poff[n_lists] = static_cast<int32_t>(words);
         std::vector<int32_t> p24(static_cast<size_t>(words));
-        for (int64_t L = 0; L < n_lists; ++L) {
+        on_threads(n_chunks, [&](int64_t first, int64_t step) {
+          chunk_lists(first, step, [&](int64_t L) {
             const int64_t ng = ngr[L], nb4 = ng / 4;
             const int64_t base = static_cast<int64_t>(goff[L]) * 64;
             uint32_t *dst = reinterpret_cast<uint32_t *>(p24.data()) + poff[L];
@@ -547,7 +594,8 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 for (int64_t lane = 0; lane < 64; ++lane)
                     dst[nb4 * 192 + (g - nb4 * 4) * 64 + lane] =
                         static_cast<uint32_t>(pk[base + nb4 * 256 + (g - nb4 * 4) * 64 + lane]);
-        }
+          });
+        });
         // keep the all-padding batch of the 32-bit layout after the repacked
         // lists (the simple loop that reads 24-bit indices never streams it)
         p24.insert(p24.end(), pk.end() - 256, pk.end());
