@@ -518,36 +518,36 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         // unchanged), an empty lane takes a row absent from the list; padding
         // reads the zero slot (column code cb)
         on_threads(n_chunks, [&](int64_t first, int64_t step) {
-          LaneScratch S;
-          std::vector<uint8_t> present(static_cast<size_t>(t.rw));
-          const int32_t *lane_load = S.lane_load;
-          const int64_t *lane_begin = S.lane_begin;
-          const std::vector<int64_t> &seq = S.seq;
-          chunk_lists(first, step, [&](int64_t L) {
-            if (count[L] == 0) return;
-            const int64_t ng = lane_owned(L, S);
-            std::fill(present.begin(), present.end(), 0);
-            for (int64_t i = lstart[L]; i < lstart[L + 1]; ++i) present[lrow[i]] = 1;
-            int free_row = 0;
-            for (int l = 0; l < 64; ++l) {
-                int32_t last = -1;
-                for (int64_t i = 0; i < lane_load[l]; ++i) {
-                    const int64_t at = seq[lane_begin[l] + i];
-                    const int64_t k = lent[at];
-                    last = lrow[at];
-                    const int64_t pos = slot(L, i, l);
-                    pk[pos] = static_cast<int32_t>((last << row_shift) | (ci[k] % t.cb));
-                    pv[pos] = vals[k];
+            LaneScratch S;
+            std::vector<uint8_t> present(static_cast<size_t>(t.rw));
+            const int32_t *lane_load = S.lane_load;
+            const int64_t *lane_begin = S.lane_begin;
+            const std::vector<int64_t> &seq = S.seq;
+            chunk_lists(first, step, [&](int64_t L) {
+                if (count[L] == 0) return;
+                const int64_t ng = lane_owned(L, S);
+                std::fill(present.begin(), present.end(), 0);
+                for (int64_t i = lstart[L]; i < lstart[L + 1]; ++i) present[lrow[i]] = 1;
+                int free_row = 0;
+                for (int l = 0; l < 64; ++l) {
+                    int32_t last = -1;
+                    for (int64_t i = 0; i < lane_load[l]; ++i) {
+                        const int64_t at = seq[lane_begin[l] + i];
+                        const int64_t k = lent[at];
+                        last = lrow[at];
+                        const int64_t pos = slot(L, i, l);
+                        pk[pos] = static_cast<int32_t>((last << row_shift) | (ci[k] % t.cb));
+                        pv[pos] = vals[k];
+                    }
+                    if (last < 0) {
+                        while (present[free_row]) ++free_row;
+                        present[free_row] = 1;
+                        last = free_row;
+                    }
+                    for (int64_t i = lane_load[l]; i < ng; ++i)
+                        pk[slot(L, i, l)] = static_cast<int32_t>((last << row_shift) | t.cb);
                 }
-                if (last < 0) {
-                    while (present[free_row]) ++free_row;
-                    present[free_row] = 1;
-                    last = free_row;
-                }
-                for (int64_t i = lane_load[l]; i < ng; ++i)
-                    pk[slot(L, i, l)] = static_cast<int32_t>((last << row_shift) | t.cb);
-            }
-          });
+            });
         });
         // repack: per list, whole batches as three dwords per lane (a plane of
         // 64 dword pairs, then a plane of 64 dwords), then the remaining groups
@@ -562,39 +562,39 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         poff[n_lists] = static_cast<int32_t>(words);
         std::vector<int32_t> p24(static_cast<size_t>(words));
         on_threads(n_chunks, [&](int64_t first, int64_t step) {
-          chunk_lists(first, step, [&](int64_t L) {
-            const int64_t ng = ngr[L], nb4 = ng / 4;
-            const int64_t base = static_cast<int64_t>(goff[L]) * 64;
-            uint32_t *dst = reinterpret_cast<uint32_t *>(p24.data()) + poff[L];
-            const int64_t nsb = nb4 / 4;
-            for (int64_t b = 0; b < nb4; ++b)
-                for (int64_t lane = 0; lane < 64; ++lane) {
-                    const uint32_t *e = reinterpret_cast<const uint32_t *>(pk.data()) + base + b * 256 + lane * 4;
-                    const uint32_t w0 = e[0] | (e[1] << 24);
-                    const uint32_t w1 = (e[1] >> 8) | (e[2] << 16);
-                    const uint32_t w2 = (e[2] >> 16) | (e[3] << 8);
-                    if (b < nsb * 4) {
-                        // super-batch sb: words 3t .. 3t + 2 of batch t = b % 4, word i in
-                        // plane i / 4, slot i % 4 of the lane's 16 bytes
-                        uint32_t *sbp = dst + (b / 4) * 768;
-                        const int64_t i0 = 3 * (b % 4);
-                        const uint32_t w[3] = {w0, w1, w2};
-                        for (int64_t k = 0; k < 3; ++k) {
-                            const int64_t i = i0 + k;
-                            sbp[(i / 4) * 256 + lane * 4 + (i % 4)] = w[k];
+            chunk_lists(first, step, [&](int64_t L) {
+                const int64_t ng = ngr[L], nb4 = ng / 4;
+                const int64_t base = static_cast<int64_t>(goff[L]) * 64;
+                uint32_t *dst = reinterpret_cast<uint32_t *>(p24.data()) + poff[L];
+                const int64_t nsb = nb4 / 4;
+                for (int64_t b = 0; b < nb4; ++b)
+                    for (int64_t lane = 0; lane < 64; ++lane) {
+                        const uint32_t *e = reinterpret_cast<const uint32_t *>(pk.data()) + base + b * 256 + lane * 4;
+                        const uint32_t w0 = e[0] | (e[1] << 24);
+                        const uint32_t w1 = (e[1] >> 8) | (e[2] << 16);
+                        const uint32_t w2 = (e[2] >> 16) | (e[3] << 8);
+                        if (b < nsb * 4) {
+                            // super-batch sb: words 3t .. 3t + 2 of batch t = b % 4, word i in
+                            // plane i / 4, slot i % 4 of the lane's 16 bytes
+                            uint32_t *sbp = dst + (b / 4) * 768;
+                            const int64_t i0 = 3 * (b % 4);
+                            const uint32_t w[3] = {w0, w1, w2};
+                            for (int64_t k = 0; k < 3; ++k) {
+                                const int64_t i = i0 + k;
+                                sbp[(i / 4) * 256 + lane * 4 + (i % 4)] = w[k];
+                            }
+                        } else {
+                            uint32_t *bp = dst + nsb * 768 + (b - nsb * 4) * 192;
+                            bp[lane * 2] = w0;
+                            bp[lane * 2 + 1] = w1;
+                            bp[128 + lane] = w2;
                         }
-                    } else {
-                        uint32_t *bp = dst + nsb * 768 + (b - nsb * 4) * 192;
-                        bp[lane * 2] = w0;
-                        bp[lane * 2 + 1] = w1;
-                        bp[128 + lane] = w2;
                     }
-                }
-            for (int64_t g = nb4 * 4; g < ng; ++g)
-                for (int64_t lane = 0; lane < 64; ++lane)
-                    dst[nb4 * 192 + (g - nb4 * 4) * 64 + lane] =
-                        static_cast<uint32_t>(pk[base + nb4 * 256 + (g - nb4 * 4) * 64 + lane]);
-          });
+                for (int64_t g = nb4 * 4; g < ng; ++g)
+                    for (int64_t lane = 0; lane < 64; ++lane)
+                        dst[nb4 * 192 + (g - nb4 * 4) * 64 + lane] =
+                            static_cast<uint32_t>(pk[base + nb4 * 256 + (g - nb4 * 4) * 64 + lane]);
+            });
         });
         // keep the all-padding batch of the 32-bit layout after the repacked
         // lists (the simple loop that reads 24-bit indices never streams it)
