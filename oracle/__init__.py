@@ -28,13 +28,14 @@ NDIR = 4
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc -O2 (no fast-math, no contraction)."""
+    """Compile the oracle with gcc -O2 (no fast-math, no contraction); OpenMP
+    shares the loops over independent outputs among threads."""
     os.makedirs(_BUILD, exist_ok=True)
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", tmp] + srcs + ["-lm"]
+               "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp] + srcs + ["-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -81,11 +82,28 @@ def _declare(lib):
         "wn_forward": (None, [_I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
         "wn_loss_grad": (_D, [_I, _I, _I, _I, _I, _P, _P, _P, _P]),
         "wn_adam": (None, [_I64, _P, _P, _P, _P, _I64, _D, _D, _D, _D]),
+        "or_set_threads": (None, [_I]),
+        "or_max_threads": (_I, []),
+        "or_last_loop_seconds": (_D, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+
+
+def set_threads(n):
+    """Threads of the loops over independent outputs (results do not depend on it)."""
+    _load().or_set_threads(int(n))
+
+
+def max_threads():
+    return int(_load().or_max_threads())
+
+
+def last_loop_seconds():
+    """Wall time of the iteration loop of the last admm() call (set-up excluded)."""
+    return float(_load().or_last_loop_seconds())
 
 
 def _f64(a):

@@ -7,7 +7,12 @@
  * no code, header or table with the GPU library.
  *
  * Everything is plain IEEE double arithmetic, loops in fixed index order,
- * serial, built without fast-math.  Conventions:
+ * built without fast-math.  Loops whose outputs are independent of each
+ * other (one row, one column, one voxel or one group per iteration) are
+ * shared among OpenMP threads; every sum keeps the order of the serial loop
+ * and every reduction over many outputs (objective, residual norms) stays
+ * serial, so results are bitwise the same for any number of threads.
+ * Conventions:
  *
  *   voxel j = s*Q + q, spatial bin s = iy*nx + ix          (Section II, J = S x Q)
  *   direction p: 0 = +x, 1 = -x, 2 = +y, 3 = -y            (four spatial neighbours)
@@ -24,8 +29,30 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NDIR 4
+
+/* Threads for the loops over independent outputs (1: serial). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* neighbour of spatial bin s in direction p, or -1 when it lies outside */
 static int64_t neighbour(int ny, int nx, int64_t s, int p)
@@ -48,6 +75,7 @@ static double weight(const double *w, int Q, int64_t s, int p, int q)
 void or_forward(int64_t I, const int64_t *rowptr, const int32_t *col, const double *val,
                 const double *f, const double *r, double *p)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < I; ++i) {
         double acc = 0.0;
         for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
@@ -67,10 +95,86 @@ void or_back(int64_t I, int64_t J, const int64_t *rowptr, const int32_t *col,
             e[col[k]] += val[k] * t[i];
 }
 
+/* The entries of A column by column: column j holds its entries in the order
+ * a row-by-row pass over the CSR form meets them (rows ascending), so
+ * e_j = sum over that list of a_ij t_i adds exactly the terms of or_back in
+ * the same order, and the columns can be summed independently. */
+typedef struct {
+    int64_t J;
+    int64_t *colptr;
+    int32_t *row;
+    double *val;
+} or_csc;
+
+static int csc_build(int64_t I, int64_t J, const int64_t *rowptr, const int32_t *col,
+                     const double *val, or_csc *At)
+{
+    int64_t nnz = rowptr[I];
+    At->J = J;
+    At->colptr = calloc((size_t)(J + 1), sizeof(int64_t));
+    At->row = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    At->val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *next = malloc(sizeof(int64_t) * (size_t)(J > 0 ? J : 1));
+    if (!At->colptr || !At->row || !At->val || !next) {
+        free(next);
+        return -1;
+    }
+    /* each thread counts and fills the columns of its own range, passing over
+     * the rows in order: every column list is written by one thread, rows
+     * ascending, whatever the number of threads */
+#pragma omp parallel
+    {
+        int64_t nth = 1, me = 0;
+#ifdef _OPENMP
+        nth = omp_get_num_threads();
+        me = omp_get_thread_num();
+#endif
+        int64_t j0 = J * me / nth, j1 = J * (me + 1) / nth;
+        for (int64_t k = 0; k < nnz; ++k)
+            if (col[k] >= j0 && col[k] < j1)
+                At->colptr[col[k] + 1]++;
+#pragma omp barrier
+#pragma omp single
+        for (int64_t j = 0; j < J; ++j)
+            At->colptr[j + 1] += At->colptr[j];
+        for (int64_t j = j0; j < j1; ++j)
+            next[j] = At->colptr[j];
+        for (int64_t i = 0; i < I; ++i)
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (col[k] >= j0 && col[k] < j1) {
+                    int64_t pos = next[col[k]]++;
+                    At->row[pos] = (int32_t)i;
+                    At->val[pos] = val[k];
+                }
+    }
+    free(next);
+    return 0;
+}
+
+static void csc_free(or_csc *At)
+{
+    free(At->colptr);
+    free(At->row);
+    free(At->val);
+}
+
+/* e = A^T t from the column lists (the same sums as or_back). */
+static void back_csc(const or_csc *At, const double *t, double *e)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < At->J; ++j) {
+        double acc = 0.0;
+        for (int64_t k = At->colptr[j]; k < At->colptr[j + 1]; ++k)
+            acc += At->val[k] * t[At->row[k]];
+        e[j] = acc;
+    }
+}
+
 /* g = w .* (G f), the stacked finite differences of Eq. 3. */
 void or_diff(int ny, int nx, int Q, const double *w, const double *f, double *g)
 {
     int64_t S = (int64_t)ny * nx;
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < S; ++s)
         for (int p = 0; p < NDIR; ++p) {
             int64_t nb = neighbour(ny, nx, s, p);
@@ -82,21 +186,34 @@ void or_diff(int ny, int nx, int Q, const double *w, const double *f, double *g)
 }
 
 /* out = (w .* G)^T t: each difference row adds +w*t to its own voxel and -w*t
- * to its in-grid neighbour. */
+ * to its in-grid neighbour.  Written per output voxel (s, q), the terms come
+ * in the order of a pass over the rows by increasing s and p: the row of the
+ * bin below (s - nx, direction +y), of the bin to the left (s - 1, +x), the
+ * four rows of s, then the bin to the right (s + 1, -x) and the bin above
+ * (s + nx, -y). */
 void or_diff_adj(int ny, int nx, int Q, const double *w, const double *t, double *out)
 {
+    static const int before[2] = {3, 1}, after[2] = {0, 2};
     int64_t S = (int64_t)ny * nx;
-    for (int64_t j = 0; j < S * Q; ++j)
-        out[j] = 0.0;
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < S; ++s)
-        for (int p = 0; p < NDIR; ++p) {
-            int64_t nb = neighbour(ny, nx, s, p);
-            for (int q = 0; q < Q; ++q) {
-                double v = weight(w, Q, s, p, q) * t[(s * NDIR + p) * Q + q];
-                out[s * Q + q] += v;
+        for (int q = 0; q < Q; ++q) {
+            double acc = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                int64_t nb = neighbour(ny, nx, s, before[k]);
+                int pb = before[k] ^ 1;   /* direction from nb back to s */
                 if (nb >= 0)
-                    out[nb * Q + q] -= v;
+                    acc -= weight(w, Q, nb, pb, q) * t[(nb * NDIR + pb) * Q + q];
             }
+            for (int p = 0; p < NDIR; ++p)
+                acc += weight(w, Q, s, p, q) * t[(s * NDIR + p) * Q + q];
+            for (int k = 0; k < 2; ++k) {
+                int64_t nb = neighbour(ny, nx, s, after[k]);
+                int pb = after[k] ^ 1;
+                if (nb >= 0)
+                    acc -= weight(w, Q, nb, pb, q) * t[(nb * NDIR + pb) * Q + q];
+            }
+            out[s * Q + q] = acc;
         }
 }
 
@@ -154,9 +271,11 @@ void or_shrink(int ny, int nx, int Q, int grouping, double thr, const double *v,
 {
     int64_t S = (int64_t)ny * nx;
     if (grouping == 0) {
+#pragma omp parallel for schedule(static)
         for (int64_t s = 0; s < S; ++s)
             shrink_group(NDIR * Q, v + s * NDIR * Q, 1, thr, d + s * NDIR * Q);
     } else {
+#pragma omp parallel for schedule(static)
         for (int64_t s = 0; s < S; ++s)
             for (int q = 0; q < Q; ++q)
                 shrink_group(NDIR, v + s * NDIR * Q + q, Q, thr, d + s * NDIR * Q + q);
@@ -238,8 +357,8 @@ void or_objective(const or_problem *P, const double *f, double out[3])
  *   EM surrogate of L at g (sensitivity s = A^T 1, back-projected ratio e),
  *   De Pierro surrogate of (lam/2)||D f - z||^2 at g (gradient gam, curvature H),
  *   every hyper-voxel then solves its own 1-D problem in closed form. */
-void or_image_sweep(const or_problem *P, const double *sens, const double *H, const double *z,
-                    double *g)
+static void image_sweep(const or_problem *P, const or_csc *At, const double *sens,
+                        const double *H, const double *z, double *g)
 {
     int64_t J = n_vox(P), I = P->I;
     double *p = malloc(sizeof(double) * (I > 0 ? I : 1));
@@ -247,13 +366,19 @@ void or_image_sweep(const or_problem *P, const double *sens, const double *H, co
     double *t = malloc(sizeof(double) * (J * NDIR > 0 ? J * NDIR : 1));
     double *gam = malloc(sizeof(double) * (J > 0 ? J : 1));
     or_forward(I, P->rowptr, P->col, P->val, g, P->r, p);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < I; ++i)
         p[i] = P->y[i] / p[i];
-    or_back(I, J, P->rowptr, P->col, P->val, p, e);
+    if (At)
+        back_csc(At, p, e);
+    else
+        or_back(I, J, P->rowptr, P->col, P->val, p, e);
     or_diff(P->ny, P->nx, P->Q, P->w, g, t);
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < J * NDIR; ++k)
         t[k] -= z[k];
     or_diff_adj(P->ny, P->nx, P->Q, P->w, t, gam);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < J; ++j) {
         double B = sens[j] + P->lam * gam[j] - H[j] * g[j];
         double C = g[j] * e[j];
@@ -263,6 +388,12 @@ void or_image_sweep(const or_problem *P, const double *sens, const double *H, co
     free(e);
     free(t);
     free(gam);
+}
+
+void or_image_sweep(const or_problem *P, const double *sens, const double *H, const double *z,
+                    double *g)
+{
+    image_sweep(P, NULL, sens, H, z, g);
 }
 
 /* Sensitivity s = A^T 1. */
@@ -298,6 +429,23 @@ double or_plain_init(const or_problem *P)
  * report[5k..5k+4] holds the objective of f^{k+1}, its data and TV parts,
  * the primal residual ||w.*Gf - d|| and the dual residual lam ||D^T(d^{k+1}-d^k)||.
  */
+static double g_loop_seconds = 0.0;
+
+/* Wall time of the iteration loop of the last or_admm call (set-up excluded). */
+double or_last_loop_seconds(void)
+{
+    return g_loop_seconds;
+}
+
+static double now_seconds(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
+
 int or_admm(const or_problem *P, int n_iter, int sweeps, double *f, double *d, double *c,
             double *report)
 {
@@ -308,24 +456,36 @@ int or_admm(const or_problem *P, int n_iter, int sweeps, double *f, double *d, d
     double *v = malloc(sizeof(double) * (JN > 0 ? JN : 1));
     double *dn = malloc(sizeof(double) * (JN > 0 ? JN : 1));
     double *tmp = malloc(sizeof(double) * (J > 0 ? J : 1));
-    if (!sens || !H || !z || !v || !dn || !tmp)
+    double *ones = malloc(sizeof(double) * (P->I > 0 ? P->I : 1));
+    or_csc At;
+    if (!sens || !H || !z || !v || !dn || !tmp || !ones ||
+        csc_build(P->I, J, P->rowptr, P->col, P->val, &At) != 0)
         return -1;
-    or_sensitivity(P, sens);
+    for (int64_t i = 0; i < P->I; ++i)
+        ones[i] = 1.0;
+    back_csc(&At, ones, sens);                  /* s = A^T 1, as or_sensitivity */
+    free(ones);
     or_curv(P->ny, P->nx, P->Q, P->w, P->lam, H);
+    double t0 = now_seconds();
     for (int k = 0; k < n_iter; ++k) {
+#pragma omp parallel for schedule(static)
         for (int64_t m = 0; m < JN; ++m)
             z[m] = d[m] - c[m];
         for (int sw = 0; sw < sweeps; ++sw)
-            or_image_sweep(P, sens, H, z, f);
+            image_sweep(P, &At, sens, H, z, f);
         or_diff(P->ny, P->nx, P->Q, P->w, f, v);
+#pragma omp parallel for schedule(static)
         for (int64_t m = 0; m < JN; ++m)
             v[m] += c[m];
         or_shrink(P->ny, P->nx, P->Q, P->grouping, P->beta / P->lam, v, dn);
         double rp = 0.0, rd = 0.0;
         for (int64_t m = 0; m < JN; ++m) {
-            double cn = v[m] - dn[m];          /* c^k + Df^{k+1} - d^{k+1}   (Eq. 6) */
-            double prim = cn - c[m];           /* = Df^{k+1} - d^{k+1}            */
+            double prim = (v[m] - dn[m]) - c[m];   /* = Df^{k+1} - d^{k+1}            */
             rp += prim * prim;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t m = 0; m < JN; ++m) {
+            double cn = v[m] - dn[m];          /* c^k + Df^{k+1} - d^{k+1}   (Eq. 6) */
             c[m] = cn;
             z[m] = dn[m] - d[m];               /* reuse z for d^{k+1} - d^k       */
             d[m] = dn[m];
@@ -343,6 +503,8 @@ int or_admm(const or_problem *P, int n_iter, int sweeps, double *f, double *d, d
             report[5 * k + 4] = P->lam * sqrt(rd);
         }
     }
+    g_loop_seconds = now_seconds() - t0;
+    csc_free(&At);
     free(sens);
     free(H);
     free(z);
