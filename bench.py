@@ -51,59 +51,116 @@ def algorithmic_bytes(prob, value_bytes, fmt):
     return out
 
 
-def kernel_fingerprint():
-    """SHA-256 of the product kernels' sources (sgtv_tiled.hip, sgtv_device.h,
-    sgtv_kernels.h) with comments and white space removed: a counter summary
-    stays valid across edits of comments only."""
-    import hashlib
+PRODUCT_SOURCES = ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h")
+
+
+def _code_only(src):
     import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_fingerprint(schedule=None):
+    """SHA-256 of what decides the bytes the products stream: the product
+    kernels' sources (sgtv_tiled.hip, sgtv_device.h, sgtv_kernels.h), the host
+    builder of the tiled format in sgtv_api.hip (automatic schedule, packing,
+    upload) and the schedule in use, with comments and white space removed: a
+    counter summary stays valid across edits of comments only."""
+    import hashlib
     h = hashlib.sha256()
-    for f in ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h"):
-        with open(os.path.join(ROOT, "paper_1601_08201_amd", "csrc", f)) as fh:
-            src = fh.read()
-        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
-        src = re.sub(r"//[^\n]*", " ", src)
-        h.update(" ".join(src.split()).encode())
+    csrc = os.path.join(ROOT, "paper_1601_08201_amd", "csrc")
+    for f in PRODUCT_SOURCES:
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
+    with open(os.path.join(csrc, "sgtv_api.hip")) as fh:
+        api = fh.read()
+    a, b = api.find("TileParams choose_tiles("), api.find("struct System {")
+    if a >= 0 and b > a:
+        h.update(_code_only(api[a:b]).encode())
+    if schedule is not None:
+        h.update(json.dumps(schedule, sort_keys=True).encode())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, storage, fmt, config):
+PRODUCT_PROFILE = os.path.join("profiles", "tiled_product_fp32_paper_scan.md")
+
+
+def measured_traffic(kernel, storage, fmt, config, schedule=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when there is none for this workload or the kernel code changed since."""
+    when there is none for this workload or the kernels, the builder or the
+    schedule changed since it was taken."""
     import re
     if storage != "f32" or fmt != "tiled" or config != "paper" or kernel not in ("forward", "back"):
         return None
-    path = os.path.join(ROOT, "profiles", "tiled_product_fp32_paper_scan.md")
+    path = os.path.join(ROOT, PRODUCT_PROFILE)
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if kernel_fingerprint() != rec.get("kernel_source_sha256"):
+    if kernel_fingerprint(schedule) != rec.get("kernel_source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"].get(kernel)
 
 
-def cpu_baseline(prob, iters):
+def host_threads():
+    """Threads the oracle may use on this host: the CPUs this process may run
+    on, capped by OMP_NUM_THREADS when it is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_problem(prob):
+    """The scan with FP64 arrays (widened once, outside any timing)."""
     import numpy as np
-    import oracle
-    rp = prob.rowptr
-    col = prob.col
-    val = prob.val.astype(np.float64)
-    y = prob.y.astype(np.float64)
-    r = prob.r.astype(np.float64)
 
     class P:
         pass
     p = P()
-    p.__dict__.update(dict(ny=prob.ny, nx=prob.nx, Q=prob.Q, I=prob.I, rowptr=rp, col=col, val=val,
-                           y=y, r=r, beta=prob.beta, rho=prob.rho, sweeps=prob.sweeps))
-    f0 = np.full(prob.J, oracle.plain_init(p), np.float64)
-    t0 = time.perf_counter()
-    oracle.admm(p, iters, f0=f0, report=False)
-    dt = time.perf_counter() - t0
-    return iters / dt, dt
+    p.__dict__.update(dict(ny=prob.ny, nx=prob.nx, Q=prob.Q, I=prob.I, J=prob.J, rowptr=prob.rowptr,
+                           col=prob.col, val=prob.val.astype(np.float64), y=prob.y.astype(np.float64),
+                           r=prob.r.astype(np.float64), beta=prob.beta, rho=prob.rho, sweeps=prob.sweeps))
+    return p
+
+
+def oracle_run(p, iters, threads, **kw):
+    """The FP64 oracle from the uniform start on `threads` threads: (image, iterations per
+    second of the iteration loop alone, loop seconds)."""
+    import numpy as np
+    import oracle
+    oracle.set_threads(threads)
+    f0 = np.full(p.J, oracle.plain_init(p), np.float64)
+    f, _, _, _ = oracle.admm(p, iters, f0=f0, report=False, **kw)
+    sec = oracle.last_loop_seconds()
+    return f, iters / sec, sec
+
+
+def oracle_error(p, f_gpu, f_or, **kw):
+    """Image relative L2 error and relative objective error of a GPU image against the
+    oracle's image after the same iterations, both objectives from the oracle (FP64)."""
+    import numpy as np
+    import oracle
+    g = f_gpu.astype(np.float64)
+    rel_l2 = float(np.linalg.norm(g - f_or) / max(np.linalg.norm(f_or), 1e-300))
+    phi_g = oracle.objective(p, g, **kw)[0]
+    phi_o = oracle.objective(p, f_or, **kw)[0]
+    return {"image_rel_l2": rel_l2, "objective_rel": abs(phi_g - phi_o) / abs(phi_o)}
 
 
 def _gen_batch_scan(args):
@@ -135,7 +192,7 @@ def batch_main(args):
     t0 = time.time()
     sched = autotune.batch_schedule([(p.I, p.J) for p in probs])
     with cf.ThreadPoolExecutor(8) as ex:
-        list(ex.map(lambda p: B.add_scan(p, sched), probs))
+        index = list(ex.map(lambda p: B.add_scan(p, sched), probs))
     log("batch built in %.1fs (schedule %s)" % (time.time() - t0, sched))
     B.iterate(args.warmup)
     B.prepare(args.steps)   # graph capture outside the timed region
@@ -147,6 +204,17 @@ def batch_main(args):
     b.record(stream)
     torch.cuda.synchronize()
     ms_batched = a.elapsed_time(b)
+    # error against the FP64 oracle of the two smallest scans after the same iterations
+    err = []
+    if not args.no_cpu_baseline:
+        nth = host_threads()
+        for k in sorted(range(len(probs)), key=lambda k: probs[k].nnz)[:2]:
+            p = oracle_problem(probs[k])
+            f_or, _, _ = oracle_run(p, args.warmup + args.steps, nth)
+            e = oracle_error(p, B.image(index[k]), f_or)
+            err.append(dict(e, scan="%dx%dx%d" % (p.ny, p.nx, p.Q), iterations=args.warmup + args.steps))
+            log("scan %s after %d iterations vs the FP64 oracle: %s" % (err[-1]["scan"], args.warmup + args.steps,
+                                                                        json.dumps(e)))
     B.close()
     # the same scans one after another, each with its own single-scan schedule
     # (tuned when cached): a scan launched alone has to fill the GPU by itself
@@ -187,6 +255,7 @@ def batch_main(args):
                      "unit": "GB/s", "frac": alg * args.steps / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": None},
         "cpu_baseline": None,
+        "oracle_error": err or None,
     }
     print(json.dumps(out), flush=True)
 
@@ -235,6 +304,17 @@ def sweep_main(args):
                         spectral_error=study.spectral_error(x, prob.x_true, S, Q)))
     best = study.select(res)
     n_total = args.warmup + args.steps
+    err = []
+    if not args.no_cpu_baseline:
+        p = oracle_problem(prob)
+        nth = host_threads()
+        for i in (0, len(pairs) - 1):
+            g, b = pairs[i]
+            f_or, _, _ = oracle_run(p, n_total, nth, w=w, grouping=g, beta=b)
+            e = oracle_error(p, B.image(i), f_or, w=w, grouping=g, beta=b)
+            err.append(dict(e, grouping=study.GROUPINGS[g], beta=b, iterations=n_total))
+            log("scan %s beta %g after %d iterations vs the FP64 oracle: %s"
+                % (study.GROUPINGS[g], b, n_total, json.dumps(e)))
     log("sweep of %d scans: batched %.3f ms/iter, sequential %.3f ms/iter, images equal: %s"
         % (len(pairs), ms_batched / args.steps, ms_seq / args.steps, same))
     for r in res:
@@ -244,13 +324,17 @@ def sweep_main(args):
     scan_its = len(pairs) * args.steps
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
         n_cpu = args.cpu_iters
-        t0 = time.perf_counter()
-        oracle.admm(prob, n_cpu, beta=betas[0], w=w, grouping=0, report=False)
-        dt = time.perf_counter() - t0
-        cpu = {"value": n_cpu / dt, "unit": "scan-iters/s", "cores": 1, "kind": "oracle",
-               "sample": "one scan of the sweep, %d iterations (FP64 C oracle, one thread)" % n_cpu}
+        p = oracle_problem(prob)
+        nth = host_threads()
+        _, rate1, sec1 = oracle_run(p, n_cpu, 1, beta=betas[0], w=w, grouping=0)
+        _, rate, sec = oracle_run(p, n_cpu, nth, beta=betas[0], w=w, grouping=0)
+        cpu = {"value": rate, "unit": "scan-iters/s", "cores": nth, "kind": "oracle",
+               "sample": "one scan of the sweep, %d iterations (FP64 C oracle, %d OpenMP threads), loop %.1fs"
+                         % (n_cpu, nth, sec),
+               "single_thread": {"value": rate1, "unit": "scan-iters/s", "cores": 1,
+                                 "sample": "the same, one thread, loop %.1fs" % sec1},
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
     out = {
         "metric": "beta-sweep scan-iterations/s (both regularisers, one batch)",
         "value": scan_its / (ms_batched * 1e-3),
@@ -274,6 +358,7 @@ def sweep_main(args):
                      "unit": "GB/s", "frac": alg * args.steps / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": None},
         "cpu_baseline": cpu,
+        "oracle_error": err or None,
     }
     print(json.dumps(out), flush=True)
     B.close()
@@ -359,16 +444,18 @@ def warmstart_main(args):
         t1 = time.time()
         model, net, hist = warmstart.train(xin[k], tgt, mode=mode, input_iters=k, epochs=args.epochs, log=log)
         nets[name] = (model, net)
+        const = warmstart.constant_loss(xin[k], tgt, mode)
         train_info[name] = {"seconds": time.time() - t1, "loss_first_last": [hist[0], hist[-1]],
+                            "loss_of_constant_prediction": const,
                             "input": "plain image after %d iterations" % k if k else "normalised backprojection",
                             "output": mode}
-        log("%s: trained %d epochs in %.1fs, loss %.5f -> %.5f"
-            % (name, args.epochs, train_info[name]["seconds"], hist[0], hist[-1]))
+        log("%s: trained %d epochs in %.1fs, loss %.5f -> %.5f (constant prediction %.5f)"
+            % (name, args.epochs, train_info[name]["seconds"], hist[0], hist[-1], const))
     del xin, tgt
     scans = warmstart.draw_scans(scanner, range(20000, 20000 + args.eval_scans))
     R = recon.R
     tols = (1e-2, 1e-3, 1e-4)
-    recs = {"plain": []}
+    recs = {"plain": [], "restart_without_network": []}
     recs.update({name: [] for name in variants})
     fallbacks = {name: 0 for name in variants}
     for n, (_, y, r) in enumerate(scans):
@@ -381,6 +468,14 @@ def warmstart_main(args):
         setup = time.perf_counter() - t
         it, sec = warmstart.iterations_to_targets(R, phi_star, tols)
         recs["plain"].append((it, [setup + s_ if s_ is not None else None for s_ in sec]))
+        # ablation: the same restart (k_in plain iterations, consistent split and
+        # dual) from the plain image itself, no network
+        t = time.perf_counter()
+        spent = warmstart.restart_without_network(R, k_in)
+        setup = time.perf_counter() - t
+        it, sec = warmstart.iterations_to_targets(R, phi_star, tols)
+        recs["restart_without_network"].append(([None if i is None else i + spent for i in it],
+                                                [setup + s_ if s_ is not None else None for s_ in sec]))
         for name, (model, net) in nets.items():
             # plain iterations, network, fallback test, restart with consistent split and dual
             t = time.perf_counter()
@@ -408,6 +503,36 @@ def warmstart_main(args):
             name, [summary[name]["%g" % t]["iterations_q25_q50_q75"][1] for t in tols]))
     med_plain = summary["plain"]["0.0001"]["ms_q25_q50_q75"][1]
     med_learn = summary["learned"]["0.0001"]["ms_q25_q50_q75"][1]
+    med_restart = summary["restart_without_network"]["0.0001"]["ms_q25_q50_q75"][1]
+    # paired per-scan comparison of the network leg with its ablation at 1e-4
+    pairs_it = [(a[0][-1], b[0][-1]) for a, b in zip(recs["learned"], recs["restart_without_network"])
+                if a[0][-1] is not None and b[0][-1] is not None]
+    network_vs_ablation = {
+        "median_iterations_learned": float(np.median([a for a, _ in pairs_it])) if pairs_it else None,
+        "median_iterations_restart_without_network": float(np.median([b for _, b in pairs_it])) if pairs_it else None,
+        "scans_where_network_fewer_iterations": int(sum(a < b for a, b in pairs_it)),
+        "scans_where_network_more_iterations": int(sum(a > b for a, b in pairs_it)),
+        "median_ms_ratio_restart_over_learned": med_restart / med_learn,
+    }
+    log("network vs restart without network at 1e-4: " + json.dumps(network_vs_ablation))
+    # error against the FP64 oracle: the plain reconstruction of two held-out
+    # scans after 100 iterations
+    err = []
+    if not args.no_cpu_baseline:
+        nth = host_threads()
+        for n, (_, y, r) in enumerate(scans[:2]):
+            class Scan:
+                pass
+            sc = Scan()
+            sc.__dict__.update(dict(ny=scanner.ny, nx=scanner.nx, Q=scanner.Q, I=scanner.I, J=scanner.J,
+                                    rowptr=scanner.rowptr, col=scanner.col, val=scanner.val, y=y, r=r,
+                                    beta=scanner.beta, rho=scanner.rho, sweeps=1))
+            p = oracle_problem(sc)
+            recon.load(y, r)
+            f_gpu = recon.plain(100)
+            f_or, _, _ = oracle_run(p, 100, nth)
+            err.append(dict(oracle_error(p, f_gpu, f_or), scan=20000 + n, iterations=100))
+        log("plain reconstructions vs the FP64 oracle: " + json.dumps(err))
     out = {
         "metric": "time to 1e-4 rel obj, learned vs plain (64x64x64 scanner, held-out phantoms)",
         "value": med_plain / med_learn,
@@ -421,9 +546,11 @@ def warmstart_main(args):
                                % (args.train_scans, args.epochs, args.eval_scans, k_in),
                    "global_batch": 32, "parallelism": "single GPU"},
         "by_tolerance": summary,
+        "network_vs_restart_without_network": network_vs_ablation,
         "fallbacks": fallbacks,
         "training": train_info,
         "cpu_baseline": None,
+        "oracle_error": err or None,
     }
     print(json.dumps(out), flush=True)
 
@@ -557,13 +684,28 @@ def main():
     iter_bytes = sum(alg.values())
 
     cpu = None
+    err = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: %d oracle iterations on the host ..." % args.cpu_iters)
-        rate, secs = cpu_baseline(prob, args.cpu_iters)
-        cpu = {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle",
-               "sample": "%d ADMM iterations of the same %dx%dx%d scan (FP64, serial C), %.1fs"
-                         % (args.cpu_iters, prob.ny, prob.nx, prob.Q, secs)}
-        log("cpu baseline %.4f iters/s" % rate)
+        # the FP64 oracle on the host: one thread, then every thread of this
+        # host; its image after cpu_iters iterations is the reference of the
+        # GPU's image after as many iterations from the same uniform start
+        p = oracle_problem(prob)
+        nth = host_threads()
+        n1 = max(1, args.cpu_iters // 4)
+        log("cpu baseline: %d oracle iterations on 1 thread, %d on %d threads ..." % (n1, args.cpu_iters, nth))
+        _, rate1, sec1 = oracle_run(p, n1, 1)
+        f_or, rate, secs = oracle_run(p, args.cpu_iters, nth)
+        cpu = {"value": rate, "unit": "iters/s", "cores": nth, "kind": "oracle",
+               "sample": "%d ADMM iterations of the same %dx%dx%d scan (FP64 C oracle, %d OpenMP threads), "
+                         "iteration loop %.1fs" % (args.cpu_iters, prob.ny, prob.nx, prob.Q, nth, secs),
+               "single_thread": {"value": rate1, "unit": "iters/s", "cores": 1,
+                                 "sample": "%d iterations, loop %.1fs" % (n1, sec1)},
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        log("cpu baseline %.4f iters/s on %d threads, %.4f on one (%s)" % (rate, nth, rate1, cpu["cpu_model"]))
+        R.set_init(None)
+        R.iterate(args.cpu_iters)
+        err = dict(oracle_error(p, R.image(), f_or), iterations=args.cpu_iters)
+        log("GPU image after %d iterations vs the FP64 oracle: %s" % (args.cpu_iters, json.dumps(err)))
 
     out = {
         "metric": "ADMM iters/s + HBM GB/s at 128^2x128; time to 1e-4 rel obj, learned vs plain",
@@ -586,9 +728,12 @@ def main():
         "kernels": kern,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, args.storage, args.format, args.config),
-                     "traffic_unit": "bytes per launch"},
+                     "traffic": measured_traffic(dom, args.storage, args.format, args.config, R.schedule()),
+                     "traffic_unit": "bytes per launch",
+                     "traffic_source": "HBM counters (FETCH_SIZE, WRITE_SIZE, calibrated) in " + PRODUCT_PROFILE
+                                       + ", valid for the current kernels, builder and schedule"},
         "cpu_baseline": cpu,
+        "oracle_error": err,
     }
     print(json.dumps(out), flush=True)
     R.close()

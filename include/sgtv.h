@@ -326,10 +326,13 @@ int sgtv_batch_objective(sgtv_batch b, int32_t scan, sgtv_report *out);
 int sgtv_batch_get_image(sgtv_batch b, int32_t scan, float *x, int mem_kind);
 
 /*
- * Learned warm start: a convolutional network that maps the normalised
- * backprojection of a scan (sgtv_backprojection, an image of height x width
- * pixels with one channel per spectral bin, NHWC = the voxel order above) to
- * a nonnegative start image for sgtv_set_init.  Architecture: `layers`
+ * Learned warm start: a convolutional network that maps an early image of a
+ * scan (height x width pixels with one channel per spectral bin, NHWC = the
+ * voxel order above) to a nonnegative start image for sgtv_set_init_dual.
+ * The early image is either the image after a few plain iterations, from
+ * which the network predicts a per-voxel correction factor, or the
+ * normalised backprojection (sgtv_backprojection), from which it predicts
+ * the image itself (see wsnet_start).  Architecture: `layers`
  * 3x3 convolutions with zero padding 1, 64 channels in and out, weights
  * [co][ky][kx][ci] and one bias per output channel; ReLU after every layer
  * but the last, softplus after the last.  Training minimises the mean

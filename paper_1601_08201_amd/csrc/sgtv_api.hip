@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -214,10 +215,20 @@ size_t tile_lds_bytes(const TileParams &t) {
 // n_items items; an exception in any worker (an allocation that failed) is
 // rethrown as std::bad_alloc once all have finished.  Workers that cannot be
 // started run in the caller.
+// Threads of the host-side packing: SGTV_HOST_THREADS when it is set to a
+// positive count (at most 64), else up to 8 and no more than the host has.
+// The packed arrays do not depend on it.
+int64_t host_threads() {
+    if (const char *e = std::getenv("SGTV_HOST_THREADS")) {
+        const long n = std::strtol(e, nullptr, 10);
+        if (n >= 1) return std::min<long>(n, 64);
+    }
+    return std::max<int64_t>(1, std::min<int64_t>(8, std::thread::hardware_concurrency()));
+}
+
 template <class Fn>
 void on_threads(int64_t n_items, Fn work) {
-    const int64_t nth = std::max<int64_t>(
-        1, std::min<int64_t>({8, n_items, static_cast<int64_t>(std::thread::hardware_concurrency())}));
+    const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(host_threads(), n_items));
     std::atomic<bool> failed{false};
     auto run = [&](int64_t first) {
         try {

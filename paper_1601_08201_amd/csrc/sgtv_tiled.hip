@@ -402,14 +402,12 @@ template <int VT, int MODE>
 static hipError_t launch_tiled_t(const TileMap &M, const float *x, float *part, hipStream_t st) {
     const size_t lds = M.lds_bytes();
     // raise the kernel's dynamic-LDS limit once (outside any graph capture
-    // that may follow: the first launch of a context is never captured)
-    static bool raised = false;
-    if (!raised) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled<VT, MODE>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-        if (e != hipSuccess) return e;
-        raised = true;
-    }
+    // that may follow: the first launch of a context is never captured); the
+    // initialisation of a function-local static runs once even when several
+    // threads launch at the same time
+    static const hipError_t raised = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_tiled<VT, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (raised != hipSuccess) return raised;
     hipLaunchKernelGGL((k_tiled<VT, MODE>), dim3(static_cast<unsigned>(M.n_rb * M.ns)),
                        dim3(static_cast<unsigned>(M.waves * kWave)), lds, st, M, M.pk,
                        static_cast<const typename Code<VT>::T *>(M.val), M.goff, x, part);
@@ -435,13 +433,9 @@ template <int MODE>
 static hipError_t launch_tiled_batch_t(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
                                        const float *const *xs, float *const *parts, int waves,
                                        size_t lds, hipStream_t st) {
-    static bool raised = false;
-    if (!raised) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tiled_batch<0, MODE>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-        if (e != hipSuccess) return e;
-        raised = true;
-    }
+    static const hipError_t raised = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_tiled_batch<0, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (raised != hipSuccess) return raised;
     hipLaunchKernelGGL((k_tiled_batch<0, MODE>), dim3(static_cast<unsigned>(n_tiles)),
                        dim3(static_cast<unsigned>(waves * kWave)), lds, st, tiles, maps, xs, parts);
     return hipGetLastError();

@@ -357,15 +357,14 @@ __global__ void k_weights_bf16(const float *__restrict__ w, __bf16 *__restrict__
 
 // ---------------------------------------------------------------- launchers
 int conv_workgroups() {
-    static int n = 0;
-    if (n == 0) {
+    // computed once (thread-safe initialisation of a function-local static)
+    static const int n = [] {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            n = cus;
-        else
-            n = 256;
-    }
+            return cus;
+        return 256;
+    }();
     return n;
 }
 
@@ -373,14 +372,10 @@ template <int EP>
 static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
                          int W, __bf16 *ob, float *oz, float *osp, const __bf16 *mask,
                          hipStream_t st) {
-    static bool raised = false;
     const size_t lds = conv_lds_bytes(W);
-    if (!raised) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv3x3<EP>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        if (e != hipSuccess) return e;
-        raised = true;
-    }
+    static const hipError_t raised = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_conv3x3<EP>), hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    if (raised != hipSuccess) return raised;
     const int n_steps = B * ((H + kStepRows - 1) / kStepRows);
     if (n_steps == 0) return hipSuccess;
     // one workgroup per CU (the staged weights and rows take 129 KB of LDS)

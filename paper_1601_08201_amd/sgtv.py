@@ -529,7 +529,7 @@ class Batch:
 
     def __init__(self, device=0, stream=None):
         self._b = sgtv_batch_create(device, stream)
-        self._J = []
+        self._J = {}     # batch index -> unknowns (add_scan may run on several threads)
 
     def close(self):
         if self._b is not None:
@@ -546,7 +546,7 @@ class Batch:
         i = sgtv_batch_add_scan(self._b, prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col,
                                 prob.val, prob.y, prob.r, prob.beta if beta is None else beta, prob.rho,
                                 schedule, w, grouping)
-        self._J.append(prob.ny * prob.nx * prob.Q)
+        self._J[i] = prob.ny * prob.nx * prob.Q
         return i
 
     def __len__(self):

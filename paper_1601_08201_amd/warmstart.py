@@ -240,6 +240,24 @@ def warm_start(R, net, model, shape):
     return k, True
 
 
+def restart_without_network(R, k):
+    """The ablation of the learned start: from the uniform start, k plain
+    iterations, then a restart from that image with the consistent split and
+    dual (sgtv_set_init_dual), as warm_start does with the network's image.
+    Returns the plain iterations spent."""
+    R.set_init(None)
+    R.iterate(k)
+    R.set_init_dual(R.image())
+    return k
+
+
+def constant_loss(xin, tgt, mode):
+    """Mean squared error of the constant prediction 1 against the scaled
+    training targets (the loss of a network that learned nothing but the mean)."""
+    t, _ = training_targets(xin, tgt, mode)
+    return float(np.mean((t.astype(np.float64) - 1.0) ** 2))
+
+
 def iterations_to_target(R, phi_star, tol=1e-4, check=5, cap=3000):
     """Iterate (already initialised) until objective <= phi_star (1 + tol),
     checking every `check` iterations; returns (iterations, reached)."""

@@ -230,6 +230,30 @@ void check_case(const char *name, const Csr &m, TileParams t, bool want24, bool 
                 slot.empty() ? "contiguous" : "dealt", static_cast<long long>(sum_max));
 }
 
+// The packed arrays of one case built with one host thread and with eight.
+void check_threads(const char *name, const Csr &m, TileParams t) {
+    std::vector<int32_t> pk[2], goff[2], poff[2];
+    std::vector<float> pv[2];
+    std::vector<uint16_t> slot[2];
+    sgtv::TileMap map[2]{};
+    const char *counts[2] = {"1", "8"};
+    for (int k = 0; k < 2; ++k) {
+        setenv("SGTV_HOST_THREADS", counts[k], 1);
+        const int e = build_tiled(m.n_rows, m.n_cols, m.rp, m.ci, m.v, t, true, pk[k], pv[k], goff[k], poff[k],
+                                  slot[k], map[k]);
+        CHECK(e == SGTV_OK, "%s: build with %s threads failed", name, counts[k]);
+    }
+    unsetenv("SGTV_HOST_THREADS");
+    CHECK(pk[0] == pk[1], "%s: packed indices differ between 1 and 8 threads", name);
+    CHECK(pv[0].size() == pv[1].size() &&
+              std::memcmp(pv[0].data(), pv[1].data(), sizeof(float) * pv[0].size()) == 0,
+          "%s: values differ between 1 and 8 threads", name);
+    CHECK(goff[0] == goff[1] && poff[0] == poff[1] && slot[0] == slot[1],
+          "%s: list offsets or slot tables differ between 1 and 8 threads", name);
+    CHECK(std::memcmp(&map[0], &map[1], sizeof(map[0])) == 0, "%s: tile maps differ", name);
+    std::printf("%s: identical with 1 and 8 host threads\n", name);
+}
+
 }  // namespace
 
 int main() {
@@ -241,6 +265,11 @@ int main() {
     check_case("24-bit, long row runs and duplicates", b, TileParams{64, 8, 512, 1}, true, true);
     const Csr c = make_csr(2048, 200000, 30, 3, false);
     check_case("24-bit, counts past 2^22: contiguous rows", c, TileParams{64, 16, 12, 1}, true, false);
+    check_threads("threads, 24-bit dealt rows", a, TileParams{64, 4, 1024, 2});
+    check_threads("threads, 32-bit", a, TileParams{100, 4, 1023, 2});
+    check_threads("threads, long row runs", b, TileParams{64, 8, 512, 1});
+    const Csr d = make_csr(40000, 30000, 16, 4, false);
+    check_threads("threads, many row blocks", d, TileParams{128, 16, 4096, 4});
     if (failures) return 1;
     std::printf("ok\n");
     return 0;

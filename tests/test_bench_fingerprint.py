@@ -1,5 +1,6 @@
-"""The committed HBM counter summary is keyed on the product kernels' code:
-an edit of comments or white space keeps it valid, an edit of code does not
+"""The committed HBM counter summary is keyed on the product kernels' code,
+the host builder of the tiled format and the schedule: an edit of comments or
+white space keeps it valid, an edit of code or another schedule does not
 (CPU only)."""
 import importlib.util
 import os
@@ -8,7 +9,7 @@ import shutil
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-FILES = ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h")
+FILES = ("sgtv_tiled.hip", "sgtv_device.h", "sgtv_kernels.h", "sgtv_api.hip")
 
 
 @pytest.fixture()
@@ -37,8 +38,8 @@ def test_committed_summary_is_readable(bench):
     assert re.fullmatch(r"[0-9a-f]{64}", rec["kernel_source_sha256"])
     for k in ("forward", "back"):
         assert 0.8e9 < rec["traffic_bytes_per_launch"][k] < 1.2e9
-        got = bench.measured_traffic(k, "f32", "tiled", "paper")
-        if rec["kernel_source_sha256"] == bench.kernel_fingerprint():
+        got = bench.measured_traffic(k, "f32", "tiled", "paper", rec.get("schedule"))
+        if rec["kernel_source_sha256"] == bench.kernel_fingerprint(rec.get("schedule")):
             assert got == rec["traffic_bytes_per_launch"][k]
         else:
             assert got is None
@@ -55,3 +56,15 @@ def test_comments_do_not_change_the_fingerprint(bench, tmp_path, monkeypatch):
     p = dst / "sgtv_tiled.hip"
     p.write_text(p.read_text().replace("kXPrefetch = 4", "kXPrefetch = 2"))
     assert bench.kernel_fingerprint() != ref
+
+
+def test_builder_and_schedule_change_the_fingerprint(bench, tmp_path, monkeypatch):
+    dst = copy_tree(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    ref = bench.kernel_fingerprint({"waves": 16})
+    assert bench.kernel_fingerprint({"waves": 8}) != ref
+    p = dst / "sgtv_api.hip"
+    text = p.read_text()
+    assert "16380" in text[text.find("TileParams choose_tiles("):text.find("struct System {")]
+    p.write_text(text.replace("std::min<int64_t>(16380,", "std::min<int64_t>(16376,", 1))
+    assert bench.kernel_fingerprint({"waves": 16}) != ref

@@ -127,6 +127,30 @@ def test_adam_first_step_follows_gradient_signs(sg):
     np.testing.assert_allclose(step[big], ((q - p) / lr)[big], atol=2e-3)
 
 
+def test_adam_five_steps_against_fp64(sg):
+    """Five Adam steps on the GPU's own gradients: after each step every
+    parameter equals the FP64 oracle's Adam (Kingma and Ba) fed the same
+    gradients, to FP32 rounding of the parameters and moments."""
+    x, t = data(9)
+    p = layer_params(sg, 2, 10)
+    N = sg.WarmStartNet(layers=2, height=8, max_batch=4).set_params(p)
+    q = p.astype(np.float64).copy()
+    m = np.zeros_like(q)
+    v = np.zeros_like(q)
+    g = np.empty(p.size, np.float32)
+    lrs = [1e-3, 2e-3, 5e-4, 1e-3, 3e-3]
+    for step, lr in enumerate(lrs, start=1):
+        N.backward(x, t, g)
+        N.adam_step(lr=lr)
+        oracle.wn_adam(q, g.astype(np.float64), m, v, step, lr=lr)
+        got = N.params().astype(np.float64)
+        err = np.abs(got - q)
+        print("adam step", step, "max abs error", err.max(), "moved", np.abs(q - p).max(), flush=True)
+        np.testing.assert_allclose(got, q, rtol=1e-6, atol=1e-8)
+    # the parameters moved by many times the tolerance
+    assert np.median(np.abs(q - p)) > 1e-4
+
+
 def test_training_lowers_the_loss(sg):
     x, _ = data(6, B=4)
     t = np.sqrt(x).astype(np.float32)

@@ -5,7 +5,8 @@ from synthetic CSR matrices with the library's own builder and decodes it
 independently of the kernels: every matrix entry stored exactly once with its
 value bits, padding that adds zero, lane-owned 24-bit lists, distinct rows per
 group in 32-bit lists, and a permutation per tile when rows are dealt to the
-waves.  Cases: dealt rows, 16 waves over 3 slabs, the 32-bit format, long row
+waves; and the packed arrays built on one host thread and on eight are byte
+for byte the same.  Cases: dealt rows, 16 waves over 3 slabs, the 32-bit format, long row
 runs with duplicate entries, and the contiguous order kept past 2^22 counts."""
 import os
 import subprocess
@@ -30,3 +31,4 @@ def test_tiled_format_round_trips(tmp_path):
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("ok")
     assert out.stdout.count("dealt rows") >= 3 and "contiguous rows" in out.stdout
+    assert out.stdout.count("identical with 1 and 8 host threads") == 4
