@@ -2338,7 +2338,8 @@ int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps
     const double c2 = 1.0 - std::pow(beta2, static_cast<double>(net->step));
     HIP_TRY(sgtv::wsn::adam(net->params.as<float>(), net->grad.as<float>(), net->m.as<float>(),
                             net->v.as<float>(), net->n_param, static_cast<float>(lr), static_cast<float>(beta1),
-                            static_cast<float>(beta2), static_cast<float>(eps), static_cast<float>(c1),
+                            static_cast<float>(beta2), static_cast<float>(1.0 - beta1),
+                            static_cast<float>(1.0 - beta2), static_cast<float>(eps), static_cast<float>(c1),
                             static_cast<float>(c2), net->stream));
     if (int e = net_weights(net)) return e;
     return SGTV_OK;

@@ -329,14 +329,16 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ out,
     block_sum_store(acc, partials + blockIdx.x);
 }
 
+// 1 - beta1 and 1 - beta2 come from the host, formed in FP64: 1 - 0.999f in
+// FP32 would be 0.000999987, a 1.3e-5 relative error in every second moment.
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float omb1,
+                       float omb2, float eps, float c1, float c2) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const float gi = g[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        const float mi = b1 * m[i] + omb1 * gi;
+        const float vi = b2 * v[i] + omb2 * gi * gi;
         m[i] = mi;
         v[i] = vi;
         p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -459,9 +461,9 @@ hipError_t mse_grad(const float *out, const float *target, const float *z, int64
 }
 
 hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
-                float b2, float eps, float c1, float c2, hipStream_t st) {
+                float b2, float omb1, float omb2, float eps, float c1, float c2, hipStream_t st) {
     hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256))),
-                       dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+                       dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, omb1, omb2, eps, c1, c2);
     return hipGetLastError();
 }
 
