@@ -232,6 +232,19 @@ int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes);
  * J floats, of the data currently set. */
 int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result
+ * as sgtv_backprojection, computed without any allocation.  Its intermediate
+ * vectors live in a static device buffer of the library (8388608 floats,
+ * 32 MiB, on every GPU the library runs on, held until the process ends), so
+ * J may be at most SGTV_NOALLOC_MAX_VOXELS (SGTV_ESHAPE beyond).  x (J
+ * floats) is host or device memory as mem_kind says; the call synchronises
+ * the context stream.  Every call on one GPU uses the same buffer: calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller. */
+#define SGTV_NOALLOC_MAX_VOXELS 4194304
+int sgtv_backprojection_noalloc(sgtv_ctx ctx, float *x, int mem_kind);
+
 /*
  * Launch schedule of the two sparse products A f and A^T t.  Takes effect at
  * the next sgtv_set_system; zero fields are chosen automatically.

@@ -21,9 +21,37 @@
 #include "sgtv_kernels.h"
 #include "sgtv_wsnet.h"
 
+// Device buffer of sgtv_backprojection_noalloc: a file-scope array that the
+// code object brings to every GPU the library runs on, held until the process
+// ends.  Host code must not pass `scratch` itself to a kernel (in host code it
+// names a host-side stand-in); it uses the address hipGetSymbolAddress
+// returns for the current device, kept per device by scratch_address().
+constexpr int64_t kScratchFloats = int64_t(1) << 23;   // 32 MiB
+static __device__ __align__(256) float scratch[kScratchFloats];
+
 namespace {
 
 thread_local std::string g_err;
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (at the first sgtv_create on it).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, float **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 // Spare floats after every vector that the tiled products gather from: the
 // kernels stage whole float4 groups, which may run past the last element.
@@ -1117,6 +1145,13 @@ int sgtv_create(sgtv_ctx *out, int device, void *hip_stream) {
     int n = 0;
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(SGTV_EINVAL, "device index out of range");
+    {
+        // set-up of the static device buffer on this device (once per device)
+        DeviceGuard g(device);
+        if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+        float *sp = nullptr;
+        HIP_TRY(scratch_address(device, &sp));
+    }
     try {
         auto c = new sgtv_ctx_s();
         c->device = device;
@@ -1665,6 +1700,27 @@ int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind) {
     if (int st = back_project(S, ctx->y.as<float>(), e.as<float>(), ctx->stream)) return st;
     HIP_TRY(sgtv::launch_div_safe(e.as<float>(), S.sens.as<float>(), out.as<float>(), S.J, ctx->stream));
     HIP_TRY(hipMemcpyAsync(x, out.p, sizeof(float) * S.J, to_caller(mem_kind), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SGTV_OK;
+}
+
+int sgtv_backprojection_noalloc(sgtv_ctx ctx, float *x, int mem_kind) {
+    if (int e = check_ready(ctx)) return e;
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (!x) return fail(SGTV_EINVAL, "x is NULL");
+    const System &S = *ctx->sys;
+    if (2 * S.J > kScratchFloats)
+        return fail(SGTV_ESHAPE, "sgtv_backprojection_noalloc takes at most " + std::to_string(kScratchFloats / 2) +
+                                     " hyper-voxels (J = " + std::to_string(S.J) + ")");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    float *buf = nullptr;
+    HIP_TRY(scratch_address(ctx->device, &buf));
+    // A^T y in the first J floats of the buffer, the quotient in the next J
+    float *e = buf, *q = buf + S.J;
+    if (int st = back_project(S, ctx->y.as<float>(), e, ctx->stream)) return st;
+    HIP_TRY(sgtv::launch_div_safe(e, S.sens.as<float>(), q, S.J, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(x, q, sizeof(float) * S.J, to_caller(mem_kind), ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return SGTV_OK;
 }

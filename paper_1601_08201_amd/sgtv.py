@@ -17,6 +17,7 @@ import numpy as np
 from .build import LIB_PATH
 
 SGTV_OK, SGTV_EINVAL, SGTV_ESHAPE, SGTV_ESTATE, SGTV_EDEVICE, SGTV_ENOMEM = 0, -1, -2, -3, -4, -5
+SGTV_NOALLOC_MAX_VOXELS = 4194304   # largest J of sgtv_backprojection_noalloc
 SGTV_F32, SGTV_BF16, SGTV_F16 = 0, 1, 2
 SGTV_HOST, SGTV_DEVICE = 0, 1
 WSNET_START_RATIO, WSNET_START_DIRECT = 0, 1
@@ -99,6 +100,7 @@ def lib():
             "sgtv_get_state": (_I, [_P, _P, _P, _P, ctypes.POINTER(_I64), _I]),
             "sgtv_set_state": (_I, [_P, _P, _P, _P, _I64, _I]),
             "sgtv_backprojection": (_I, [_P, _P, _I]),
+            "sgtv_backprojection_noalloc": (_I, [_P, _P, _I]),
             "sgtv_set_profiling": (_I, [_P, _I]),
             "sgtv_set_graphs": (_I, [_P, _I]),
             "sgtv_batch_create": (_I, [ctypes.POINTER(_P), _I, _P]),
@@ -320,6 +322,16 @@ def sgtv_backprojection(ctx, out=None):
     out = _out(n_img, out)
     p, mk = _out_arg(out)
     _check(lib().sgtv_backprojection(ctx, p, mk))
+    return out
+
+
+def sgtv_backprojection_noalloc(ctx, out=None):
+    """As sgtv_backprojection, with no device allocation inside the call (the
+    library's static device buffer holds the intermediates)."""
+    n_img, _, _ = sgtv_state_sizes(ctx)
+    out = _out(n_img, out)
+    p, mk = _out_arg(out)
+    _check(lib().sgtv_backprojection_noalloc(ctx, p, mk))
     return out
 
 
