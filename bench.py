@@ -204,17 +204,34 @@ def batch_main(args):
     b.record(stream)
     torch.cuda.synchronize()
     ms_batched = a.elapsed_time(b)
+    # the same batch continued in one cooperative launch per call (persistent kernel)
+    B.set_launch("persistent")
+    B.iterate(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.iterate(args.steps)
+    torch.cuda.synchronize()
+    ms_persistent = 1e3 * (time.perf_counter() - t0)
+    B.phase_times()
+    B.iterate(args.steps)   # again, for the phase clocks of the persistent kernel
+    ph, ph_it = B.phase_times()
+    phases = {k: v / max(ph_it, 1) for k, v in zip(("forward+split", "ratio", "back", "image_update",
+                                                     "last_split"), ph.tolist())}
+    log("persistent phases, ms per iteration: " + json.dumps(phases))
+    B.set_launch("graph")
+    log("batched: graph %.3f ms/iter, persistent %.3f ms/iter (grid %d)"
+        % (ms_batched / args.steps, ms_persistent / args.steps, B.launch()[1]))
     # error against the FP64 oracle of the two smallest scans after the same iterations
     err = []
     if not args.no_cpu_baseline:
         nth = host_threads()
         for k in sorted(range(len(probs)), key=lambda k: probs[k].nnz)[:2]:
             p = oracle_problem(probs[k])
-            f_or, _, _ = oracle_run(p, args.warmup + args.steps, nth)
+            n_done = 2 * (args.warmup + args.steps)
+            f_or, _, _ = oracle_run(p, n_done, nth)
             e = oracle_error(p, B.image(index[k]), f_or)
-            err.append(dict(e, scan="%dx%dx%d" % (p.ny, p.nx, p.Q), iterations=args.warmup + args.steps))
-            log("scan %s after %d iterations vs the FP64 oracle: %s" % (err[-1]["scan"], args.warmup + args.steps,
-                                                                        json.dumps(e)))
+            err.append(dict(e, scan="%dx%dx%d" % (p.ny, p.nx, p.Q), iterations=n_done))
+            log("scan %s after %d iterations vs the FP64 oracle: %s" % (err[-1]["scan"], n_done, json.dumps(e)))
     B.close()
     # the same scans one after another, each with its own single-scan schedule
     # (tuned when cached): a scan launched alone has to fill the GPU by itself
@@ -248,6 +265,10 @@ def batch_main(args):
                                "I = J/2, 32 nnz/col; %d unknowns, %d nonzeros" % (len(probs), unknowns, nnz),
                    "global_batch": len(probs), "parallelism": "single GPU"},
         "sequential": {"value": scan_its / (ms_seq * 1e-3), "ms_per_step": ms_seq / args.steps},
+        "persistent": {"value": scan_its / (ms_persistent * 1e-3), "ms_per_step": ms_persistent / args.steps,
+                       "note": "one cooperative launch per call with grid barriers; host clock around the "
+                               "call, which waits for the launch",
+                       "phase_ms_per_iteration": phases},
         "speedup_vs_sequential": ms_seq / ms_batched,
         "batch_iteration_alg_GBs": alg * args.steps / (ms_batched * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": "whole batched iteration",
@@ -277,10 +298,12 @@ def sweep_main(args):
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def run(sequential):
+    def run(sequential, persistent=False):
         B = sgtv.Batch(stream=stream.cuda_stream)
         for g, b in pairs:
             B.add_scan(prob, w=w, grouping=g, beta=b)
+        if persistent:
+            B.set_launch("persistent")
         it = B.iterate_sequential if sequential else B.iterate
         it(args.warmup)
         B.prepare(args.steps, sequential=sequential)   # graph capture outside the timed region
@@ -294,6 +317,15 @@ def sweep_main(args):
 
     B, ms_batched = run(False)
     Bs, ms_seq = run(True)
+    Bp, ms_pers = run(False, persistent=True)
+    ph, ph_it = Bp.phase_times()
+    phases = {k: v / max(ph_it, 1) for k, v in zip(("forward+split", "ratio", "back", "image_update",
+                                                     "last_split"), ph.tolist())}
+    log("sweep persistent phases, ms per iteration: " + json.dumps(phases))
+    same_p = all(np.array_equal(B.image(i), Bp.image(i)) for i in range(len(pairs)))
+    log("sweep persistent launch: %.4f ms/iter (graph %.4f), images equal: %s"
+        % (ms_pers / args.steps, ms_batched / args.steps, same_p))
+    Bp.close()
     S, Q = prob.ny * prob.nx, prob.Q
     res = []
     same = True
@@ -349,6 +381,8 @@ def sweep_main(args):
                    "global_batch": len(pairs), "parallelism": "single GPU"},
         "sequential": {"value": scan_its / (ms_seq * 1e-3), "ms_per_step": ms_seq / args.steps,
                        "images_bitwise_equal": same},
+        "persistent": {"value": scan_its / (ms_pers * 1e-3), "ms_per_step": ms_pers / args.steps,
+                       "images_bitwise_equal": same_p, "phase_ms_per_iteration": phases},
         "speedup_vs_sequential": ms_seq / ms_batched,
         "selected": {study.GROUPINGS[g]: {"beta": r["beta"], "spatial_error": r["spatial_error"],
                                           "spectral_error": r["spectral_error"]} for g, r in best.items()},

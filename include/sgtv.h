@@ -332,6 +332,29 @@ int sgtv_batch_iterate(sgtv_batch b, int n_iters);
  * batch or n_iters = 0.  Errors as sgtv_prepare, and SGTV_EINVAL for a
  * sequential other than 0 or 1. */
 int sgtv_batch_prepare(sgtv_batch b, int n_iters, int sequential);
+/* How sgtv_batch_iterate runs the iterations.
+ *   SGTV_BATCH_GRAPH (default): five batched launches per iteration, the n
+ *     iterations captured into one HIP graph (asynchronous).
+ *   SGTV_BATCH_PERSISTENT: one cooperative launch (hipLaunchCooperativeKernel:
+ *     a grid that cannot be resident at once is refused) of one workgroup per
+ *     free slot of every CU runs all n iterations, its workgroups walking the
+ *     phases of every scan with grid-wide barriers between dependent phases
+ *     (four per iteration).  A barrier wait is bounded (two seconds): past it
+ *     the launch is abandoned, the call returns SGTV_EDEVICE and the batch
+ *     state is undefined.  The call waits for the launch.  Needs a multiple of
+ *     4 waves per workgroup.
+ * Both give bitwise the same images.  get_launch also reports the grid of the
+ * last persistent launch (0 before the first). */
+enum { SGTV_BATCH_GRAPH = 0, SGTV_BATCH_PERSISTENT = 1 };
+int sgtv_batch_set_launch(sgtv_batch b, int mode);
+int sgtv_batch_get_launch(sgtv_batch b, int *mode, int32_t *grid);
+/* Time spent in each phase of the persistent launches since the last call,
+ * as workgroup 0 sees it (clock ticks between its barrier exits), in
+ * milliseconds: ms[0] forward products with the previous split, ms[1] ratio,
+ * ms[2] back products, ms[3] image update, ms[4] the final split of each
+ * launch; *iters = the iterations they cover.  Clears the record. */
+int sgtv_batch_phase_times(sgtv_batch b, double *ms, int64_t *iters);
+
 /* The same iterations scan after scan, each with its own graph: the
  * reference the batched launch is measured against. */
 int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters);

@@ -1794,6 +1794,12 @@ struct sgtv_batch_s {
     int fcur = 0, vcur = 0;
     hipStream_t cap = nullptr;
     std::vector<sgtv_ctx_s::Graph> graphs;
+    // persistent launch: arrival counter and error flag of its grid barriers
+    int launch = SGTV_BATCH_GRAPH;
+    DBuf bar, pdev, ticks;            // barrier and queue counters; the kernel's table; phase clocks
+    sgtv::PersistentDev pdev_host{};
+    int persistent_grid = 0;
+    int64_t persistent_iters = 0;     // iterations behind the phase clocks
     ~sgtv_batch_s() {
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
         if (cap) (void)hipStreamDestroy(cap);
@@ -1929,6 +1935,81 @@ void batch_sync_scans(sgtv_batch_s *b, int n_iters) {
     }
 }
 
+// Iterations per cooperative launch: the barrier counter (4 arrivals of every
+// workgroup per iteration) stays far below 2^32.
+constexpr int kPersistentChunk = 100000;
+// Longest wait at one grid barrier before the launch is abandoned.
+constexpr double kBarrierLimitSeconds = 2.0;
+
+// n_iters iterations of every scan in cooperative launches of the persistent
+// kernel; waits for them and reports a barrier that timed out.
+int batch_persistent(sgtv_batch_s *b, int n_iters) {
+    if (b->dirty)
+        if (int e = batch_tables(b)) return e;
+    if (b->waves % 4 != 0)
+        return fail(SGTV_EINVAL, "the persistent launch needs a multiple of 4 waves per workgroup");
+    if (!b->bar.p) HIP_TRY(b->bar.alloc(sizeof(uint32_t) * sgtv::kBarWords));
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+    if (khz <= 0) return fail(SGTV_EDEVICE, "no wall-clock rate for the grid barriers");
+    const uint64_t limit = static_cast<uint64_t>(kBarrierLimitSeconds * 1000.0 * khz);
+    if (!b->pdev.p) HIP_TRY(b->pdev.alloc(sizeof(sgtv::PersistentDev)));
+    if (!b->ticks.p) {
+        HIP_TRY(b->ticks.alloc(sizeof(uint64_t) * sgtv::kPhaseSlots));
+        HIP_TRY(hipMemsetAsync(b->ticks.p, 0, sizeof(uint64_t) * sgtv::kPhaseSlots, b->stream));
+    }
+    {
+        sgtv::PersistentDev &D = b->pdev_host;
+        D.tiles_f = b->tiles_f.as<sgtv::BatchTile>();
+        D.tiles_b = b->tiles_b.as<sgtv::BatchTile>();
+        D.maps_f = b->maps_f.as<sgtv::TileMap>();
+        D.maps_b = b->maps_b.as<sgtv::TileMap>();
+        D.xs_f0 = b->xs_f[0].as<const float *>();
+        D.xs_f1 = b->xs_f[1].as<const float *>();
+        D.xs_b = b->xs_b.as<const float *>();
+        D.parts_f = b->parts_f.as<float *>();
+        D.parts_b = b->parts_b.as<float *>();
+        D.scans = b->scandev.as<sgtv::ScanDev>();
+        D.rblocks = b->rblocks.as<sgtv::BatchBlock>();
+        D.vblocks = b->vblocks.as<sgtv::BatchBlock>();
+        D.sblocks = b->sblocks.as<sgtv::BatchBlock>();
+        D.bar = b->bar.as<uint32_t>();
+        D.limit = limit;
+        D.ticks = b->ticks.as<uint64_t>();
+        HIP_TRY(hipMemcpyAsync(b->pdev.p, &D, sizeof(D), hipMemcpyHostToDevice, b->stream));
+    }
+    for (int done = 0; done < n_iters;) {
+        const int n = std::min(n_iters - done, kPersistentChunk);
+        HIP_TRY(hipMemsetAsync(b->bar.p, 0, sizeof(uint32_t) * sgtv::kBarWords, b->stream));
+        const sgtv::PersistentPlan plan{b->n_tiles_f, b->n_tiles_b, b->n_rblocks, b->n_vblocks, b->n_sblocks,
+                                        n, b->fcur, b->vcur, b->waves / 4};
+        const size_t lds = std::max(b->lds_f, b->lds_b);
+        const int threads = b->waves * sgtv::kWave;
+        const char *what = "";
+        if (hipError_t e = sgtv::persistent_grid(b->variant, threads, lds, &b->persistent_grid, &what))
+            return hip_fail(e, (std::string("persistent launch: ") + what).c_str());
+        if (hipError_t e = sgtv::launch_admm_persistent(b->pdev.as<sgtv::PersistentDev>(), plan, lds, threads,
+                                                        b->variant, b->persistent_grid, b->stream))
+            return hip_fail(e, ("persistent launch: hipLaunchCooperativeKernel (grid " +
+                                std::to_string(b->persistent_grid) + " x " + std::to_string(threads) +
+                                " threads, " + std::to_string(lds) + " bytes of LDS)").c_str());
+        int err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, b->bar.as<int>() + sgtv::kBarErr, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        if (err)
+            return fail(SGTV_EDEVICE, "persistent launch: a grid barrier waited longer than its limit and the "
+                                      "launch was abandoned; the batch state is undefined");
+        if (n & 1) {
+            b->fcur ^= 1;
+            b->vcur ^= 1;
+        }
+        batch_sync_scans(b, n);
+        b->persistent_iters += n;
+        done += n;
+    }
+    return SGTV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2055,6 +2136,7 @@ int sgtv_batch_iterate(sgtv_batch b, int n_iters) {
     if (n_iters < 0) return fail(SGTV_EINVAL, "n_iters must be >= 0");
     if (b->scans.empty() || n_iters == 0) return SGTV_OK;
     DeviceGuard g(b->device);
+    if (b->launch == SGTV_BATCH_PERSISTENT) return batch_persistent(b, n_iters);
     sgtv_ctx_s::Graph gr{};
     if (int e = batch_graph(b, n_iters, &gr)) return e;
     HIP_TRY(hipGraphLaunch(gr.exec, b->stream));
@@ -2075,6 +2157,7 @@ int sgtv_batch_prepare(sgtv_batch b, int n_iters, int sequential) {
     }
     if (b->scans.empty() || n_iters == 0) return SGTV_OK;
     DeviceGuard g(b->device);
+    if (b->launch == SGTV_BATCH_PERSISTENT) return b->dirty ? batch_tables(b) : SGTV_OK;
     sgtv_ctx_s::Graph gr{};
     return batch_graph(b, n_iters, &gr);
 }
@@ -2088,6 +2171,38 @@ int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters) {
         b->fcur = b->scans.front()->fcur;
         b->vcur = b->scans.front()->vcur;
     }
+    return SGTV_OK;
+}
+
+int sgtv_batch_set_launch(sgtv_batch b, int mode) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (mode != SGTV_BATCH_GRAPH && mode != SGTV_BATCH_PERSISTENT)
+        return fail(SGTV_EINVAL, "launch mode must be SGTV_BATCH_GRAPH or SGTV_BATCH_PERSISTENT");
+    b->launch = mode;
+    return SGTV_OK;
+}
+
+int sgtv_batch_get_launch(sgtv_batch b, int *mode, int32_t *grid) {
+    if (!b || !mode) return fail(SGTV_EINVAL, "null argument");
+    *mode = b->launch;
+    if (grid) *grid = b->persistent_grid;
+    return SGTV_OK;
+}
+
+int sgtv_batch_phase_times(sgtv_batch b, double *ms, int64_t *iters) {
+    if (!b || !ms || !iters) return fail(SGTV_EINVAL, "null argument");
+    for (int k = 0; k < sgtv::kPhaseSlots; ++k) ms[k] = 0.0;
+    *iters = b->persistent_iters;
+    if (!b->ticks.p) return SGTV_OK;
+    DeviceGuard g(b->device);
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+    uint64_t t[sgtv::kPhaseSlots] = {};
+    HIP_TRY(hipMemcpyAsync(t, b->ticks.p, sizeof(t), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    HIP_TRY(hipMemsetAsync(b->ticks.p, 0, sizeof(t), b->stream));
+    for (int k = 0; k < sgtv::kPhaseSlots; ++k) ms[k] = khz > 0 ? static_cast<double>(t[k]) / khz : 0.0;
+    b->persistent_iters = 0;
     return SGTV_OK;
 }
 

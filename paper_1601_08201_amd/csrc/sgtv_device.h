@@ -234,6 +234,59 @@ __device__ __forceinline__ void split_bin(int64_t s, bool active, int ls, int se
     }
 }
 
+// ---------------------------------------------------------------- batched elements
+// One element of the batched elementwise steps, on scan S with the image and
+// split buffers of parity fcur / vcur (the arithmetic of the single-scan
+// kernels, so a scan of a batch reproduces its own run bit for bit).
+
+// ratio_i = y_i / (sum of the forward partials + r_i)
+__device__ __forceinline__ void batch_ratio_elem(const ScanDev &S, int64_t i) {
+    if (i >= S.I) return;
+    float acc = S.fpart[i];
+    for (int k = 1; k < S.ns_f; ++k) acc += S.fpart[static_cast<int64_t>(k) * S.I + i];
+    const float p = acc + S.r[i];
+    S.ratio[i] = S.y[i] / p;
+}
+
+// image update of hyper-voxel j: reads f[fcur], writes f[fcur ^ 1] (FP32 values)
+__device__ __forceinline__ void batch_voxel_elem(const ScanDev &S, int64_t j, int fcur, int vcur) {
+    if (j >= S.grid.J) return;
+    auto e = [&]() {
+        float s = S.bpart[j];
+        for (int k = 1; k < S.ns_b; ++k) s += S.bpart[static_cast<int64_t>(k) * S.grid.J + j];
+        return s;
+    };
+    const float *g = S.f[fcur], *v = S.v[vcur], *a = S.a[vcur];
+    float gnew;
+    if (S.grouping == 0)
+        gnew = S.wts.full ? voxel_update_value<0, true>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam)
+                          : voxel_update_value<0, false>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam);
+    else
+        gnew = S.wts.full ? voxel_update_value<1, true>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam)
+                          : voxel_update_value<1, false>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam);
+    S.f[fcur ^ 1][j] = gnew;
+}
+
+// split and dual update of the 256-thread block that starts at spatial bin s0
+// (one segment of 2^seg_log2 lanes per bin; t = thread within the block): the
+// new image is f[fcur], (v, a) is read from parity vcur and written to vcur ^ 1.
+// Every lane of the calling waves must take part (segment shuffles).
+__device__ __forceinline__ void batch_split_block(const ScanDev &S, int64_t s0, int t, int fcur, int vcur) {
+    const int sl = S.seg_log2;
+    const int64_t s = s0 + (t >> sl);
+    const int ls = t & ((1 << sl) - 1);
+    const float *f = S.f[fcur], *v = S.v[vcur], *a = S.a[vcur];
+    float *vn = S.v[vcur ^ 1], *an = S.a[vcur ^ 1];
+    const bool act = s < S.grid.S;
+    if (S.grouping == 0) {
+        if (S.wts.full) split_bin<0, true>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+        else split_bin<0, false>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+    } else {
+        if (S.wts.full) split_bin<1, true>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+        else split_bin<1, false>(s, act, ls, sl, f, v, a, vn, an, S.grid, S.wts, S.thr);
+    }
+}
+
 // Split state that makes image f a fixed point of the split update: with
 // d = w.*G f and thr = beta / rho, the scaled dual satisfying the optimality
 // condition of Eq. 5 is c_g = thr d_g / ||d_g|| on every group g with d_g != 0

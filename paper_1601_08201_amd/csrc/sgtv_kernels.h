@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sgtv_persistent.h"
+
 namespace sgtv {
 
 constexpr int kWave = 64;          // wavefront width on gfx950
@@ -94,7 +96,37 @@ struct BatchBlock {
     int64_t start;
 };
 
+// Arguments of the persistent batched iteration (one cooperative launch of
+// n iterations over every scan; the order of work: sgtv_persistent.h).
+// The tables live in device memory (the kernel indexes them at run time).
+struct PersistentDev {
+    const BatchTile *tiles_f, *tiles_b;
+    const TileMap *maps_f, *maps_b;
+    const float *const *xs_f0;      // forward input of every scan for fc = 0 (f[0]) ...
+    const float *const *xs_f1;      // ... and fc = 1 (f[1])
+    const float *const *xs_b;       // back input (the ratio) of every scan
+    float *const *parts_f, *const *parts_b;
+    const ScanDev *scans;
+    const BatchBlock *rblocks, *vblocks, *sblocks;
+    uint32_t *bar;                  // kBarWords counters, all 0 at launch (layout below)
+    uint64_t limit;                 // longest wait at a barrier, in wall-clock ticks
+    uint64_t *ticks;                // kPhaseSlots clock ticks added by workgroup 0: phases A-D
+                                    // (from one barrier exit to the next), the last split
+};
+constexpr int kPhaseSlots = 5;
+
+// Words of the persistent launch's counter buffer, each on its own 64-byte line:
+// barrier arrivals (all workgroups), the error flag, the arrivals of every
+// workgroup group g = wg mod 8, and the forward and back tile queues.
+constexpr int kBarGlobal = 0, kBarErr = 1, kBarGroup = 16, kBarQueueF = 160, kBarQueueB = 288;
+constexpr int kBarWords = 416;
+
 // Launchers (all asynchronous on `st`).
+// Workgroups of the persistent launch (all resident at once); *what names the
+// call that failed.
+hipError_t persistent_grid(int variant, int threads, size_t lds, int *grid, const char **what);
+hipError_t launch_admm_persistent(const PersistentDev *D, const PersistentPlan &plan, size_t lds,
+                                  int threads, int variant, int grid, hipStream_t st);
 hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
                               const float *const *xs, float *const *parts, int waves, size_t lds,
                               int variant, hipStream_t st);

@@ -11,6 +11,7 @@
 // by at most one lane per instruction, so read-modify-write needs no atomics
 // and each sum has a fixed order.
 #include "sgtv_device.h"
+#include "sgtv_persistent.h"
 
 namespace sgtv {
 
@@ -113,7 +114,7 @@ __device__ __forceinline__ void tile_super24(const U4 A, const U4 B, const U4 C,
 // MODE 2: MODE 1, and the next column block is read into registers (kXPrefetch
 //         float4 per thread; needs cb <= 16 * threads) after the last batch
 //         of the current block has been issued.
-template <int VT, int MODE>
+template <int VT, int MODE, bool PREFETCH = true>
 __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
                                            const int32_t *__restrict__ pk,
                                            const typename Code<VT>::T *__restrict__ val,
@@ -162,7 +163,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     // the next column block is read into registers before the block barrier
     // (so its latency overlaps the wait there): MODE 2, and the simple loop on
     // 24-bit lists when the block fits the prefetch registers
-    const bool pre = MODE == 2 || (MODE == 0 && M.idx24 && M.cb <= kXPrefetch * 4 * nthr);
+    const bool pre = PREFETCH && (MODE == 2 || (MODE == 0 && M.idx24 && M.cb <= kXPrefetch * 4 * nthr));
     for (int c = 0; c < ncbs; ++c) {
         const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
         const int g0 = goff[L];
@@ -298,6 +299,113 @@ __global__ __launch_bounds__(1024) void k_tiled_batch(const BatchTile *__restric
     const TileMap &M = maps[bt.scan];
     tiled_body<VT, MODE>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
                          M.goff, xs[bt.scan], parts[bt.scan]);
+}
+
+// ---------------------------------------------------------------- persistent batch
+// All phases of n ADMM iterations of a batch in one cooperative launch (the
+// order of work, its dependences and the tile queues: sgtv_persistent.h).
+// Between dependent phases every workgroup waits at a grid barrier: each wave
+// waits for its own memory operations, then one thread makes the workgroup's
+// writes visible device-wide, adds its arrival to its group's counter (the
+// last of a group adds the group to the global count) and waits for the
+// phase's count.  The wait is bounded: past `limit` ticks of the constant-rate
+// clock, or when another workgroup has already given up, the workgroup sets
+// the error flag and leaves the kernel, so every wave ends and the host
+// reports the failure.
+template <int MODE>
+struct PersistentWork {
+    const PersistentDev &D;   // in device memory
+    uint64_t *last;           // LDS: clock at the last barrier exit (workgroup 0, thread 0)
+    __device__ __forceinline__ uint32_t *word(int i) const { return D.bar + i; }
+    __device__ __forceinline__ int64_t grab(int phase, uint32_t q) {
+        __shared__ int next;
+        __syncthreads();   // every thread has read the previous index
+        if (threadIdx.x == 0)
+            next = static_cast<int>(__hip_atomic_fetch_add(
+                word((phase == kPhaseForward ? kBarQueueF : kBarQueueB) + 16 * static_cast<int>(q)), 1u,
+                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        __syncthreads();
+        return next;
+    }
+    __device__ __forceinline__ void clear(int phase) {
+        if (threadIdx.x < kMaxQueues)
+            __hip_atomic_store(word((phase == kPhaseForward ? kBarQueueF : kBarQueueB) + 16 * threadIdx.x), 0u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ void tile(int phase, int64_t t, int fc) {
+        const bool fwd = phase == kPhaseForward;
+        const BatchTile bt = (fwd ? D.tiles_f : D.tiles_b)[t];
+        if (bt.local < 0) return;   // alignment filler (uniform in the workgroup)
+        const TileMap &M = (fwd ? D.maps_f : D.maps_b)[bt.scan];
+        const float *x = fwd ? (fc ? D.xs_f1 : D.xs_f0)[bt.scan] : D.xs_b[bt.scan];
+        float *part = (fwd ? D.parts_f : D.parts_b)[bt.scan];
+        // without the register prefetch of the next column block: its 16
+        // registers would push the walk past the 128 of a 16-wave workgroup
+        // (same sums in the same order, only the timing of the staging loads
+        // differs).  grab() synchronised the workgroup before this tile.
+        tiled_body<0, MODE, false>(M, bt.local, M.pk, static_cast<const float *>(M.val), M.goff, x, part);
+    }
+    __device__ __forceinline__ void blocks(int phase, int64_t first, int64_t stride, int64_t n, int fc, int vc) {
+        const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
+        const BatchBlock *tab = phase == kPhaseRatio ? D.rblocks : phase == kPhaseVoxel ? D.vblocks : D.sblocks;
+        for (int64_t b = first + q; b < n; b += stride) {
+            const BatchBlock bb = tab[b];
+            const ScanDev &S = D.scans[bb.scan];
+            if (phase == kPhaseRatio) batch_ratio_elem(S, bb.start + t);
+            else if (phase == kPhaseVoxel) batch_voxel_elem(S, bb.start + t, fc, vc);
+            else batch_split_block(S, bb.start, t, fc, vc);
+        }
+    }
+    __device__ __forceinline__ bool barrier(uint32_t target) {
+        __shared__ int ok;
+        const uint32_t G = gridDim.x, m = target / G;
+        const uint32_t ng = persistent_queues(G), g = blockIdx.x % ng, n_g = (G - g + ng - 1) / ng;
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's loads and stores have completed
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int good = __hip_atomic_load(word(kBarErr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+            if (good) {
+                // release: the workgroup's writes (now in this XCD's L2) become visible device-wide
+                const uint32_t old = __hip_atomic_fetch_add(word(kBarGroup + 16 * static_cast<int>(g)), 1u,
+                                                            __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                if (old + 1 == m * n_g)
+                    __hip_atomic_fetch_add(word(kBarGlobal), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(word(kBarGlobal), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < m * ng) {
+                    if (__hip_atomic_load(word(kBarErr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        good = 0;
+                        break;
+                    }
+                    if (static_cast<uint64_t>(wall_clock64()) - t0 > D.limit) {
+                        __hip_atomic_store(word(kBarErr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        good = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                // acquire: the other workgroups' writes become visible here
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            ok = good;
+            if (blockIdx.x == 0) {   // phase durations as workgroup 0 sees them
+                const uint64_t now = wall_clock64();
+                D.ticks[(m - 1) % 4] += now - *last;
+                *last = now;
+            }
+        }
+        __syncthreads();
+        return ok != 0;
+    }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_admm_persistent(const PersistentDev *__restrict__ D,
+                                                          PersistentPlan plan) {
+    __shared__ uint64_t last;
+    if (threadIdx.x == 0) last = wall_clock64();
+    PersistentWork<MODE> w{*D, &last};
+    persistent_walk(plan, blockIdx.x, gridDim.x, w);
+    if (blockIdx.x == 0 && threadIdx.x == 0) D->ticks[4] += wall_clock64() - last;
 }
 
 // The same without the objective, four rows per thread (16-byte loads and
@@ -448,6 +556,52 @@ hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const Til
     if (variant == 1)
         return launch_tiled_batch_t<1>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
     return launch_tiled_batch_t<0>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
+}
+
+template <int MODE>
+static const void *persistent_fn() {
+    return reinterpret_cast<const void *>(&k_admm_persistent<MODE>);
+}
+
+hipError_t persistent_grid(int variant, int threads, size_t lds, int *grid, const char **what) {
+    const void *fn = variant == 1 ? persistent_fn<1>() : persistent_fn<0>();
+    // the dynamic limit leaves room for the kernel's own static LDS (its barrier flag)
+    auto raise = [](const void *f) {
+        hipFuncAttributes at{};
+        hipError_t e = hipFuncGetAttributes(&at, f);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   kMaxLds - static_cast<int>(at.sharedSizeBytes));
+    };
+    static const hipError_t r0 = raise(persistent_fn<0>());
+    static const hipError_t r1 = raise(persistent_fn<1>());
+    *what = "hipFuncGetAttributes / hipFuncSetAttribute";
+    if (r0 != hipSuccess) return r0;
+    if (r1 != hipSuccess) return r1;
+    int dev = 0, cus = 0, per_cu = 0;
+    *what = "hipGetDevice";
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    *what = "hipDeviceGetAttribute(multiprocessor count)";
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *what = "hipOccupancyMaxActiveBlocksPerMultiprocessor";
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (e != hipSuccess) return e;
+    *what = "occupancy of the persistent kernel";
+    if (per_cu < 1 || cus < 1) return hipErrorCooperativeLaunchTooLarge;
+    *grid = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_admm_persistent(const PersistentDev *D, const PersistentPlan &plan, size_t lds,
+                                  int threads, int variant, int grid, hipStream_t st) {
+    const void *fn = variant == 1 ? persistent_fn<1>() : persistent_fn<0>();
+    const PersistentDev *a0 = D;
+    PersistentPlan a1 = plan;
+    void *args[] = {&a0, &a1};
+    return hipLaunchCooperativeKernel(fn, dim3(static_cast<unsigned>(grid)), dim3(static_cast<unsigned>(threads)),
+                                      args, static_cast<unsigned>(lds), st);
 }
 
 hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,

@@ -111,6 +111,9 @@ def lib():
             "sgtv_batch_iterate": (_I, [_P, _I]),
             "sgtv_batch_prepare": (_I, [_P, _I, _I]),
             "sgtv_batch_iterate_sequential": (_I, [_P, _I]),
+            "sgtv_batch_set_launch": (_I, [_P, _I]),
+            "sgtv_batch_get_launch": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I32)]),
+            "sgtv_batch_phase_times": (_I, [_P, _P, ctypes.POINTER(_I64)]),
             "sgtv_batch_objective": (_I, [_P, _I32, ctypes.POINTER(Report)]),
             "sgtv_batch_get_image": (_I, [_P, _I32, _P, _I]),
             "wsnet_create": (_I, [ctypes.POINTER(_P), _I, _P, _I32, _I32, _I32, _I32, _I32]),
@@ -523,6 +526,31 @@ def sgtv_batch_iterate_sequential(b, n_iters):
     _check(lib().sgtv_batch_iterate_sequential(b, int(n_iters)))
 
 
+BATCH_LAUNCH = {"graph": 0, "persistent": 1}
+
+
+def sgtv_batch_set_launch(b, mode):
+    """mode: "graph" (five batched launches per iteration in a HIP graph) or
+    "persistent" (one cooperative launch with grid barriers)."""
+    _check(lib().sgtv_batch_set_launch(b, BATCH_LAUNCH[mode] if isinstance(mode, str) else int(mode)))
+
+
+def sgtv_batch_phase_times(b):
+    """Milliseconds per phase of the persistent launches since the last call
+    (forward + split, ratio, back, image update, final split) and the
+    iterations they cover."""
+    ms = np.zeros(5, np.float64)
+    it = _I64()
+    _check(lib().sgtv_batch_phase_times(b, ms.ctypes.data_as(_P), ctypes.byref(it)))
+    return ms, it.value
+
+
+def sgtv_batch_get_launch(b):
+    m, g = _I(), _I32()
+    _check(lib().sgtv_batch_get_launch(b, ctypes.byref(m), ctypes.byref(g)))
+    return {v: k for k, v in BATCH_LAUNCH.items()}[m.value], g.value
+
+
 def sgtv_batch_objective(b, scan):
     rep = Report()
     _check(lib().sgtv_batch_objective(b, int(scan), ctypes.byref(rep)))
@@ -577,6 +605,17 @@ class Batch:
     def iterate_sequential(self, n):
         sgtv_batch_iterate_sequential(self._b, n)
         return self
+
+    def set_launch(self, mode):
+        sgtv_batch_set_launch(self._b, mode)
+        return self
+
+    def launch(self):
+        """(mode, grid of the last persistent launch)"""
+        return sgtv_batch_get_launch(self._b)
+
+    def phase_times(self):
+        return sgtv_batch_phase_times(self._b)
 
     def objective(self, scan):
         return sgtv_batch_objective(self._b, scan)

@@ -108,3 +108,57 @@ def test_batch_prepare_both_modes(sg):
     for a, b in zip(*runs):
         np.testing.assert_array_equal(a, b)
 
+
+
+@pytest.mark.parametrize("calls", [(30,), (7, 1, 22)])
+def test_persistent_launch_equals_graph(sg, calls):
+    """One cooperative launch with grid barriers gives bitwise the images and
+    reports of the graph-replayed batched launches, also across calls of odd
+    length (buffer parities)."""
+    probs = scans()
+    A, P = sg.Batch(), sg.Batch()
+    for p in probs:
+        A.add_scan(p, schedule=SCHED)
+        P.add_scan(p, schedule=SCHED)
+    P.set_launch("persistent")
+    for n in calls:
+        print("persistent launch of", n, "iterations", flush=True)
+        A.iterate(n)
+        P.iterate(n)
+    mode, grid = P.launch()
+    print("grid", grid, flush=True)
+    assert mode == "persistent" and grid >= 1
+    for i in range(len(probs)):
+        np.testing.assert_array_equal(P.image(i), A.image(i))
+        assert P.objective(i) == A.objective(i)
+
+
+def test_persistent_launch_weights_and_groupings(sg):
+    """The paper-shaped scan with pitch weights, both groupings and two betas
+    in one persistent launch against the graph path and the oracle."""
+    prob = datagen.make_problem("teflon", 1)
+    w = prob.meta["weights"]
+    pairs = [(0, 0.2), (1, 0.05), (0, 1.0), (1, 0.5)]
+    A, P = sg.Batch(), sg.Batch()
+    for g, b in pairs:
+        A.add_scan(prob, w=w, grouping=g, beta=b)
+        P.add_scan(prob, w=w, grouping=g, beta=b)
+    P.set_launch("persistent")
+    A.iterate(41)
+    P.iterate(41)
+    for i, (g, b) in enumerate(pairs):
+        np.testing.assert_array_equal(P.image(i), A.image(i))
+        f_o, _, _, _ = oracle.admm(prob, 41, beta=b, w=w, grouping=g, report=False)
+        err = np.linalg.norm(P.image(i) - f_o) / np.linalg.norm(f_o)
+        print("grouping", g, "beta", b, "rel_l2", err, flush=True)
+        assert err <= 1e-5
+
+
+def test_launch_mode_is_checked(sg):
+    B = sg.Batch()
+    assert B.launch() == ("graph", 0)
+    with pytest.raises(sg.SgtvError):
+        sg.sgtv_batch_set_launch(B._b, 7)
+    B.set_launch("persistent")
+    B.iterate(3)          # empty batch: nothing to run
+    assert B.launch()[0] == "persistent"
