@@ -28,13 +28,15 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(prob, value_bytes, fmt):
+def algorithmic_bytes(prob, value_bytes, fmt, fused=False):
     """Bytes each kernel must move per launch: every array it needs, touched once.
 
     Tiled format: forward = A (values + indices), x, p out; ratio = p, y, r,
     ratio out; back = A, ratio, e out; image update = e, g, v, a, sens, H,
-    g out; split = f, v, a in and v, a out.  The sliced-ELL kernels fuse the
-    ratio into the forward pass and the image update into the back pass.
+    g out; split = f, v, a in and v, a out; the image and split update in one
+    pass (fused) = e, g, sens, g out, v and a in and out (48 J + 8 S bytes).
+    The sliced-ELL kernels fuse the ratio into the forward pass and the image
+    update into the back pass.
     """
     I, J, nnz = prob.I, prob.J, prob.nnz
     S = prob.ny * prob.nx
@@ -45,6 +47,9 @@ def algorithmic_bytes(prob, value_bytes, fmt):
         out["ratio"] = 16 * I
         out["back"] = a + 4 * I + 4 * J
         out["image_update"] = 4 * J + 4 * J + 16 * J + 4 * S + 4 * J + 4 * J + 4 * J
+        if fused:
+            del out["split_update"], out["image_update"]
+            out["update_fused"] = 4 * J + 4 * J + 4 * J + 4 * J + 32 * J + 8 * S
     else:
         out["forward"] = a + 4 * (I + 1) + 4 * J + 12 * I
         out["back"] = a + 4 * (J + 1) + 4 * I + 32 * J + 4 * S
@@ -697,7 +702,10 @@ def main():
     times = R.kernel_times()
     R.set_profiling(False)
     vb = {"f32": 4, "bf16": 2, "f16": 2}[args.storage]
-    alg = algorithmic_bytes(prob, vb, args.format)
+    fused = R.fused_update()[0]
+    alg = algorithmic_bytes(prob, vb, args.format, fused=fused)
+    if fused:
+        times["update_fused"] = times.pop("image_update")
     kern = {}
     for name, (tot, cnt) in times.items():
         if cnt and name in alg:
@@ -707,7 +715,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_us"])
     achieved = kern[dom]["gbs"]
     log("kernels: " + json.dumps(kern))
-    log("schedule: " + json.dumps(R.schedule()))
+    log("schedule: " + json.dumps(R.schedule()) + ", fused image and split update (tile): "
+        + json.dumps(R.fused_update()))
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

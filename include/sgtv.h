@@ -156,6 +156,19 @@ int sgtv_prepare(sgtv_ctx ctx, int n_iters);
  * the kernels one by one. */
 int sgtv_set_graphs(sgtv_ctx ctx, int enable);
 
+/* Image update and split/dual update of the last surrogate sweep in one
+ * elementwise-and-stencil pass over tiles of spatial bins (tiled format;
+ * default off): a workgroup updates the image of its tile and of a one-bin
+ * ring in LDS, then the groups of its tile from it, so the new image is not
+ * read back from memory.  The results are the same bit for bit as with the
+ * two launches; on an MI355X the two launches are faster (the ring is
+ * computed twice and a tile's LDS allows one workgroup per CU), so they stay
+ * the default.  get_fused_update reports whether the pass is used for the
+ * current system and its tile (bins in x and y; 0 when a tile's LDS would
+ * not fit). */
+int sgtv_set_fused_update(sgtv_ctx ctx, int enable);
+int sgtv_get_fused_update(sgtv_ctx ctx, int *active, int32_t *tile_x, int32_t *tile_y);
+
 /* Objective and residuals of the current state (FP64 reductions); synchronises. */
 int sgtv_objective(sgtv_ctx ctx, sgtv_report *out);
 
@@ -288,7 +301,8 @@ int sgtv_get_schedule(sgtv_ctx ctx, sgtv_schedule *s);
  * 0 forward projection A f (sliced ELL: fused with the ratio), 1
  * backprojection A^T t (sliced ELL: fused with the image update), 2 split and
  * dual update, 3 ratio y / (A f + r) of the tiled format, 4 image update of
- * the tiled format.
+ * the tiled format (with the split and dual update when they run in one pass,
+ * see sgtv_set_fused_update).
  */
 int sgtv_set_profiling(sgtv_ctx ctx, int enable);
 int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts);

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libsgtv.so")
 
-SOURCES = ["sgtv_kernels.hip", "sgtv_tiled.hip", "sgtv_batch.hip", "sgtv_wsnet.hip", "sgtv_api.hip"]
+SOURCES = ["sgtv_kernels.hip", "sgtv_tiled.hip", "sgtv_update.hip", "sgtv_batch.hip", "sgtv_wsnet.hip",
+           "sgtv_api.hip"]
 
 ARCH = "gfx950"
 

@@ -687,6 +687,9 @@ struct System {
     float w4[4] = {1, 1, 1, 1};
     bool wfull = false;
     DBuf rs_ptr, rs_idx, rs_val, cs_ptr, cs_idx, cs_val, colscale, sens, H, wbuf;
+    DBuf htab;                   // H0 by neighbour pattern (weights constant per direction)
+    int fused_tw = 0, fused_th = 0;   // tile of the fused image and split update (0: not fused)
+    int fused_threads = sgtv::kFusedThreads;
     std::vector<int64_t> perm;   // internal row -> caller row (identity for tiles)
     int64_t n_rslices = 0, n_cslices = 0;
     Tiled fwd, back;             // tiled format: A (rows = measurements), A^T (rows = voxels)
@@ -730,6 +733,9 @@ struct sgtv_ctx_s {
     // reductions
     DBuf part, red;
     int64_t part_cap = 0;
+    // image and split updates in one pass (off by default: slower here, see
+    // sgtv_set_fused_update)
+    bool fused = false;
     // graph replay of iterate(n)
     bool use_graphs = true;
     hipStream_t cap = nullptr;   // capture stream (own, created on first use)
@@ -843,6 +849,36 @@ int back_project(const System &S, const float *t, float *e, hipStream_t st) {
     return SGTV_OK;
 }
 
+// Tile of the fused image and split update: the largest of a few shapes that
+// still gives a tile for each of the 256 CUs, else the smallest (small grids
+// are latency-bound); its LDS (the tile and its ring, all spectral bins) must
+// fit.  SGTV_FUSED_TILE="tw,th" overrides the choice (measurement); tw = 0
+// turns the fused pass off.
+void choose_fused_tile(int ny, int nx, int Q, int *tw, int *th) {
+    *tw = *th = 0;
+    if (const char *e = std::getenv("SGTV_FUSED_TILE")) {
+        int a = 0, b = 0;
+        if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a >= 0 && b >= 0) {
+            if (a > 0 && b > 0 && sgtv::fused_lds_bytes(a, b, Q) <= static_cast<size_t>(sgtv::kFusedMaxLds)) {
+                *tw = a;
+                *th = b;
+            }
+            return;
+        }
+    }
+    static const int cand[][2] = {{8, 8}, {16, 4}, {8, 4}, {4, 4}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
+    int best_w = 0, best_h = 0;
+    for (const auto &c : cand) {
+        if (sgtv::fused_lds_bytes(c[0], c[1], Q) > static_cast<size_t>(sgtv::kFusedMaxLds)) continue;
+        best_w = c[0];
+        best_h = c[1];
+        const int64_t tiles = static_cast<int64_t>((nx + c[0] - 1) / c[0]) * ((ny + c[1] - 1) / c[1]);
+        if (tiles >= 256) break;
+    }
+    *tw = best_w;
+    *th = best_h;
+}
+
 int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t ny, int32_t nx,
                  int32_t Q, const int64_t *row_ptr, const int32_t *col_idx, const float *val,
                  int64_t nnz, int vt, const float *w, int64_t w_len, int mk) {
@@ -898,6 +934,25 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         }
     }
     std::vector<float> Hf(Hd.begin(), Hd.end());
+    // with weights constant per direction, H0 of a voxel depends only on which
+    // of its four neighbours lie in the grid: a table of the 16 patterns
+    std::vector<float> htab(16, 0.0f);
+    if (!S->wfull) {
+        std::vector<char> seen(16, 0);
+        for (int64_t s = 0; s < S->S; ++s) {
+            const int iy = static_cast<int>(s / nx), ix = static_cast<int>(s % nx);
+            const int m = (ix + 1 < nx ? 1 : 0) | (ix > 0 ? 2 : 0) | (iy + 1 < ny ? 4 : 0) | (iy > 0 ? 8 : 0);
+            for (int q = 0; q < Q; ++q) {
+                const float h = Hf[s * Q + q];
+                if (!seen[m]) {
+                    htab[m] = h;
+                    seen[m] = 1;
+                } else if (std::memcmp(&h, &htab[m], sizeof(float)) != 0) {
+                    return fail(SGTV_EDEVICE, "curvature differs within one neighbour pattern");
+                }
+            }
+        }
+    }
 
     // column scales and 16-bit codes
     std::vector<float> sigma;
@@ -1029,7 +1084,13 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         HIP_TRY(upload(S->cs_idx, csi));
     }
     HIP_TRY(upload(S->H, Hf));
+    HIP_TRY(upload(S->htab, htab));
     if (S->wfull) HIP_TRY(upload(S->wbuf, wf));
+    choose_fused_tile(ny, nx, Q, &S->fused_tw, &S->fused_th);
+    if (const char *e = std::getenv("SGTV_FUSED_THREADS")) {
+        const int t = std::atoi(e);
+        if (t == 256 || t == 512 || t == 1024) S->fused_threads = t;
+    }
 
     // sensitivity s = A^T 1 with the stored (possibly quantised) values
     std::vector<float> ones(static_cast<size_t>(I + kVecPad), 1.0f);
@@ -1075,6 +1136,18 @@ struct TimedLaunch {
     }
 };
 
+int seg_log2_of(int Q) {
+    int sl = 0;
+    while ((1 << sl) < Q && sl < 6) ++sl;
+    return sl;
+}
+
+// The fused image and split update applies: tiled format, a tile that fits
+bool fused_ok(const sgtv_ctx_s *c) {
+    const System &S = *c->sys;
+    return c->fused && S.format == SGTV_FORMAT_TILED && S.fused_tw > 0 && S.fused_th > 0;
+}
+
 // One ADMM iteration (Eqs. 4-6) as a launch sequence on the context stream.
 int step(sgtv_ctx_s *c) {
     const System &S = *c->sys;
@@ -1099,13 +1172,44 @@ int step(sgtv_ctx_s *c) {
                 TimedLaunch t(c, 1);
                 HIP_TRY(sgtv::launch_tiled(S.back.map, S.vt, c->ratio.as<float>(), S.bpart.as<float>(), c->stream));
             }
+            if (sw + 1 == c->sweeps && fused_ok(c)) {
+                // last sweep: the image update fused with the split and dual update
+                TimedLaunch t(c, 4);
+                sgtv::FusedUpdate A{};
+                A.part = S.bpart.as<float>();
+                A.ns = S.back.map.ns;
+                A.scale = scale;
+                A.g = c->f[c->fcur].as<float>();
+                A.g_next = c->f[c->fcur ^ 1].as<float>();
+                A.gs_next = gs_next;
+                A.v_old = c->v[c->vcur].as<float>();
+                A.a_old = c->a[c->vcur].as<float>();
+                A.v_new = c->v[c->vcur ^ 1].as<float>();
+                A.a_new = c->a[c->vcur ^ 1].as<float>();
+                A.sens = S.sens.as<float>();
+                A.H = S.H.as<float>();
+                A.htab = S.htab.as<float>();
+                A.grid = S.grid;
+                A.wts = w;
+                A.lam = lam;
+                A.thr = static_cast<float>(c->beta / c->rho);
+                A.tw = S.fused_tw;
+                A.th = S.fused_th;
+                A.tiles_x = (S.nx + S.fused_tw - 1) / S.fused_tw;
+                A.seg_log2 = seg_log2_of(S.Q);
+                HIP_TRY(sgtv::launch_update_fused(A, c->grouping, S.fused_threads, c->stream));
+                c->fcur ^= 1;
+                c->vcur ^= 1;
+                c->k += 1;
+                return SGTV_OK;
+            }
             {
                 TimedLaunch t(c, 4);
                 HIP_TRY(sgtv::launch_voxel_update(S.bpart.as<float>(), S.back.map.ns, scale,
                                                   c->f[c->fcur].as<float>(), c->f[c->fcur ^ 1].as<float>(),
                                                   gs_next, c->v[c->vcur].as<float>(), c->a[c->vcur].as<float>(),
-                                                  S.sens.as<float>(), S.H.as<float>(), S.grid, w,
-                                                  c->grouping, lam, c->stream));
+                                                  S.sens.as<float>(), S.H.as<float>(), S.htab.as<float>(), S.grid,
+                                                  w, c->grouping, lam, c->stream));
             }
         } else {
             {
@@ -1421,6 +1525,22 @@ int sgtv_prepare(sgtv_ctx ctx, int n_iters) {
     DeviceGuard g(ctx->device);
     Context::Graph gr{};
     return context_graph(ctx, n_iters, &gr);
+}
+
+int sgtv_set_fused_update(sgtv_ctx ctx, int enable) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    DeviceGuard g(ctx->device);
+    drop_graphs(ctx);
+    ctx->fused = enable != 0;
+    return SGTV_OK;
+}
+
+int sgtv_get_fused_update(sgtv_ctx ctx, int *active, int32_t *tile_x, int32_t *tile_y) {
+    if (!ctx || !active) return fail(SGTV_EINVAL, "null argument");
+    *active = ctx->sys ? (fused_ok(ctx) ? 1 : 0) : (ctx->fused ? 1 : 0);
+    if (tile_x) *tile_x = ctx->sys ? ctx->sys->fused_tw : 0;
+    if (tile_y) *tile_y = ctx->sys ? ctx->sys->fused_th : 0;
+    return SGTV_OK;
 }
 
 int sgtv_set_graphs(sgtv_ctx ctx, int enable) {

@@ -133,15 +133,15 @@ __device__ __forceinline__ float voxel_root(float H, float B, float C) {
 // the grid reads the voxel's own bin and its terms are then discarded, so the
 // loads need no branches.  e = (A^T ratio)_j comes from the callable E, called
 // after the stencil loads are issued so that its own loads overlap them.
-template <int GROUPING, bool WFULL, class E>
-__device__ __forceinline__ float voxel_update_value(int64_t j, E e_of, const float *__restrict__ g,
-                                                    const float *__restrict__ v,
-                                                    const float *__restrict__ a,
-                                                    const float *__restrict__ sens,
-                                                    const float *__restrict__ H, const Grid &grid,
-                                                    const Weights &wts, float lam) {
+// The same at a known position, with the curvature H0_j from the callable HF
+// (the array H or the table of the neighbour pattern), read where H[j] is.
+template <int GROUPING, bool WFULL, class E, class HF>
+__device__ __forceinline__ float voxel_update_at(int64_t j, const VoxelPos &P, E e_of, const float *__restrict__ g,
+                                                 const float *__restrict__ v,
+                                                 const float *__restrict__ a,
+                                                 const float *__restrict__ sens, HF h_of,
+                                                 const Grid &grid, const Weights &wts, float lam) {
     const int Q = grid.Q;
-    const VoxelPos P = voxel_pos(j, grid);
     const int64_t s = P.s;
     const int q = P.q;
     const float gs = g[j];
@@ -166,10 +166,28 @@ __device__ __forceinline__ float voxel_update_value(int64_t j, E e_of, const flo
         const float dtn = fmaf(-wn, fmaf(wn, gn - gs, vn - 2.0f * dn), dt);
         dt = in ? dtn : dt;
     }
-    const float h = lam * H[j];
+    const float h = lam * h_of();
     const float B = sens[j] + lam * dt - h * gs;
     const float C = gs * e_of();
     return voxel_root(h, B, C);
+}
+
+template <int GROUPING, bool WFULL, class E>
+__device__ __forceinline__ float voxel_update_value(int64_t j, E e_of, const float *__restrict__ g,
+                                                    const float *__restrict__ v,
+                                                    const float *__restrict__ a,
+                                                    const float *__restrict__ sens,
+                                                    const float *__restrict__ H, const Grid &grid,
+                                                    const Weights &wts, float lam) {
+    const VoxelPos P = voxel_pos(j, grid);
+    return voxel_update_at<GROUPING, WFULL>(j, P, e_of, g, v, a, sens, [&]() { return H[j]; }, grid, wts, lam);
+}
+
+// Neighbour pattern of a spatial bin: bit p set when the neighbour in
+// direction p (+x, -x, +y, -y) lies inside the grid.  The curvature H0 of a
+// voxel depends only on it when the weights are constant per direction.
+__device__ __forceinline__ int neighbour_mask(const Grid &g, int iy, int ix) {
+    return (ix + 1 < g.nx ? 1 : 0) | (ix > 0 ? 2 : 0) | (iy + 1 < g.ny ? 4 : 0) | (iy > 0 ? 8 : 0);
 }
 
 __device__ __forceinline__ float shrink_factor(float nrm, float thr) {

@@ -121,6 +121,30 @@ constexpr int kPhaseSlots = 5;
 constexpr int kBarGlobal = 0, kBarErr = 1, kBarGroup = 16, kBarQueueF = 160, kBarQueueB = 288;
 constexpr int kBarWords = 416;
 
+// Image update and split/dual update in one pass over tiles of tw x th
+// spatial bins (sgtv_update.hip).
+constexpr int kFusedMaxLds = 65536;        // LDS of one workgroup's image tile and ring
+struct FusedUpdate {
+    const float *part;        // back-product partial sums, ns slabs of J
+    int ns;
+    const float *scale;       // per-column scale of 16-bit values (nullptr: FP32)
+    const float *g;           // image f^k
+    float *g_next, *gs_next;  // new image; its scaled copy for 16-bit values (or nullptr)
+    const float *v_old, *a_old;
+    float *v_new, *a_new;
+    const float *sens;
+    const float *H;           // curvature array (full weights) ...
+    const float *htab;        // ... or 16 values by neighbour pattern (device memory)
+    Grid grid;
+    Weights wts;
+    float lam, thr;
+    int tw, th, tiles_x, seg_log2;
+};
+constexpr int kFusedThreads = 1024;        // default workgroup size
+size_t fused_lds_bytes(int tw, int th, int Q);
+// threads per workgroup: 256, 512 or 1024
+hipError_t launch_update_fused(const FusedUpdate &A, int grouping, int threads, hipStream_t st);
+
 // Launchers (all asynchronous on `st`).
 // Workgroups of the persistent launch (all resident at once); *what names the
 // call that failed.
@@ -144,7 +168,7 @@ hipError_t launch_back_combine(const float *part, int ns, int64_t n, const float
                                float *e, hipStream_t st);
 hipError_t launch_voxel_update(const float *part, int ns, const float *scale, const float *g,
                                float *g_next, float *gs_next, const float *v, const float *a,
-                               const float *sens, const float *H, const Grid &grid,
+                               const float *sens, const float *H, const float *htab, const Grid &grid,
                                const Weights &w, int grouping, float lam, hipStream_t st);
 hipError_t launch_forward_ratio(const Sell &A, int vt, const float *x, const float *y,
                                 const float *r, float *ratio, double *partials, bool objective,

@@ -474,12 +474,15 @@ __global__ __launch_bounds__(kBlock) void k_back_combine(const float *__restrict
     }
 }
 
+// H0 comes from the array H (full weights) or, for weights constant per
+// direction, from the 16-entry table htab by neighbour pattern (the same
+// values; the J-float array is not read).
 template <int GROUPING, bool WFULL>
 __global__ __launch_bounds__(kBlock) void k_voxel_update(
     const float *__restrict__ part, int ns, const float *__restrict__ scale,
     const float *__restrict__ g, float *__restrict__ g_next, float *__restrict__ gs_next,
     const float *__restrict__ v, const float *__restrict__ a, const float *__restrict__ sens,
-    const float *__restrict__ H, Grid grid, Weights wts, float lam) {
+    const float *__restrict__ H, const float *__restrict__ htab, Grid grid, Weights wts, float lam) {
     const int64_t n = grid.J;
     for (int64_t j = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x; j < n;
          j += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -488,7 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_voxel_update(
             for (int k = 1; k < ns; ++k) e += part[static_cast<int64_t>(k) * n + j];
             return scale ? e * scale[j] : e;
         };
-        const float gnew = voxel_update_value<GROUPING, WFULL>(j, e_of, g, v, a, sens, H, grid, wts, lam);
+        const VoxelPos P = voxel_pos(j, grid);
+        auto h_of = [&]() { return WFULL ? H[j] : htab[neighbour_mask(grid, P.iy, P.ix)]; };
+        const float gnew = voxel_update_at<GROUPING, WFULL>(j, P, e_of, g, v, a, sens, h_of, grid, wts, lam);
         g_next[j] = gnew;
         if (gs_next) gs_next[j] = gnew * scale[j];
     }
@@ -631,13 +636,13 @@ hipError_t launch_back_combine(const float *part, int ns, int64_t n, const float
 
 hipError_t launch_voxel_update(const float *part, int ns, const float *scale, const float *g,
                                float *g_next, float *gs_next, const float *v, const float *a,
-                               const float *sens, const float *H, const Grid &grid,
+                               const float *sens, const float *H, const float *htab, const Grid &grid,
                                const Weights &w, int grouping, float lam, hipStream_t st) {
     const unsigned nb = stride_blocks(grid.J);
     auto kern = grouping == 0 ? (w.full ? k_voxel_update<0, true> : k_voxel_update<0, false>)
                               : (w.full ? k_voxel_update<1, true> : k_voxel_update<1, false>);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, part, ns, scale, g, g_next, gs_next, v,
-                       a, sens, H, grid, w, lam);
+                       a, sens, H, htab, grid, w, lam);
     return hipGetLastError();
 }
 

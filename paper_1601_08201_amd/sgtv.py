@@ -101,6 +101,8 @@ def lib():
             "sgtv_set_state": (_I, [_P, _P, _P, _P, _I64, _I]),
             "sgtv_backprojection": (_I, [_P, _P, _I]),
             "sgtv_backprojection_noalloc": (_I, [_P, _P, _I]),
+            "sgtv_set_fused_update": (_I, [_P, _I]),
+            "sgtv_get_fused_update": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
             "sgtv_set_profiling": (_I, [_P, _I]),
             "sgtv_set_graphs": (_I, [_P, _I]),
             "sgtv_batch_create": (_I, [ctypes.POINTER(_P), _I, _P]),
@@ -338,6 +340,17 @@ def sgtv_backprojection_noalloc(ctx, out=None):
     return out
 
 
+def sgtv_set_fused_update(ctx, enable=True):
+    _check(lib().sgtv_set_fused_update(ctx, 1 if enable else 0))
+
+
+def sgtv_get_fused_update(ctx):
+    """(in use, tile bins in x, tile bins in y)"""
+    a, tx, ty = _I(), _I32(), _I32()
+    _check(lib().sgtv_get_fused_update(ctx, ctypes.byref(a), ctypes.byref(tx), ctypes.byref(ty)))
+    return bool(a.value), tx.value, ty.value
+
+
 def sgtv_set_schedule(ctx, **fields):
     """Schedule for the next set_system; unnamed fields are automatic (0)."""
     sch = Schedule(**{k: int(v) for k, v in fields.items()})
@@ -463,6 +476,13 @@ class Reconstructor:
     def set_schedule(self, **fields):
         sgtv_set_schedule(self._ctx, **fields)
         return self
+
+    def set_fused_update(self, enable=True):
+        sgtv_set_fused_update(self._ctx, enable)
+        return self
+
+    def fused_update(self):
+        return sgtv_get_fused_update(self._ctx)
 
     def schedule(self):
         return sgtv_get_schedule(self._ctx)

@@ -391,3 +391,50 @@ def test_tiles_with_and_without_row_balancing(sg):
     sched = dict(format=0, waves=16, fwd_rows_per_wave=64, fwd_block_cols=12, fwd_slabs=1,
                  back_rows_per_wave=64, back_block_cols=12, back_slabs=1)
     check_against_oracle(sg, prob, 20, schedule=sched)
+
+
+FUSED_CASES = {
+    "small": dict(cfg="small", seed=1),
+    "teflon weights": dict(cfg="teflon", seed=1, w="dir"),
+    "teflon standard TV": dict(cfg="teflon", seed=2, w="dir", grouping=1),
+    "full weights": dict(cfg=dict(ny=9, nx=13, Q=24, I=1500, nnz_per_col=8, rects=3), seed=4, w="full"),
+    "Q=1": dict(cfg=dict(ny=40, nx=23, Q=1, I=700, nnz_per_col=6, rects=3), seed=5),
+    "Q=129": dict(cfg=dict(ny=6, nx=11, Q=129, I=4000, nnz_per_col=8, rects=2), seed=6),
+    "one row": dict(cfg=dict(ny=1, nx=37, Q=16, I=300, nnz_per_col=6, rects=1), seed=7),
+    "3 sweeps": dict(cfg="small", seed=8, sweeps=3),
+    "bf16 values": dict(cfg="small", seed=9, storage="bf16"),
+}
+
+
+@pytest.mark.parametrize("name", list(FUSED_CASES))
+def test_fused_update_equals_two_launches(sg, name):
+    """The image and split update in one pass give the images, splits and
+    reports of the two separate launches bit for bit (tile edges, partial
+    tiles, grid borders, weights, both groupings, several sweeps, 16-bit
+    values), and the fused pass is the one in use."""
+    c = FUSED_CASES[name]
+    prob = datagen.make_problem(c["cfg"], c["seed"])
+    w = None
+    if c.get("w") == "dir":
+        w = prob.meta["weights"]
+    elif c.get("w") == "full":
+        w = np.random.default_rng(3).uniform(0.5, 2.0, 4 * prob.J).astype(np.float32)
+    out = []
+    for fused in (True, False):
+        R = sg.Reconstructor()
+        R.set_fused_update(fused)
+        R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val,
+                     storage=c.get("storage", "f32"), w=w)
+        if c.get("grouping"):
+            R.set_grouping(c["grouping"])
+        R.set_data(prob.y, prob.r, prob.beta, prob.rho, c.get("sweeps", 1))
+        active, tx, ty = R.fused_update()
+        print(name, "fused" if fused else "two launches", "active", active, "tile", tx, ty, flush=True)
+        assert active == fused and tx > 0 and ty > 0
+        R.iterate(17)
+        R.iterate(4)
+        out.append((R.image(), *R.split(), R.objective()))
+        R.close()
+    for a, b in zip(out[0][:3], out[1][:3]):
+        np.testing.assert_array_equal(a, b)
+    assert out[0][3] == out[1][3]
