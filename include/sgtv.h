@@ -232,14 +232,38 @@ int sgtv_iterate_adaptive(sgtv_ctx ctx, int64_t max_iters, const sgtv_adaptive *
                           sgtv_check *checks, int32_t max_checks, int32_t *n_checks,
                           int64_t *iters_done, int *converged);
 
-/* Device memory: sgtv_workspace_bytes estimates (within about 25 % for
- * random matrices of evenly spread entries; -1 for invalid arguments) what one context
- * allocates for a system of I measurements, J hyper-voxels and nnz entries
- * with the automatic schedule (both tiled copies of A, state, data, partial
- * sums); sgtv_device_bytes reports what the context holds now.  The library
- * allocates this memory itself at sgtv_set_system / sgtv_set_data. */
+/* Device memory.  With sgtv_set_system the library allocates the context's
+ * memory itself (at set_system and set_data).  sgtv_workspace_bytes estimates
+ * that amount beforehand (within about 25 % for random matrices of evenly
+ * spread entries; -1 for invalid arguments) for a system of I measurements,
+ * J hyper-voxels and nnz entries with the automatic schedule;
+ * sgtv_device_bytes reports what the library has allocated for the context
+ * now (memory in a caller's workspace is not counted). */
 int64_t sgtv_workspace_bytes(int64_t I, int64_t J, int64_t nnz, int storage_dtype);
 int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes);
+
+/*
+ * Caller-owned device memory, in two phases.  sgtv_plan_system takes the
+ * arguments of sgtv_set_system, checks and packs the system on the host
+ * (nothing on the device yet), keeps it in the context and returns in *bytes
+ * the exact size of device memory the context will use for this system, its
+ * data, its iteration state (either grouping) and the temporaries of single
+ * calls.  sgtv_commit_system then puts the planned system into `workspace`,
+ * a device buffer of the context's GPU that the caller allocated (a torch
+ * tensor, say) of at least that many bytes, aligned to 256 bytes; it replaces
+ * the context's system and data like sgtv_set_system.  From then on no call
+ * on the context allocates device memory: set_data, set_grouping, set_init,
+ * set_init_dual, set_state, get_split, backprojection and iterate use the
+ * workspace only.  The library never frees it; the caller keeps it alive
+ * and unchanged until sgtv_destroy or the next set_system / commit_system
+ * (sgtv_set_system returns the context to library-allocated memory).
+ * Errors: commit without a plan SGTV_ESTATE, a smaller or misaligned
+ * workspace SGTV_ENOMEM / SGTV_EINVAL (context unchanged).
+ */
+int sgtv_plan_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q, const int64_t *row_ptr,
+                     const int32_t *col_idx, const float *val, int64_t nnz, int storage_dtype, const float *w,
+                     int64_t w_len, int mem_kind, int64_t *bytes);
+int sgtv_commit_system(sgtv_ctx ctx, void *workspace, int64_t bytes);
 
 /* Normalised backprojection x_in = (A^T y) / (A^T 1) (0 where A^T 1 = 0),
  * J floats, of the data currently set. */

@@ -73,26 +73,71 @@ int hip_fail(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(e_, #expr);                                          \
     } while (0)
 
-// Owning device allocation.
+// A range of caller-owned device memory handed out in 256-byte aligned
+// pieces (bump allocation; `used` is reset when the section is filled anew).
+// A counting arena hands out no memory: it only adds up what would be taken.
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool count = false;
+};
+
+// While set (ArenaScope), DBuf::alloc takes its memory from this arena
+// instead of hipMalloc.
+thread_local Arena *t_arena = nullptr;
+
+struct ArenaScope {
+    Arena *prev;
+    ArenaScope(Arena *a, bool reset) : prev(t_arena) {
+        if (a && reset) a->used = 0;
+        t_arena = a;
+    }
+    ~ArenaScope() { t_arena = prev; }
+};
+
+bool counting() { return t_arena && t_arena->count; }
+
+// Device allocation: owned (hipMalloc / hipFree) or borrowed from an arena.
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed) {
+        o.p = nullptr; o.bytes = 0; o.borrowed = false;
+    }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; bytes = o.bytes; borrowed = o.borrowed;
+            o.p = nullptr; o.bytes = 0; o.borrowed = false;
+        }
         return *this;
     }
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     hipError_t alloc(size_t n) {
         release();
+        if (Arena *a = t_arena) {
+            const size_t off = align_up(a->used), need = n ? n : 16;
+            if (!a->count && off + need > a->cap) return hipErrorOutOfMemory;
+            a->used = off + need;
+            // a counting arena gives a non-null placeholder that is never dereferenced
+            p = a->count ? reinterpret_cast<void *>(kAlign) : a->base + off;
+            bytes = n;
+            borrowed = true;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&p, n ? n : 16);
         if (e == hipSuccess) bytes = n;
         else p = nullptr;
@@ -129,7 +174,7 @@ template <class T>
 hipError_t upload(DBuf &dst, const std::vector<T> &src) {
     hipError_t e = dst.alloc(sizeof(T) * src.size());
     if (e != hipSuccess) return e;
-    if (src.empty()) return hipSuccess;
+    if (src.empty() || counting()) return hipSuccess;
     return hipMemcpy(dst.p, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
 }
 
@@ -656,25 +701,39 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     return SGTV_OK;
 }
 
-template <class V>
-int upload_tiled(Tiled &T, int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
-                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
-                 bool idx24) {
+// Host image of one tiled copy (what the device buffers will hold).
+struct PackedTiled {
     std::vector<int32_t> pk, goff, poff;
+    std::vector<float> v32;          // FP32 values ...
+    std::vector<uint16_t> v16;       // ... or 16-bit codes
     std::vector<uint16_t> slot;
+    sgtv::TileMap map{};
+};
+
+template <class V>
+int pack_tiled(PackedTiled &T, int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
+               const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t, bool idx24) {
     std::vector<V> pv;
-    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, idx24, pk, pv, goff, poff, slot, T.map))
+    if (int e = build_tiled(n_rows, n_cols, rp, ci, vals, t, idx24, T.pk, pv, T.goff, T.poff, T.slot, T.map))
         return e;
-    HIP_TRY(upload(T.pk, pk));
-    HIP_TRY(upload(T.val, pv));
-    HIP_TRY(upload(T.goff, goff));
-    if (!poff.empty()) HIP_TRY(upload(T.poff, poff));
-    if (!slot.empty()) HIP_TRY(upload(T.slot, slot));
+    if constexpr (sizeof(V) == 4) T.v32.swap(pv);
+    else T.v16.swap(pv);
+    return SGTV_OK;
+}
+
+int upload_tiled(Tiled &T, const PackedTiled &P) {
+    T.map = P.map;
+    HIP_TRY(upload(T.pk, P.pk));
+    if (!P.v32.empty() || P.v16.empty()) HIP_TRY(upload(T.val, P.v32));
+    else HIP_TRY(upload(T.val, P.v16));
+    HIP_TRY(upload(T.goff, P.goff));
+    if (!P.poff.empty()) HIP_TRY(upload(T.poff, P.poff));
+    if (!P.slot.empty()) HIP_TRY(upload(T.slot, P.slot));
     T.map.pk = T.pk.as<int32_t>();
     T.map.val = T.val.p;
     T.map.goff = T.goff.as<int32_t>();
-    T.map.poff = poff.empty() ? nullptr : T.poff.as<int32_t>();
-    T.map.slot = slot.empty() ? nullptr : T.slot.as<uint16_t>();
+    T.map.poff = P.poff.empty() ? nullptr : T.poff.as<int32_t>();
+    T.map.slot = P.slot.empty() ? nullptr : T.slot.as<uint16_t>();
     return SGTV_OK;
 }
 
@@ -710,6 +769,29 @@ struct System {
     }
 };
 
+// A system packed on the host, not yet on the device: the metadata in S (no
+// device buffers) and the host arrays of every buffer.
+struct Packed {
+    std::unique_ptr<System> S;
+    std::vector<float> colscale, H, htab, wf;
+    PackedTiled fwd, back;
+    size_t fpart_floats = 0, bpart_floats = 0;
+    std::vector<int64_t> rsp, csp;
+    std::vector<int32_t> rsi, csi;
+    std::vector<float> rsv32, csv32;
+    std::vector<uint16_t> rsv16, csv16;
+};
+
+// Caller-owned device memory of a context, cut into sections that are filled
+// independently: the system (matrix copies, H, partial sums, reductions),
+// the data (y, r, ratio), the iteration state and the temporaries of single
+// calls.
+struct Workspace {
+    char *base = nullptr;
+    size_t size = 0;
+    Arena sys, data, state, temp;
+};
+
 }  // namespace
 
 struct sgtv_ctx_s;
@@ -733,6 +815,12 @@ struct sgtv_ctx_s {
     // reductions
     DBuf part, red;
     int64_t part_cap = 0;
+    // caller-owned device memory (base null: the library allocates) and a
+    // system packed by sgtv_plan_system, waiting for sgtv_commit_system
+    Workspace ws;
+    std::unique_ptr<Packed> pending;
+    int64_t pending_bytes = 0;
+    size_t pending_sections[4] = {0, 0, 0, 0};
     // image and split updates in one pass (off by default: slower here, see
     // sgtv_set_fused_update)
     bool fused = false;
@@ -879,10 +967,12 @@ void choose_fused_tile(int ny, int nx, int Q, int *tw, int *th) {
     *th = best_h;
 }
 
-int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t ny, int32_t nx,
-                 int32_t Q, const int64_t *row_ptr, const int32_t *col_idx, const float *val,
-                 int64_t nnz, int vt, const float *w, int64_t w_len, int mk) {
-    auto S = std::make_unique<System>();
+// Validate the system and pack it on the host (no device memory touched).
+int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, int32_t Q,
+                const int64_t *row_ptr, const int32_t *col_idx, const float *val, int64_t nnz, int vt,
+                const float *w, int64_t w_len, int mk) {
+    PK.S = std::make_unique<System>();
+    System *S = PK.S.get();
     S->I = I; S->ny = ny; S->nx = nx; S->Q = Q; S->vt = vt; S->nnz = nnz;
     S->S = static_cast<int64_t>(ny) * nx;
     S->J = S->S * Q;
@@ -968,7 +1058,7 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         }
         for (int64_t j = 0; j < J; ++j)
             if (sigma[j] == 0.0f) sigma[j] = 1.0f;   // empty / all-zero column: any scale
-        HIP_TRY(upload(S->colscale, sigma));
+        PK.colscale = std::move(sigma);
     }
 
     S->format = c->want.format;
@@ -1001,20 +1091,22 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         // the simple loop (variant 1) reads 24-bit indices where the tile fits them
         const bool i24 = S->sched.variant == 1;
         if (vt == SGTV_F32) {
-            if (int e = upload_tiled(S->fwd, I, J, rp, ci, av, tf, i24)) return e;
+            if (int e = pack_tiled(PK.fwd, I, J, rp, ci, av, tf, i24)) return e;
             std::vector<float> cv(static_cast<size_t>(nnz));
             for (int64_t k = 0; k < nnz; ++k) cv[k] = av[csrc[k]];
-            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb, i24)) return e;
+            if (int e = pack_tiled(PK.back, J, I, cp, cidx, cv, tb, i24)) return e;
         } else {
-            if (int e = upload_tiled(S->fwd, I, J, rp, ci, codes, tf, i24)) return e;
+            if (int e = pack_tiled(PK.fwd, I, J, rp, ci, codes, tf, i24)) return e;
             std::vector<uint16_t> cv(static_cast<size_t>(nnz));
             for (int64_t k = 0; k < nnz; ++k) cv[k] = codes[csrc[k]];
-            if (int e = upload_tiled(S->back, J, I, cp, cidx, cv, tb, i24)) return e;
+            if (int e = pack_tiled(PK.back, J, I, cp, cidx, cv, tb, i24)) return e;
         }
-        S->fwd.map.variant = S->sched.variant - 1;
-        S->back.map.variant = S->sched.variant - 1;
-        HIP_TRY(S->fpart.alloc(sizeof(float) * I * tf.ns));
-        HIP_TRY(S->bpart.alloc(sizeof(float) * J * tb.ns));
+        PK.fwd.map.variant = S->sched.variant - 1;
+        PK.back.map.variant = S->sched.variant - 1;
+        S->fwd.map = PK.fwd.map;
+        S->back.map = PK.back.map;
+        PK.fpart_floats = static_cast<size_t>(I) * tf.ns;
+        PK.bpart_floats = static_cast<size_t>(J) * tb.ns;
     } else {
         // internal row order: rows sorted by decreasing length (stable), so that
         // the 64 rows of a slice have nearly equal lengths
@@ -1060,56 +1152,88 @@ int build_system(sgtv_ctx_s *c, std::unique_ptr<System> &out, int64_t I, int32_t
         if (vt == SGTV_F32) {
             std::vector<float> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
             for (int64_t k = 0; k < nnz; ++k) { lv[k] = av[lsrc[k]]; cv[k] = av[csrc[k]]; }
-            std::vector<float> rsv, csv;
-            pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
-            pack_sell(J, cp, cidx, cv, csp, csi, csv);
-            HIP_TRY(upload(S->rs_val, rsv));
-            HIP_TRY(upload(S->cs_val, csv));
+            pack_sell(I, lp, lidx, lv, rsp, rsi, PK.rsv32);
+            pack_sell(J, cp, cidx, cv, csp, csi, PK.csv32);
         } else {
             std::vector<uint16_t> lv(static_cast<size_t>(nnz)), cv(static_cast<size_t>(nnz));
             for (int64_t k = 0; k < nnz; ++k) { lv[k] = codes[lsrc[k]]; cv[k] = codes[csrc[k]]; }
-            std::vector<uint16_t> rsv, csv;
-            pack_sell(I, lp, lidx, lv, rsp, rsi, rsv);
-            pack_sell(J, cp, cidx, cv, csp, csi, csv);
-            HIP_TRY(upload(S->rs_val, rsv));
-            HIP_TRY(upload(S->cs_val, csv));
+            pack_sell(I, lp, lidx, lv, rsp, rsi, PK.rsv16);
+            pack_sell(J, cp, cidx, cv, csp, csi, PK.csv16);
         }
         if (rsp.back() >= (int64_t(1) << 31) || csp.back() >= (int64_t(1) << 31))
             return fail(SGTV_ESHAPE, "padded matrix exceeds 2^31 entries");
         S->n_rslices = static_cast<int64_t>(rsp.size()) - 1;
         S->n_cslices = static_cast<int64_t>(csp.size()) - 1;
-        HIP_TRY(upload(S->rs_ptr, rsp));
-        HIP_TRY(upload(S->rs_idx, rsi));
-        HIP_TRY(upload(S->cs_ptr, csp));
-        HIP_TRY(upload(S->cs_idx, csi));
+        PK.rsp.swap(rsp);
+        PK.rsi.swap(rsi);
+        PK.csp.swap(csp);
+        PK.csi.swap(csi);
     }
-    HIP_TRY(upload(S->H, Hf));
-    HIP_TRY(upload(S->htab, htab));
-    if (S->wfull) HIP_TRY(upload(S->wbuf, wf));
+    PK.H.swap(Hf);
+    PK.htab.swap(htab);
+    if (S->wfull) PK.wf.swap(wf);
     choose_fused_tile(ny, nx, Q, &S->fused_tw, &S->fused_th);
     if (const char *e = std::getenv("SGTV_FUSED_THREADS")) {
         const int t = std::atoi(e);
         if (t == 256 || t == 512 || t == 1024) S->fused_threads = t;
     }
-
-    // sensitivity s = A^T 1 with the stored (possibly quantised) values
-    std::vector<float> ones(static_cast<size_t>(I + kVecPad), 1.0f);
-    DBuf d_ones;
-    HIP_TRY(upload(d_ones, ones));
-    HIP_TRY(S->sens.alloc(sizeof(float) * J));
-    if (int e = back_project(*S, d_ones.as<float>(), S->sens.as<float>(), c->stream)) return e;
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    out = std::move(S);
     return SGTV_OK;
 }
 
-int ensure_partials(sgtv_ctx_s *c) {
-    const System &S = *c->sys;
+// Put a packed system on the device: every buffer is allocated (from the
+// current arena, if any; a counting arena only adds up the bytes) and
+// filled, and the sensitivity s = A^T 1 is computed with the stored values
+// (its vector of ones is a temporary from `temp`, or library memory when
+// temp is null).  Leaves the host arrays in PK.
+int upload_system(sgtv_ctx_s *c, Packed &PK, Arena *temp) {
+    System &S = *PK.S;
+    if (S.vt != SGTV_F32) HIP_TRY(upload(S.colscale, PK.colscale));
+    if (S.format == SGTV_FORMAT_TILED) {
+        if (int e = upload_tiled(S.fwd, PK.fwd)) return e;
+        if (int e = upload_tiled(S.back, PK.back)) return e;
+        HIP_TRY(S.fpart.alloc(sizeof(float) * PK.fpart_floats));
+        HIP_TRY(S.bpart.alloc(sizeof(float) * PK.bpart_floats));
+    } else {
+        if (S.vt == SGTV_F32) {
+            HIP_TRY(upload(S.rs_val, PK.rsv32));
+            HIP_TRY(upload(S.cs_val, PK.csv32));
+        } else {
+            HIP_TRY(upload(S.rs_val, PK.rsv16));
+            HIP_TRY(upload(S.cs_val, PK.csv16));
+        }
+        HIP_TRY(upload(S.rs_ptr, PK.rsp));
+        HIP_TRY(upload(S.rs_idx, PK.rsi));
+        HIP_TRY(upload(S.cs_ptr, PK.csp));
+        HIP_TRY(upload(S.cs_idx, PK.csi));
+    }
+    HIP_TRY(upload(S.H, PK.H));
+    HIP_TRY(upload(S.htab, PK.htab));
+    if (S.wfull) HIP_TRY(upload(S.wbuf, PK.wf));
+    HIP_TRY(S.sens.alloc(sizeof(float) * S.J));
+    if (counting()) return SGTV_OK;
+    // sensitivity s = A^T 1 with the stored (possibly quantised) values
+    std::vector<float> ones(static_cast<size_t>(S.I + kVecPad), 1.0f);
+    DBuf d_ones;
+    {
+        ArenaScope ts(temp, true);
+        HIP_TRY(upload(d_ones, ones));
+    }
+    if (int e = back_project(S, d_ones.as<float>(), S.sens.as<float>(), c->stream)) return e;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SGTV_OK;
+}
+
+// FP64 partial sums the reductions of a system need.
+int64_t partials_needed(const System &S) {
     const int64_t n1 = (S.n_rslices + 3) / 4;
     int sl = 0;
     while ((1 << sl) < S.Q && sl < 6) ++sl;
     const int64_t n2 = (S.S + (256 >> sl) - 1) / (256 >> sl);
-    const int64_t need = std::max<int64_t>({n1, 6 * n2, 4096, 16});
+    return std::max<int64_t>({n1, 6 * n2, 4096, 16});
+}
+
+int ensure_partials(sgtv_ctx_s *c) {
+    const int64_t need = partials_needed(*c->sys);
     if (need > c->part_cap) {
         HIP_TRY(c->part.alloc(sizeof(double) * need));
         c->part_cap = need;
@@ -1236,6 +1360,41 @@ int step(sgtv_ctx_s *c) {
     return SGTV_OK;
 }
 
+// Argument checks of sgtv_set_system / sgtv_plan_system that need no data.
+int check_system_args(int64_t I, int32_t ny, int32_t nx, int32_t Q, const int64_t *row_ptr, const int32_t *col_idx,
+                      const float *val, int64_t nnz, int storage_dtype, const float *w, int64_t w_len,
+                      int mem_kind) {
+    if (int e = check_mem_kind(mem_kind)) return e;
+    if (I < 1 || ny < 1 || nx < 1 || Q < 1) return fail(SGTV_ESHAPE, "I, ny, nx and Q must be >= 1");
+    if (nnz < 0 || nnz >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "nnz must be in [0, 2^31)");
+    const int64_t J = static_cast<int64_t>(ny) * nx * Q;
+    if (J >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "J = ny*nx*Q must be below 2^31");
+    if (I >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "I must be below 2^31");
+    if (storage_dtype != SGTV_F32 && storage_dtype != SGTV_BF16 && storage_dtype != SGTV_F16)
+        return fail(SGTV_EINVAL, "unknown storage dtype");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !val))) return fail(SGTV_EINVAL, "NULL matrix array");
+    if (w && w_len != 4 && w_len != 4 * J) return fail(SGTV_ESHAPE, "w_len must be 4 or 4*J");
+    if (!w && w_len != 0) return fail(SGTV_ESHAPE, "w is NULL but w_len is not 0");
+    return SGTV_OK;
+}
+
+// Replace the context's system (may be null) and drop its data and state.
+void install_system(sgtv_ctx_s *ctx, std::unique_ptr<System> S) {
+    drop_graphs(ctx);
+    ctx->sys = std::move(S);
+    ctx->has_data = false;
+    ctx->y.release(); ctx->r.release(); ctx->ratio.release();
+    for (int b = 0; b < 2; ++b) { ctx->f[b].release(); ctx->v[b].release(); ctx->a[b].release(); }
+    ctx->fs.release();
+    ctx->part_cap = 0;
+    ctx->part.release();
+    ctx->red.release();
+}
+
+// The sections of the context's workspace, or null when the library
+// allocates the context's memory itself.
+Arena *ws_section(sgtv_ctx_s *c, Arena Workspace::*sec) { return c->ws.base ? &(c->ws.*sec) : nullptr; }
+
 }  // namespace
 
 extern "C" {
@@ -1285,35 +1444,128 @@ int sgtv_set_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q,
                     const int64_t *row_ptr, const int32_t *col_idx, const float *val,
                     int64_t nnz, int storage_dtype, const float *w, int64_t w_len, int mem_kind) {
     if (!ctx) return fail(SGTV_EINVAL, "null context");
-    if (int e = check_mem_kind(mem_kind)) return e;
-    if (I < 1 || ny < 1 || nx < 1 || Q < 1) return fail(SGTV_ESHAPE, "I, ny, nx and Q must be >= 1");
-    if (nnz < 0 || nnz >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "nnz must be in [0, 2^31)");
-    const int64_t J = static_cast<int64_t>(ny) * nx * Q;
-    if (J >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "J = ny*nx*Q must be below 2^31");
-    if (I >= (int64_t(1) << 31)) return fail(SGTV_ESHAPE, "I must be below 2^31");
-    if (storage_dtype != SGTV_F32 && storage_dtype != SGTV_BF16 && storage_dtype != SGTV_F16)
-        return fail(SGTV_EINVAL, "unknown storage dtype");
-    if (!row_ptr || (nnz > 0 && (!col_idx || !val))) return fail(SGTV_EINVAL, "NULL matrix array");
-    if (w && w_len != 4 && w_len != 4 * J) return fail(SGTV_ESHAPE, "w_len must be 4 or 4*J");
-    if (!w && w_len != 0) return fail(SGTV_ESHAPE, "w is NULL but w_len is not 0");
+    if (int e = check_system_args(I, ny, nx, Q, row_ptr, col_idx, val, nnz, storage_dtype, w, w_len, mem_kind))
+        return e;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     try {
-        std::unique_ptr<System> S;
-        if (int e = build_system(ctx, S, I, ny, nx, Q, row_ptr, col_idx, val, nnz, storage_dtype, w,
-                                 w_len, mem_kind))
+        Packed PK;
+        if (int e = pack_system(ctx, PK, I, ny, nx, Q, row_ptr, col_idx, val, nnz, storage_dtype, w, w_len,
+                                mem_kind))
             return e;
-        // commit
-        drop_graphs(ctx);
-        ctx->sys = std::move(S);
-        ctx->has_data = false;
-        ctx->y.release(); ctx->r.release(); ctx->ratio.release();
-        for (int b = 0; b < 2; ++b) { ctx->f[b].release(); ctx->v[b].release(); ctx->a[b].release(); }
-        ctx->fs.release();
-        ctx->part_cap = 0;
-        ctx->part.release();
+        if (int e = upload_system(ctx, PK, nullptr)) return e;
+        // commit: from now on the library allocates the context's memory itself
+        install_system(ctx, std::move(PK.S));
+        ctx->ws = Workspace{};
+        ctx->pending.reset();
         if (int e = ensure_partials(ctx)) return e;
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+namespace {
+
+// Bytes of the sections of a workspace: data, state and temporaries (the
+// system section is counted by a dry upload).
+size_t data_section_bytes(const System &S) {
+    return align_up(sizeof(float) * (S.I + kVecPad)) + align_up(sizeof(float) * S.I) +
+           align_up(sizeof(float) * (S.I + kVecPad));
+}
+
+size_t state_section_bytes(const System &S) {
+    // f and v double buffered, a sized for either grouping (at most J), the scaled copy
+    return 2 * align_up(sizeof(float) * (S.J + kVecPad)) + 2 * align_up(sizeof(float) * S.J * 4) +
+           2 * align_up(sizeof(float) * S.J) + align_up(sizeof(float) * (S.J + kVecPad));
+}
+
+size_t temp_section_bytes(const System &S) {
+    const size_t j4 = align_up(sizeof(float) * S.J), v4 = align_up(sizeof(float) * S.J * 4);
+    return std::max({align_up(sizeof(float) * (S.I + kVecPad)),   // ones of the sensitivity
+                     2 * v4,                                       // d and c of get_split
+                     j4 + v4 + j4,                                 // f, v, a of set_state
+                     2 * j4});                                     // backprojection
+}
+
+}  // namespace
+
+int sgtv_plan_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q, const int64_t *row_ptr,
+                     const int32_t *col_idx, const float *val, int64_t nnz, int storage_dtype, const float *w,
+                     int64_t w_len, int mem_kind, int64_t *bytes) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (!bytes) return fail(SGTV_EINVAL, "bytes is NULL");
+    if (int e = check_system_args(I, ny, nx, Q, row_ptr, col_idx, val, nnz, storage_dtype, w, w_len, mem_kind))
+        return e;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    try {
+        auto PK = std::make_unique<Packed>();
+        if (int e = pack_system(ctx, *PK, I, ny, nx, Q, row_ptr, col_idx, val, nnz, storage_dtype, w, w_len,
+                                mem_kind))
+            return e;
+        // the system section: the same allocations as the upload, counted
+        Arena cnt;
+        cnt.count = true;
+        {
+            ArenaScope sc(&cnt, true);
+            if (int e = upload_system(ctx, *PK, nullptr)) return e;
+            DBuf part, red;
+            HIP_TRY(part.alloc(sizeof(double) * partials_needed(*PK->S)));
+            HIP_TRY(red.alloc(sizeof(double) * 16));
+        }
+        const System &S = *PK->S;
+        const size_t sec[4] = {align_up(cnt.used), data_section_bytes(S), state_section_bytes(S),
+                               temp_section_bytes(S)};
+        ctx->pending = std::move(PK);
+        for (int k = 0; k < 4; ++k) ctx->pending_sections[k] = sec[k];
+        ctx->pending_bytes = static_cast<int64_t>(sec[0] + sec[1] + sec[2] + sec[3]);
+        *bytes = ctx->pending_bytes;
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+int sgtv_commit_system(sgtv_ctx ctx, void *workspace, int64_t bytes) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    if (!ctx->pending) return fail(SGTV_ESTATE, "no planned system (call sgtv_plan_system first)");
+    if (!workspace) return fail(SGTV_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(SGTV_EINVAL, "workspace must be aligned to 256 bytes");
+    if (bytes < ctx->pending_bytes)
+        return fail(SGTV_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes; the planned system needs " +
+                                     std::to_string(ctx->pending_bytes));
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    try {
+        Workspace ws;
+        ws.base = static_cast<char *>(workspace);
+        ws.size = static_cast<size_t>(bytes);
+        Arena *sec[4] = {&ws.sys, &ws.data, &ws.state, &ws.temp};
+        size_t off = 0;
+        for (int k = 0; k < 4; ++k) {
+            sec[k]->base = ws.base + off;
+            sec[k]->cap = ctx->pending_sections[k];
+            off += ctx->pending_sections[k];
+        }
+        // the old system and state go first (their memory may be reused)
+        drop_graphs(ctx);
+        install_system(ctx, nullptr);
+        ctx->ws = ws;
+        Packed &PK = *ctx->pending;
+        {
+            ArenaScope sc(&ctx->ws.sys, true);
+            if (int e = upload_system(ctx, PK, &ctx->ws.temp)) {
+                ctx->ws = Workspace{};
+                return e;
+            }
+            install_system(ctx, std::move(PK.S));
+            if (int e = ensure_partials(ctx)) return e;
+        }
+        ctx->pending.reset();
     } catch (const std::bad_alloc &) {
         return fail(SGTV_ENOMEM, "host allocation failed");
     }
@@ -1345,9 +1597,14 @@ int sgtv_set_data(sgtv_ctx ctx, const float *y, const float *r, double beta, dou
         std::vector<float> py(static_cast<size_t>(S.I + kVecPad), 0.0f), pr(static_cast<size_t>(S.I), 0.0f);
         for (int64_t i = 0; i < S.I; ++i) { py[i] = hy[S.perm[i]]; pr[i] = hr[S.perm[i]]; }
         DBuf dy, dr, dratio;
-        HIP_TRY(upload(dy, py));
-        HIP_TRY(upload(dr, pr));
-        HIP_TRY(dratio.alloc(sizeof(float) * (S.I + kVecPad)));
+        {
+            // in a workspace the data section is refilled (the old y, r and
+            // ratio are replaced in place; the host checks above have passed)
+            ArenaScope sc(ws_section(ctx, &Workspace::data), true);
+            HIP_TRY(upload(dy, py));
+            HIP_TRY(upload(dr, pr));
+            HIP_TRY(dratio.alloc(sizeof(float) * (S.I + kVecPad)));
+        }
         drop_graphs(ctx);
         ctx->y = std::move(dy);
         ctx->r = std::move(dr);
@@ -1356,6 +1613,7 @@ int sgtv_set_data(sgtv_ctx ctx, const float *y, const float *r, double beta, dou
         ctx->rho = rho;
         ctx->sweeps = sweeps;
         if (!ctx->f[0].p || ctx->a[0].bytes != sizeof(float) * n_groups(ctx)) {
+            ArenaScope sc(ws_section(ctx, &Workspace::state), true);
             if (int e = alloc_state(ctx)) return e;
         }
         ctx->has_data = true;
@@ -1387,10 +1645,16 @@ int sgtv_set_grouping(sgtv_ctx ctx, int grouping) {
     if (ctx->sys && ctx->has_data) {
         // keep f, resize (v, a) storage for the new group count
         DBuf keep_f;
-        HIP_TRY(keep_f.alloc(sizeof(float) * ctx->sys->J));
+        {
+            ArenaScope sc(ws_section(ctx, &Workspace::temp), true);
+            HIP_TRY(keep_f.alloc(sizeof(float) * ctx->sys->J));
+        }
         HIP_TRY(hipMemcpyAsync(keep_f.p, ctx->f[ctx->fcur].p, sizeof(float) * ctx->sys->J,
                                hipMemcpyDeviceToDevice, ctx->stream));
-        if (int e = alloc_state(ctx)) { ctx->grouping = old; return e; }
+        {
+            ArenaScope sc(ws_section(ctx, &Workspace::state), true);
+            if (int e = alloc_state(ctx)) { ctx->grouping = old; return e; }
+        }
         HIP_TRY(hipMemcpyAsync(ctx->f[0].p, keep_f.p, sizeof(float) * ctx->sys->J,
                                hipMemcpyDeviceToDevice, ctx->stream));
         ctx->fcur = 0;
@@ -1410,6 +1674,7 @@ int sgtv_set_init(sgtv_ctx ctx, const float *x0, int mem_kind) {
         drop_graphs(ctx);
         if (x0) {
             DBuf staged;
+            ArenaScope sc(ws_section(ctx, &Workspace::temp), true);
             if (int e = stage_floats(staged, x0, S.J, mem_kind, ctx->stream, finite_nonneg, "x0"))
                 return e;
             HIP_TRY(hipMemcpyAsync(ctx->f[0].p, staged.p, sizeof(float) * S.J,
@@ -1435,6 +1700,7 @@ int sgtv_set_init_dual(sgtv_ctx ctx, const float *x0, int mem_kind) {
     try {
         const System &S = *ctx->sys;
         DBuf staged;
+        ArenaScope sc(ws_section(ctx, &Workspace::temp), true);
         if (int e = stage_floats(staged, x0, S.J, mem_kind, ctx->stream, finite_nonneg, "x0")) return e;
         drop_graphs(ctx);
         HIP_TRY(hipMemcpyAsync(ctx->f[0].p, staged.p, sizeof(float) * S.J, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1691,8 +1957,11 @@ int sgtv_get_split(sgtv_ctx ctx, float *d, float *c, int mem_kind) {
     DeviceGuard g(ctx->device);
     const System &S = *ctx->sys;
     DBuf td, tc;
-    HIP_TRY(td.alloc(sizeof(float) * S.J * 4));
-    HIP_TRY(tc.alloc(sizeof(float) * S.J * 4));
+    {
+        ArenaScope sc(ws_section(ctx, &Workspace::temp), true);
+        HIP_TRY(td.alloc(sizeof(float) * S.J * 4));
+        HIP_TRY(tc.alloc(sizeof(float) * S.J * 4));
+    }
     HIP_TRY(sgtv::launch_split_from_state(ctx->v[ctx->vcur].as<float>(), ctx->a[ctx->vcur].as<float>(),
                                           td.as<float>(), tc.as<float>(), S.grid, ctx->grouping,
                                           ctx->stream));
@@ -1738,16 +2007,19 @@ int64_t sgtv_workspace_bytes(int64_t I, int64_t J, int64_t nnz, int storage_dtyp
 int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes) {
     if (!ctx || !bytes) return fail(SGTV_EINVAL, "null argument");
     int64_t b = 0;
+    auto add = [&](const DBuf *d) {
+        if (!d->borrowed) b += static_cast<int64_t>(d->bytes);
+    };
     for (const DBuf *d : {&ctx->y, &ctx->r, &ctx->ratio, &ctx->f[0], &ctx->f[1], &ctx->v[0], &ctx->v[1],
                           &ctx->a[0], &ctx->a[1], &ctx->fs, &ctx->part, &ctx->red})
-        b += static_cast<int64_t>(d->bytes);
+        add(d);
     if (ctx->sys) {
         const System &S = *ctx->sys;
         for (const DBuf *d : {&S.rs_ptr, &S.rs_idx, &S.rs_val, &S.cs_ptr, &S.cs_idx, &S.cs_val, &S.colscale,
-                              &S.sens, &S.H, &S.wbuf, &S.fpart, &S.bpart, &S.fwd.pk, &S.fwd.val, &S.fwd.goff,
-                              &S.fwd.poff, &S.fwd.slot, &S.back.pk, &S.back.val, &S.back.goff,
+                              &S.sens, &S.H, &S.htab, &S.wbuf, &S.fpart, &S.bpart, &S.fwd.pk, &S.fwd.val,
+                              &S.fwd.goff, &S.fwd.poff, &S.fwd.slot, &S.back.pk, &S.back.val, &S.back.goff,
                               &S.back.poff, &S.back.slot})
-            b += static_cast<int64_t>(d->bytes);
+            add(d);
     }
     *bytes = b;
     return SGTV_OK;
@@ -1788,6 +2060,7 @@ int sgtv_set_state(sgtv_ctx ctx, const float *f, const float *v, const float *a,
     try {
         const System &S = *ctx->sys;
         DBuf sf, sv, sa;
+        ArenaScope sc(ws_section(ctx, &Workspace::temp), true);
         if (int e = stage_floats(sf, f, S.J, mem_kind, ctx->stream, finite_nonneg, "f")) return e;
         if (int e = stage_floats(sv, v, S.J * 4, mem_kind, ctx->stream, finite_any, "v")) return e;
         if (int e = stage_floats(sa, a, n_groups(ctx), mem_kind, ctx->stream, unit_interval, "a")) return e;
@@ -1815,8 +2088,11 @@ int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind) {
     DeviceGuard g(ctx->device);
     const System &S = *ctx->sys;
     DBuf e, out;
-    HIP_TRY(e.alloc(sizeof(float) * S.J));
-    HIP_TRY(out.alloc(sizeof(float) * S.J));
+    {
+        ArenaScope sc(ws_section(ctx, &Workspace::temp), true);
+        HIP_TRY(e.alloc(sizeof(float) * S.J));
+        HIP_TRY(out.alloc(sizeof(float) * S.J));
+    }
     if (int st = back_project(S, ctx->y.as<float>(), e.as<float>(), ctx->stream)) return st;
     HIP_TRY(sgtv::launch_div_safe(e.as<float>(), S.sens.as<float>(), out.as<float>(), S.J, ctx->stream));
     HIP_TRY(hipMemcpyAsync(x, out.p, sizeof(float) * S.J, to_caller(mem_kind), ctx->stream));

@@ -87,6 +87,9 @@ def lib():
             "sgtv_last_error": (ctypes.c_char_p, []),
             "sgtv_version": (ctypes.c_char_p, []),
             "sgtv_set_system": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _I, _P, _I64, _I]),
+            "sgtv_plan_system": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _I, _P, _I64, _I,
+                                      ctypes.POINTER(_I64)]),
+            "sgtv_commit_system": (_I, [_P, _P, _I64]),
             "sgtv_set_data": (_I, [_P, _P, _P, _D, _D, _I, _I]),
             "sgtv_set_grouping": (_I, [_P, _I]),
             "sgtv_set_init": (_I, [_P, _P, _I]),
@@ -208,6 +211,34 @@ def sgtv_set_system(ctx, I, ny, nx, Q, row_ptr, col_idx, val, storage="f32", w=N
     wlen = 0 if w is None else int(np.prod(wa[2].shape))
     _check(lib().sgtv_set_system(ctx, int(I), int(ny), int(nx), int(Q), a[0], b[0], c[0], nnz,
                                  STORAGE.get(storage, storage), wa[0], wlen, mk))
+
+
+def sgtv_plan_system(ctx, I, ny, nx, Q, row_ptr, col_idx, val, storage="f32", w=None):
+    """Pack the system on the host; returns the exact device bytes of the
+    workspace that sgtv_commit_system needs."""
+    a = _arg(row_ptr, np.int64)
+    b = _arg(col_idx, np.int32)
+    c = _arg(val, np.float32)
+    wa = _arg(w, np.float32)
+    mk = _kind(a, b, c, wa)
+    nnz = int(b[2].shape[0]) if b[2] is not None else 0
+    wlen = 0 if w is None else int(np.prod(wa[2].shape))
+    n = _I64()
+    _check(lib().sgtv_plan_system(ctx, int(I), int(ny), int(nx), int(Q), a[0], b[0], c[0], nnz,
+                                  STORAGE.get(storage, storage), wa[0], wlen, mk, ctypes.byref(n)))
+    return n.value
+
+
+def sgtv_commit_system(ctx, workspace, nbytes=None):
+    """Put the planned system into a caller-owned device buffer: a torch
+    tensor on the context's GPU (its bytes are used) or a raw device pointer
+    with nbytes."""
+    if hasattr(workspace, "data_ptr"):
+        ptr = workspace.data_ptr()
+        size = workspace.numel() * workspace.element_size() if nbytes is None else int(nbytes)
+    else:
+        ptr, size = int(workspace), int(nbytes)
+    _check(lib().sgtv_commit_system(ctx, ctypes.c_void_p(ptr), size))
 
 
 def sgtv_set_data(ctx, y, r, beta, rho, sweeps=1):
@@ -475,6 +506,13 @@ class Reconstructor:
 
     def set_schedule(self, **fields):
         sgtv_set_schedule(self._ctx, **fields)
+        return self
+
+    def plan_system(self, I, ny, nx, Q, row_ptr, col_idx, val, storage="f32", w=None):
+        return sgtv_plan_system(self._ctx, I, ny, nx, Q, row_ptr, col_idx, val, storage, w)
+
+    def commit_system(self, workspace, nbytes=None):
+        sgtv_commit_system(self._ctx, workspace, nbytes)
         return self
 
     def set_fused_update(self, enable=True):

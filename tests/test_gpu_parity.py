@@ -438,3 +438,83 @@ def test_fused_update_equals_two_launches(sg, name):
     for a, b in zip(out[0][:3], out[1][:3]):
         np.testing.assert_array_equal(a, b)
     assert out[0][3] == out[1][3]
+
+
+def test_caller_owned_workspace(sg):
+    """Two-phase set-up: the exact size from sgtv_plan_system, a torch tensor
+    as the workspace, no device memory of the library's own afterwards, and
+    the same iterations (bit for bit) as a context that allocates itself;
+    every call that needs temporaries works inside the workspace."""
+    import torch
+    prob = datagen.make_problem("small", 3)
+    ref = run_gpu(sg, prob, 0)
+    R = sg.Reconstructor()
+    with pytest.raises(sg.SgtvError) as ei:
+        R.commit_system(torch.empty(1024, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == sg.SGTV_ESTATE
+    nbytes = R.plan_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val)
+    print("planned workspace", nbytes, "bytes; library-allocated context holds", ref.device_bytes(), flush=True)
+    assert nbytes > 0
+    small = torch.empty(nbytes - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sg.SgtvError) as ei:
+        R.commit_system(small)
+    assert ei.value.code == sg.SGTV_ENOMEM
+    ws = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sg.SgtvError) as ei:
+        sg.sgtv_commit_system(R._ctx, ws.data_ptr() + 4, nbytes)
+    assert ei.value.code == sg.SGTV_EINVAL
+    R.commit_system(ws, nbytes)
+    R.set_data(prob.y, prob.r, prob.beta, prob.rho, 1)
+    assert R.device_bytes() == 0
+    for Rx in (R, ref):
+        Rx.iterate(30)
+    np.testing.assert_array_equal(R.image(), ref.image())
+    assert R.objective() == ref.objective()
+    f_o, _, _, _ = oracle.admm(prob, 30, report=False)
+    assert rel_l2(R.image(), f_o) <= IMG_TOL
+    # temporaries and state changes inside the workspace
+    d1, c1 = R.split()
+    d2, c2 = ref.split()
+    np.testing.assert_array_equal(d1, d2)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(R.backprojection(), ref.backprojection())
+    st = R.state()
+    R.iterate(5)
+    R.set_state(*st)
+    R.iterate(5)
+    ref.iterate(5)
+    np.testing.assert_array_equal(R.image(), ref.image())
+    for Rx in (R, ref):
+        Rx.set_grouping(1)
+        Rx.set_init_dual(ref.image())
+        Rx.iterate(7)
+    np.testing.assert_array_equal(R.image(), ref.image())
+    for Rx in (R, ref):
+        Rx.set_data(prob.y * np.float32(2), prob.r, prob.beta, prob.rho, 1)
+        Rx.set_init(np.full(prob.J, 0.5, np.float32))
+        Rx.iterate(9)
+    np.testing.assert_array_equal(R.image(), ref.image())
+    assert R.device_bytes() == 0
+    R.close()
+    ref.close()
+    del ws
+
+
+def test_workspace_of_the_paper_scale_scan(sg):
+    """The planned size of the paper-scale scan, its set-up in a torch tensor
+    and two iterations equal to a library-allocated context."""
+    import torch
+    prob = datagen.make_problem("paper", 1)
+    R = sg.Reconstructor()
+    nbytes = R.plan_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val)
+    est = sg.sgtv_workspace_bytes(prob.I, prob.J, prob.nnz, "f32")
+    print("paper scan workspace", nbytes, "estimate", est, flush=True)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    R.commit_system(ws)
+    R.set_data(prob.y, prob.r, prob.beta, prob.rho, 1)
+    R.iterate(2)
+    ref = run_gpu(sg, prob, 2)
+    np.testing.assert_array_equal(R.image(), ref.image())
+    assert R.device_bytes() == 0 and ref.device_bytes() > 0.8 * nbytes
+    R.close()
+    ref.close()
