@@ -265,6 +265,25 @@ int sgtv_plan_system(sgtv_ctx ctx, int64_t I, int32_t ny, int32_t nx, int32_t Q,
                      int64_t w_len, int mem_kind, int64_t *bytes);
 int sgtv_commit_system(sgtv_ctx ctx, void *workspace, int64_t bytes);
 
+/*
+ * The packed system of a fixed scanner, stored once and loaded afterwards
+ * without packing again (packing the system matrix into the tiled layout is
+ * the slow part of sgtv_set_system).  sgtv_save_system writes the context's
+ * system (its schedule, tile tables, value arrays, H table and weights, not
+ * the data or the iteration state) to the file `path`; sgtv_load_system
+ * reads such a file into a context and installs it like sgtv_set_system
+ * (library-allocated memory, data and state cleared); the sensitivity A^T 1
+ * is computed again on the device.  A loaded system gives bit for bit the
+ * results of the system that was saved.  The file is for this library
+ * version and GPU architecture; it carries a checksum, and a damaged, short
+ * or foreign file gives SGTV_EINVAL with the context unchanged.  Its content
+ * is trusted beyond that: load only files that sgtv_save_system wrote.
+ * Errors: save without a system SGTV_ESTATE, a file that cannot be opened or
+ * written SGTV_EINVAL.
+ */
+int sgtv_save_system(sgtv_ctx ctx, const char *path);
+int sgtv_load_system(sgtv_ctx ctx, const char *path);
+
 /* Normalised backprojection x_in = (A^T y) / (A^T 1) (0 where A^T 1 = 0),
  * J floats, of the data currently set. */
 int sgtv_backprojection(sgtv_ctx ctx, float *x, int mem_kind);

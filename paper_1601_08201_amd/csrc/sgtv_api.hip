@@ -3,9 +3,13 @@
 // system matrix, device buffers of the ADMM state and the per-iteration
 // launch sequence.
 #include <hip/hip_runtime.h>
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -281,24 +285,35 @@ size_t tile_lds_bytes(const TileParams &t) {
     return a + static_cast<size_t>(t.cb) * 4 + 16;   // + the zero slot of the 24-bit format
 }
 
-// Host packing of one tiled product from CSR-like lines (rows of M in order,
-// column indices ascending within a row).  V is float or a 16-bit code.
-// Calls work(first, step) on up to 8 host threads, first = 0 .. n - 1 and
-// step = n, so that each worker takes every nth item of its own loop over
-// n_items items; an exception in any worker (an allocation that failed) is
-// rethrown as std::bad_alloc once all have finished.  Workers that cannot be
-// started run in the caller.
+// Wall times of the steps of the host-side packing, printed to stderr when
+// SGTV_SETUP_TIMES is set (diagnostics).
+struct SetupClock {
+    bool on = std::getenv("SGTV_SETUP_TIMES") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char *what) {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[sgtv setup] %-28s %8.3f s\n", what, std::chrono::duration<double>(now - t).count());
+        t = now;
+    }
+};
+
 // Threads of the host-side packing: SGTV_HOST_THREADS when it is set to a
-// positive count (at most 64), else up to 8 and no more than the host has.
+// positive count (at most 64), else up to 16 and no more than the host has.
 // The packed arrays do not depend on it.
 int64_t host_threads() {
     if (const char *e = std::getenv("SGTV_HOST_THREADS")) {
         const long n = std::strtol(e, nullptr, 10);
         if (n >= 1) return std::min<long>(n, 64);
     }
-    return std::max<int64_t>(1, std::min<int64_t>(8, std::thread::hardware_concurrency()));
+    return std::max<int64_t>(1, std::min<int64_t>(16, std::thread::hardware_concurrency()));
 }
 
+// Calls work(first, step) on up to host_threads() threads, first = 0 .. n - 1
+// and step = n, so that each worker takes every nth item of its own loop over
+// n_items items; an exception in any worker (an allocation that failed) is
+// rethrown as std::bad_alloc once all have finished.  Workers that cannot be
+// started run in the caller.
 template <class Fn>
 void on_threads(int64_t n_items, Fn work) {
     const int64_t nth = std::max<int64_t>(1, std::min<int64_t>(host_threads(), n_items));
@@ -323,6 +338,46 @@ void on_threads(int64_t n_items, Fn work) {
     if (failed) throw std::bad_alloc();
 }
 
+// The columns of a CSR matrix: cp (J + 1 offsets), the rows of every column
+// in ascending order (cidx) and the values alongside (cv).  Each worker owns
+// a range of columns: it counts them, then, after the prefix sum, passes over
+// the rows in order and places the entries of its columns, so every column
+// list is written by one worker in row order whatever the thread count.
+template <class V>
+void transpose_csr(int64_t I, int64_t J, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+                   const std::vector<V> &av, std::vector<int64_t> &cp, std::vector<int32_t> &cidx,
+                   std::vector<V> &cv) {
+    const int64_t nnz = rp[I];
+    const int64_t nw = std::max<int64_t>(1, std::min<int64_t>(host_threads(), J));
+    cp.assign(static_cast<size_t>(J + 1), 0);
+    cidx.resize(static_cast<size_t>(nnz));
+    cv.resize(static_cast<size_t>(nnz));
+    on_threads(nw, [&](int64_t me, int64_t step) {
+        for (int64_t w = me; w < nw; w += step) {
+            const int64_t c0 = J * w / nw, c1 = J * (w + 1) / nw;
+            for (int64_t k = 0; k < nnz; ++k)
+                if (ci[k] >= c0 && ci[k] < c1) cp[ci[k] + 1]++;
+        }
+    });
+    for (int64_t j = 0; j < J; ++j) cp[j + 1] += cp[j];
+    std::vector<int64_t> next(cp.begin(), cp.end() - 1);
+    on_threads(nw, [&](int64_t me, int64_t step) {
+        for (int64_t w = me; w < nw; w += step) {
+            const int64_t c0 = J * w / nw, c1 = J * (w + 1) / nw;
+            for (int64_t i = 0; i < I; ++i)
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                    const int64_t c = ci[k];
+                    if (c < c0 || c >= c1) continue;
+                    const int64_t pos = next[c]++;
+                    cidx[pos] = static_cast<int32_t>(i);
+                    cv[pos] = av[k];
+                }
+        }
+    });
+}
+
+// Host packing of one tiled product from CSR-like lines (rows of M in order,
+// column indices ascending within a row).  V is float or a 16-bit code.
 template <class V>
 int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
@@ -334,6 +389,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     // of a window of entries at once (no other lane touches its rows)
     idx24 = idx24 && t.rw >= 64 && t.rw <= 1024 && t.cb % 4 == 0 && t.cb <= 16380;
     const int row_shift = idx24 ? 14 : 16;
+    SetupClock clk;
     const int64_t RB = static_cast<int64_t>(t.waves) * t.rw;
     const int64_t n_rb = (n_rows + RB - 1) / RB;
     const int64_t ncb = (n_cols + t.cb - 1) / t.cb;
@@ -424,6 +480,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             }
         });
     }
+    clk.mark("  rows dealt to waves");
     // slot (wave * rw + row in the wave) of row r in the tile of column c
     auto slot_in_tile = [&](int64_t r, int32_t c) -> int64_t {
         const int64_t rb = r / RB, i = r - rb * RB;
@@ -453,6 +510,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                     maxrun[L] = std::max(maxrun[L], run[L]);
                 }
     });
+    clk.mark("  list counts");
     // idx24: the entries (indices into ci / vals) of every list, in row order
     std::vector<int64_t> lstart, lent;
     std::vector<int16_t> lrow;   // row within the wave of every listed entry
@@ -472,6 +530,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                     }
         });
     }
+    clk.mark("  list filling");
     // Lane-owned layout of list L: runs of equal rows, longest first (ties in
     // row order), each to the least-loaded lane (ties: lowest lane); a lane
     // keeps its runs in row order.  Fills lane_load[64] and, in lane order,
@@ -557,6 +616,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             ngr[L] = static_cast<int32_t>(std::min<int64_t>(ng, int64_t(1) << 30));
         });
     });
+    clk.mark("  lane layout (sizes)");
     goff.assign(static_cast<size_t>(n_lists + 1), 0);
     int64_t total = 0;
     for (int64_t L = 0; L < n_lists; ++L) {
@@ -595,6 +655,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 }
         });
     }
+    clk.mark("  array fill");
     poff.clear();
     if (idx24) {
         // lane-owned placement: lane l's i-th entry in group i; a lane shorter
@@ -644,6 +705,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
             words += nb4 * 3 * 64 + (ng - nb4 * 4) * 64;   // super-batches take 3 dwords per batch too
         }
         poff[n_lists] = static_cast<int32_t>(words);
+        clk.mark("  lane placement");
         std::vector<int32_t> p24(static_cast<size_t>(words));
         on_threads(n_chunks, [&](int64_t first, int64_t step) {
             chunk_lists(first, step, [&](int64_t L) {
@@ -684,6 +746,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
         // lists (the simple loop that reads 24-bit indices never streams it)
         p24.insert(p24.end(), pk.end() - 256, pk.end());
         pk.swap(p24);
+        clk.mark("  24-bit repacking");
     }
     map = sgtv::TileMap{};
     map.idx24 = idx24 ? 1 : 0;
@@ -721,6 +784,15 @@ int pack_tiled(PackedTiled &T, int64_t n_rows, int64_t n_cols, const std::vector
     return SGTV_OK;
 }
 
+// Points a tile map at its device arrays (absent arrays: null).
+void point_tiled(Tiled &T) {
+    T.map.pk = T.pk.as<int32_t>();
+    T.map.val = T.val.p;
+    T.map.goff = T.goff.as<int32_t>();
+    T.map.poff = T.poff.as<int32_t>();
+    T.map.slot = T.slot.as<uint16_t>();
+}
+
 int upload_tiled(Tiled &T, const PackedTiled &P) {
     T.map = P.map;
     HIP_TRY(upload(T.pk, P.pk));
@@ -729,11 +801,7 @@ int upload_tiled(Tiled &T, const PackedTiled &P) {
     HIP_TRY(upload(T.goff, P.goff));
     if (!P.poff.empty()) HIP_TRY(upload(T.poff, P.poff));
     if (!P.slot.empty()) HIP_TRY(upload(T.slot, P.slot));
-    T.map.pk = T.pk.as<int32_t>();
-    T.map.val = T.val.p;
-    T.map.goff = T.goff.as<int32_t>();
-    T.map.poff = P.poff.empty() ? nullptr : T.poff.as<int32_t>();
-    T.map.slot = P.slot.empty() ? nullptr : T.slot.as<uint16_t>();
+    point_tiled(T);
     return SGTV_OK;
 }
 
@@ -973,6 +1041,7 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
                 const float *w, int64_t w_len, int mk) {
     PK.S = std::make_unique<System>();
     System *S = PK.S.get();
+    SetupClock clk;
     S->I = I; S->ny = ny; S->nx = nx; S->Q = Q; S->vt = vt; S->nnz = nnz;
     S->S = static_cast<int64_t>(ny) * nx;
     S->J = S->S * Q;
@@ -985,6 +1054,7 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
     HIP_TRY(fetch(rp, row_ptr, I + 1, mk));
     HIP_TRY(fetch(ci, col_idx, nnz, mk));
     HIP_TRY(fetch(av, val, nnz, mk));
+    clk.mark("fetch");
     if (rp[0] != 0 || rp[I] != nnz) return fail(SGTV_ESHAPE, "row_ptr[0] must be 0 and row_ptr[I] must equal nnz");
     for (int64_t i = 0; i < I; ++i)
         if (rp[i + 1] < rp[i]) return fail(SGTV_ESHAPE, "row_ptr decreases at row " + std::to_string(i));
@@ -1004,6 +1074,7 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
             S->wfull = true;
         }
     }
+    clk.mark("validation");
     // De Pierro curvature without the penalty factor: H0 = |D|^T |D| 1 (the
     // kernels use rho * H0)
     std::vector<double> Hd(static_cast<size_t>(J), 0.0);
@@ -1044,6 +1115,7 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
         }
     }
 
+    clk.mark("curvature");
     // column scales and 16-bit codes
     std::vector<float> sigma;
     std::vector<uint16_t> codes;
@@ -1075,31 +1147,27 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
         S->sched.variant = q.variant > 0 ? q.variant : 1;
         S->perm.resize(static_cast<size_t>(I));
         for (int64_t i = 0; i < I; ++i) S->perm[i] = i;
-        // transpose (counting sort by column; rows ascending within a column)
-        std::vector<int64_t> cp(static_cast<size_t>(J + 1), 0);
-        for (int64_t k = 0; k < nnz; ++k) cp[ci[k] + 1]++;
-        for (int64_t j = 0; j < J; ++j) cp[j + 1] += cp[j];
-        std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
-        std::vector<int32_t> cidx(static_cast<size_t>(nnz));
-        std::vector<int64_t> csrc(static_cast<size_t>(nnz));
-        for (int64_t i = 0; i < I; ++i)
-            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-                const int64_t pos = cur[ci[k]]++;
-                cidx[pos] = static_cast<int32_t>(i);
-                csrc[pos] = k;
-            }
         // the simple loop (variant 1) reads 24-bit indices where the tile fits them
         const bool i24 = S->sched.variant == 1;
+        // transpose (rows ascending within a column) with the values alongside
+        std::vector<int64_t> cp;
+        std::vector<int32_t> cidx;
         if (vt == SGTV_F32) {
+            std::vector<float> cv;
+            transpose_csr(I, J, rp, ci, av, cp, cidx, cv);
+            clk.mark("transpose");
             if (int e = pack_tiled(PK.fwd, I, J, rp, ci, av, tf, i24)) return e;
-            std::vector<float> cv(static_cast<size_t>(nnz));
-            for (int64_t k = 0; k < nnz; ++k) cv[k] = av[csrc[k]];
+            clk.mark("forward copy");
             if (int e = pack_tiled(PK.back, J, I, cp, cidx, cv, tb, i24)) return e;
+            clk.mark("back copy");
         } else {
+            std::vector<uint16_t> cv;
+            transpose_csr(I, J, rp, ci, codes, cp, cidx, cv);
+            clk.mark("transpose");
             if (int e = pack_tiled(PK.fwd, I, J, rp, ci, codes, tf, i24)) return e;
-            std::vector<uint16_t> cv(static_cast<size_t>(nnz));
-            for (int64_t k = 0; k < nnz; ++k) cv[k] = codes[csrc[k]];
+            clk.mark("forward copy");
             if (int e = pack_tiled(PK.back, J, I, cp, cidx, cv, tb, i24)) return e;
+            clk.mark("back copy");
         }
         PK.fwd.map.variant = S->sched.variant - 1;
         PK.back.map.variant = S->sched.variant - 1;
@@ -1180,6 +1248,8 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
     return SGTV_OK;
 }
 
+int compute_sensitivity(sgtv_ctx_s *c, System &S, Arena *temp);
+
 // Put a packed system on the device: every buffer is allocated (from the
 // current arena, if any; a counting arena only adds up the bytes) and
 // filled, and the sensitivity s = A^T 1 is computed with the stored values
@@ -1209,6 +1279,11 @@ int upload_system(sgtv_ctx_s *c, Packed &PK, Arena *temp) {
     HIP_TRY(upload(S.H, PK.H));
     HIP_TRY(upload(S.htab, PK.htab));
     if (S.wfull) HIP_TRY(upload(S.wbuf, PK.wf));
+    return compute_sensitivity(c, S, temp);
+}
+
+// The sensitivity s = A^T 1 of a system whose arrays are on the device.
+int compute_sensitivity(sgtv_ctx_s *c, System &S, Arena *temp) {
     HIP_TRY(S.sens.alloc(sizeof(float) * S.J));
     if (counting()) return SGTV_OK;
     // sensitivity s = A^T 1 with the stored (possibly quantised) values
@@ -1566,6 +1641,351 @@ int sgtv_commit_system(sgtv_ctx ctx, void *workspace, int64_t bytes) {
             if (int e = ensure_partials(ctx)) return e;
         }
         ctx->pending.reset();
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// File of a packed system (sgtv_save_system / sgtv_load_system):
+//   FileHead, SysMeta, the row permutation (I int64), one ArrayRec per device
+//   array, a 64-bit hash of all of these; then the arrays' bytes, one after
+//   the other (every byte of the file is covered by a hash).
+// Arrays move in chunks of kIoChunk bytes through pinned staging buffers, one
+// per host thread, and every chunk is hashed on the way; an array's hash
+// folds its chunk hashes in order, so it does not depend on the threads.
+constexpr char kSysMagic[8] = {'S', 'G', 'T', 'V', 'S', 'Y', 'S', '1'};
+constexpr uint32_t kSysVersion = 2;
+constexpr size_t kIoChunk = size_t(8) << 20;
+constexpr int kSysArrays = 20;
+
+struct FileHead {
+    char magic[8];
+    uint32_t version, meta_bytes, map_bytes, n_arrays;
+    int64_t n_perm;
+};
+
+struct SysMeta {
+    int64_t I, J, S, nnz;
+    int32_t ny, nx, Q, vt, format, wfull, fused_tw, fused_th, fused_threads, pad_;
+    sgtv_schedule sched;
+    float w4[4];
+    int64_t n_rslices, n_cslices, fpart_bytes, bpart_bytes;
+    sgtv::TileMap fwd, back;   // the pointers in it are not used
+};
+
+struct ArrayRec {
+    int64_t offset, bytes;
+    uint64_t hash;
+    int32_t present, pad_;
+};
+
+constexpr uint64_t kHashBasis = 1469598103934665603ull, kHashPrime = 1099511628211ull;
+
+uint64_t hash_step(uint64_t h, uint64_t x) { return (((h << 23) | (h >> 41)) ^ x) * kHashPrime; }
+
+// Four interleaved lanes over 8-byte words, the tail and the length last.
+uint64_t chunk_hash(const unsigned char *p, size_t n) {
+    uint64_t h[4] = {kHashBasis, kHashBasis + 1, kHashBasis + 2, kHashBasis + 3};
+    const size_t nw = n / 8;
+    size_t k = 0;
+    for (; k + 4 <= nw; k += 4)
+        for (int l = 0; l < 4; ++l) {
+            uint64_t x;
+            std::memcpy(&x, p + 8 * (k + l), 8);
+            h[l] = hash_step(h[l], x);
+        }
+    for (; k < nw; ++k) {
+        uint64_t x;
+        std::memcpy(&x, p + 8 * k, 8);
+        h[0] = hash_step(h[0], x);
+    }
+    uint64_t tail = 0;
+    std::memcpy(&tail, p + 8 * nw, n - 8 * nw);
+    uint64_t r = hash_step(h[0], h[1]);
+    r = hash_step(r, h[2]);
+    r = hash_step(r, h[3]);
+    r = hash_step(r, tail);
+    return hash_step(r, static_cast<uint64_t>(n));
+}
+
+// The device arrays of a system in file order.
+template <class F>
+void each_array(System &S, F fn) {
+    for (DBuf *d : {&S.colscale, &S.H, &S.htab, &S.wbuf, &S.fwd.pk, &S.fwd.val, &S.fwd.goff, &S.fwd.poff,
+                    &S.fwd.slot, &S.back.pk, &S.back.val, &S.back.goff, &S.back.poff, &S.back.slot, &S.rs_ptr,
+                    &S.rs_idx, &S.rs_val, &S.cs_ptr, &S.cs_idx, &S.cs_val})
+        fn(*d);
+}
+
+struct FileCloser {
+    int fd = -1;
+    ~FileCloser() {
+        if (fd >= 0) ::close(fd);
+    }
+};
+
+// Moves the arrays between the device and the file in chunks, on the host
+// threads, each with its own pinned staging buffer; fills chunk hashes (in
+// order per array).  to_file: device -> file, else file -> device.
+int move_arrays(int device, int fd, std::vector<DBuf *> &bufs, const std::vector<ArrayRec> &rec, bool to_file,
+                std::vector<uint64_t> &hashes) {
+    struct Item {
+        int a;
+        int64_t off;
+        size_t n;
+    };
+    std::vector<Item> items;
+    std::vector<size_t> first(bufs.size() + 1, 0);
+    for (size_t a = 0; a < bufs.size(); ++a) {
+        first[a] = items.size();
+        for (int64_t off = 0; off < rec[a].bytes; off += static_cast<int64_t>(kIoChunk))
+            items.push_back({static_cast<int>(a), off,
+                             static_cast<size_t>(std::min<int64_t>(kIoChunk, rec[a].bytes - off))});
+    }
+    first[bufs.size()] = items.size();
+    std::vector<uint64_t> ch(items.size(), 0);
+    std::atomic<int> status{SGTV_OK};
+    std::mutex msg_mu;
+    std::string msg;
+    auto set_error = [&](int code, const std::string &m) {
+        int ok = SGTV_OK;
+        if (status.compare_exchange_strong(ok, code)) {
+            std::lock_guard<std::mutex> lk(msg_mu);
+            msg = m;
+        }
+    };
+    on_threads(static_cast<int64_t>(items.size()), [&](int64_t me, int64_t step) {
+        if (hipSetDevice(device) != hipSuccess) {
+            set_error(SGTV_EDEVICE, "cannot select device");
+            return;
+        }
+        void *stage = nullptr;
+        if (hipHostMalloc(&stage, kIoChunk) != hipSuccess) {
+            set_error(SGTV_ENOMEM, "pinned staging buffer of 8 MiB");
+            return;
+        }
+        unsigned char *buf = static_cast<unsigned char *>(stage);
+        for (int64_t k = me; k < static_cast<int64_t>(items.size()) && status.load() == SGTV_OK; k += step) {
+            const Item &it = items[k];
+            char *dev = static_cast<char *>(bufs[it.a]->p) + it.off;
+            const off_t at = static_cast<off_t>(rec[it.a].offset + it.off);
+            if (to_file) {
+                hipError_t e = hipMemcpy(buf, dev, it.n, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) {
+                    set_error(SGTV_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+                    break;
+                }
+                ch[k] = chunk_hash(buf, it.n);
+                for (size_t done = 0; done < it.n;) {
+                    const ssize_t w = ::pwrite(fd, buf + done, it.n - done, at + static_cast<off_t>(done));
+                    if (w <= 0) {
+                        set_error(SGTV_EINVAL, "writing the system file failed");
+                        break;
+                    }
+                    done += static_cast<size_t>(w);
+                }
+            } else {
+                size_t done = 0;
+                while (done < it.n) {
+                    const ssize_t r = ::pread(fd, buf + done, it.n - done, at + static_cast<off_t>(done));
+                    if (r <= 0) break;
+                    done += static_cast<size_t>(r);
+                }
+                if (done != it.n) {
+                    set_error(SGTV_EINVAL, "the system file is truncated");
+                    break;
+                }
+                ch[k] = chunk_hash(buf, it.n);
+                hipError_t e = hipMemcpy(dev, buf, it.n, hipMemcpyHostToDevice);
+                if (e != hipSuccess) {
+                    set_error(SGTV_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+                    break;
+                }
+            }
+        }
+        (void)hipHostFree(stage);
+    });
+    if (status.load() != SGTV_OK) return fail(status.load(), msg);
+    hashes.assign(bufs.size(), 0);
+    for (size_t a = 0; a < bufs.size(); ++a) {
+        uint64_t h = kHashBasis;
+        for (size_t k = first[a]; k < first[a + 1]; ++k) h = hash_step(h, ch[k]);
+        hashes[a] = hash_step(h, static_cast<uint64_t>(rec[a].bytes));
+    }
+    return SGTV_OK;
+}
+
+std::vector<char> head_bytes(const FileHead &fh, const SysMeta &m, const std::vector<int64_t> &perm,
+                             const std::vector<ArrayRec> &rec) {
+    std::vector<char> b(sizeof(fh) + sizeof(m) + sizeof(int64_t) * perm.size() + sizeof(ArrayRec) * rec.size());
+    char *p = b.data();
+    std::memcpy(p, &fh, sizeof(fh)); p += sizeof(fh);
+    std::memcpy(p, &m, sizeof(m)); p += sizeof(m);
+    if (!perm.empty()) std::memcpy(p, perm.data(), sizeof(int64_t) * perm.size());
+    p += sizeof(int64_t) * perm.size();
+    std::memcpy(p, rec.data(), sizeof(ArrayRec) * rec.size());
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgtv_save_system(sgtv_ctx ctx, const char *path) {
+    if (!ctx || !path) return fail(SGTV_EINVAL, "null argument");
+    if (!ctx->sys) return fail(SGTV_ESTATE, "no system set");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    try {
+        System &S = *ctx->sys;
+        SysMeta m{};
+        m.I = S.I; m.J = S.J; m.S = S.S; m.nnz = S.nnz;
+        m.ny = S.ny; m.nx = S.nx; m.Q = S.Q; m.vt = S.vt; m.format = S.format; m.wfull = S.wfull ? 1 : 0;
+        m.fused_tw = S.fused_tw; m.fused_th = S.fused_th; m.fused_threads = S.fused_threads;
+        m.sched = S.sched;
+        for (int p = 0; p < 4; ++p) m.w4[p] = S.w4[p];
+        m.n_rslices = S.n_rslices; m.n_cslices = S.n_cslices;
+        m.fpart_bytes = static_cast<int64_t>(S.fpart.bytes);
+        m.bpart_bytes = static_cast<int64_t>(S.bpart.bytes);
+        m.fwd = S.fwd.map;
+        m.back = S.back.map;
+        FileHead fh{};
+        std::memcpy(fh.magic, kSysMagic, 8);
+        fh.version = kSysVersion;
+        fh.meta_bytes = sizeof(SysMeta);
+        fh.map_bytes = sizeof(sgtv::TileMap);
+        fh.n_arrays = kSysArrays;
+        fh.n_perm = static_cast<int64_t>(S.perm.size());
+        std::vector<DBuf *> bufs;
+        each_array(S, [&](DBuf &d) { bufs.push_back(&d); });
+        std::vector<ArrayRec> rec(bufs.size());
+        int64_t off = static_cast<int64_t>(head_bytes(fh, m, S.perm, rec).size() + 8);
+        for (size_t a = 0; a < bufs.size(); ++a) {
+            rec[a].offset = off;
+            rec[a].bytes = static_cast<int64_t>(bufs[a]->bytes);
+            rec[a].present = bufs[a]->p != nullptr;
+            off += rec[a].bytes;
+        }
+        FileCloser fc;
+        fc.fd = ::open(path, O_WRONLY | O_CREAT | O_TRUNC, 0644);
+        if (fc.fd < 0) return fail(SGTV_EINVAL, std::string("cannot open ") + path + " for writing");
+        std::vector<uint64_t> hashes;
+        if (int e = move_arrays(ctx->device, fc.fd, bufs, rec, true, hashes)) return e;
+        for (size_t a = 0; a < bufs.size(); ++a) rec[a].hash = hashes[a];
+        std::vector<char> head = head_bytes(fh, m, S.perm, rec);
+        const uint64_t hh = chunk_hash(reinterpret_cast<const unsigned char *>(head.data()), head.size());
+        head.resize(head.size() + 8);
+        std::memcpy(head.data() + head.size() - 8, &hh, 8);
+        if (::pwrite(fc.fd, head.data(), head.size(), 0) != static_cast<ssize_t>(head.size()) ||
+            ::ftruncate(fc.fd, static_cast<off_t>(off)) != 0)
+            return fail(SGTV_EINVAL, std::string("writing ") + path + " failed");
+    } catch (const std::bad_alloc &) {
+        return fail(SGTV_ENOMEM, "host allocation failed");
+    }
+    return SGTV_OK;
+}
+
+int sgtv_load_system(sgtv_ctx ctx, const char *path) {
+    if (!ctx || !path) return fail(SGTV_EINVAL, "null argument");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SGTV_EDEVICE, "cannot select device");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    try {
+        FileCloser fc;
+        fc.fd = ::open(path, O_RDONLY);
+        if (fc.fd < 0) return fail(SGTV_EINVAL, std::string("cannot open ") + path);
+        struct stat st{};
+        if (::fstat(fc.fd, &st) != 0) return fail(SGTV_EINVAL, std::string("cannot stat ") + path);
+        const int64_t fsize = static_cast<int64_t>(st.st_size);
+        const std::string bad = std::string(path) + " is not a system file of this library version";
+        FileHead fh{};
+        if (::pread(fc.fd, &fh, sizeof(fh), 0) != static_cast<ssize_t>(sizeof(fh)) ||
+            std::memcmp(fh.magic, kSysMagic, 8) != 0 || fh.version != kSysVersion ||
+            fh.meta_bytes != sizeof(SysMeta) || fh.map_bytes != sizeof(sgtv::TileMap) ||
+            fh.n_arrays != kSysArrays || fh.n_perm < 0 || fh.n_perm > (int64_t(1) << 31))
+            return fail(SGTV_EINVAL, bad);
+        const size_t hb = sizeof(fh) + sizeof(SysMeta) + sizeof(int64_t) * static_cast<size_t>(fh.n_perm) +
+                          sizeof(ArrayRec) * kSysArrays;
+        if (static_cast<int64_t>(hb + 8) > fsize) return fail(SGTV_EINVAL, std::string(path) + " is truncated");
+        std::vector<char> head(hb + 8);
+        if (::pread(fc.fd, head.data(), head.size(), 0) != static_cast<ssize_t>(head.size()))
+            return fail(SGTV_EINVAL, std::string(path) + " is truncated");
+        uint64_t hh;
+        std::memcpy(&hh, head.data() + hb, 8);
+        if (hh != chunk_hash(reinterpret_cast<const unsigned char *>(head.data()), hb))
+            return fail(SGTV_EINVAL, std::string(path) + ": damaged header");
+        SysMeta m;
+        const char *p = head.data() + sizeof(fh);
+        std::memcpy(&m, p, sizeof(m)); p += sizeof(m);
+        auto Sp = std::make_unique<System>();
+        System &S = *Sp;
+        S.perm.resize(static_cast<size_t>(fh.n_perm));
+        if (fh.n_perm) std::memcpy(S.perm.data(), p, sizeof(int64_t) * S.perm.size());
+        p += sizeof(int64_t) * S.perm.size();
+        std::vector<ArrayRec> rec(kSysArrays);
+        std::memcpy(rec.data(), p, sizeof(ArrayRec) * kSysArrays);
+        // the description must be one the packer makes
+        const bool shape_ok = m.I >= 1 && m.ny >= 1 && m.nx >= 1 && m.Q >= 1 && m.S == int64_t(m.ny) * m.nx &&
+                              m.J == m.S * m.Q && m.J < (int64_t(1) << 31) && m.I < (int64_t(1) << 31) &&
+                              (m.vt == SGTV_F32 || m.vt == SGTV_BF16 || m.vt == SGTV_F16) &&
+                              (m.format == SGTV_FORMAT_TILED || m.format == SGTV_FORMAT_SELL) &&
+                              fh.n_perm == m.I && m.fpart_bytes >= 0 && m.bpart_bytes >= 0;
+        if (!shape_ok) return fail(SGTV_EINVAL, std::string(path) + ": inconsistent system description");
+        S.I = m.I; S.J = m.J; S.S = m.S; S.nnz = m.nnz;
+        S.ny = m.ny; S.nx = m.nx; S.Q = m.Q; S.vt = m.vt; S.format = m.format; S.wfull = m.wfull != 0;
+        S.fused_tw = m.fused_tw; S.fused_th = m.fused_th; S.fused_threads = m.fused_threads;
+        S.sched = m.sched;
+        for (int q = 0; q < 4; ++q) S.w4[q] = m.w4[q];
+        S.grid = sgtv::Grid{S.ny, S.nx, S.Q, S.S, S.J};
+        S.n_rslices = m.n_rslices; S.n_cslices = m.n_cslices;
+        S.fwd.map = m.fwd;
+        S.back.map = m.back;
+        std::vector<DBuf *> bufs;
+        each_array(S, [&](DBuf &d) { bufs.push_back(&d); });
+        for (const ArrayRec &r : rec)
+            if (r.bytes < 0 || r.offset < static_cast<int64_t>(hb) || r.offset > fsize || r.bytes > fsize - r.offset ||
+                (r.bytes > 0 && !r.present))
+                return fail(SGTV_EINVAL, std::string(path) + " is truncated or inconsistent");
+        // the arrays the kernels index must have the sizes the description implies
+        auto rec_of = [&](const DBuf &d) -> const ArrayRec & {
+            for (size_t a = 0; a < bufs.size(); ++a)
+                if (bufs[a] == &d) return rec[a];
+            return rec[0];
+        };
+        bool sizes_ok = rec_of(S.H).bytes == 4 * S.J && rec_of(S.htab).bytes == 64 &&
+                        (S.vt == SGTV_F32 || rec_of(S.colscale).bytes == 4 * S.J) &&
+                        (!S.wfull || rec_of(S.wbuf).bytes == 16 * S.J);
+        if (S.format == SGTV_FORMAT_TILED)
+            for (const Tiled *T : {&S.fwd, &S.back}) {
+                const sgtv::TileMap &t = T->map;
+                const int64_t n_lists = t.n_rb * static_cast<int64_t>(t.ns) * t.cbs_max * t.waves;
+                sizes_ok = sizes_ok && t.ns >= 1 && t.ns <= sgtv::kMaxSlabs && n_lists >= 0 &&
+                           rec_of(T->goff).bytes == 4 * (n_lists + 1);
+            }
+        if (!sizes_ok) return fail(SGTV_EINVAL, std::string(path) + ": inconsistent arrays");
+        for (size_t a = 0; a < bufs.size(); ++a)
+            if (rec[a].present) HIP_TRY(bufs[a]->alloc(static_cast<size_t>(rec[a].bytes)));
+        std::vector<uint64_t> hashes;
+        if (int e = move_arrays(ctx->device, fc.fd, bufs, rec, false, hashes)) return e;
+        for (size_t a = 0; a < bufs.size(); ++a)
+            if (hashes[a] != rec[a].hash) return fail(SGTV_EINVAL, std::string(path) + ": damaged array data");
+        if (S.format == SGTV_FORMAT_TILED) {
+            point_tiled(S.fwd);
+            point_tiled(S.back);
+            HIP_TRY(S.fpart.alloc(static_cast<size_t>(m.fpart_bytes)));
+            HIP_TRY(S.bpart.alloc(static_cast<size_t>(m.bpart_bytes)));
+        }
+        if (int e = compute_sensitivity(ctx, S, nullptr)) return e;
+        install_system(ctx, std::move(Sp));
+        ctx->ws = Workspace{};
+        ctx->pending.reset();
+        if (int e = ensure_partials(ctx)) return e;
     } catch (const std::bad_alloc &) {
         return fail(SGTV_ENOMEM, "host allocation failed");
     }

@@ -90,6 +90,8 @@ def lib():
             "sgtv_plan_system": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _I, _P, _I64, _I,
                                       ctypes.POINTER(_I64)]),
             "sgtv_commit_system": (_I, [_P, _P, _I64]),
+            "sgtv_save_system": (_I, [_P, ctypes.c_char_p]),
+            "sgtv_load_system": (_I, [_P, ctypes.c_char_p]),
             "sgtv_set_data": (_I, [_P, _P, _P, _D, _D, _I, _I]),
             "sgtv_set_grouping": (_I, [_P, _I]),
             "sgtv_set_init": (_I, [_P, _P, _I]),
@@ -239,6 +241,16 @@ def sgtv_commit_system(ctx, workspace, nbytes=None):
     else:
         ptr, size = int(workspace), int(nbytes)
     _check(lib().sgtv_commit_system(ctx, ctypes.c_void_p(ptr), size))
+
+
+def sgtv_save_system(ctx, path):
+    """Write the context's packed system to a file."""
+    _check(lib().sgtv_save_system(ctx, os.fsencode(path)))
+
+
+def sgtv_load_system(ctx, path):
+    """Install a packed system from a file that sgtv_save_system wrote."""
+    _check(lib().sgtv_load_system(ctx, os.fsencode(path)))
 
 
 def sgtv_set_data(ctx, y, r, beta, rho, sweeps=1):
@@ -513,6 +525,14 @@ class Reconstructor:
 
     def commit_system(self, workspace, nbytes=None):
         sgtv_commit_system(self._ctx, workspace, nbytes)
+        return self
+
+    def save_system(self, path):
+        sgtv_save_system(self._ctx, path)
+        return self
+
+    def load_system(self, path):
+        sgtv_load_system(self._ctx, path)
         return self
 
     def set_fused_update(self, enable=True):

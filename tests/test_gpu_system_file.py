@@ -1,0 +1,151 @@
+"""Saving a packed system and loading it into another context.
+
+A loaded system must give bit for bit the images and objective of the system
+that was saved (same schedule, tile tables, values, weights); a damaged,
+truncated or foreign file is refused and leaves the context as it was.  On the
+paper-scale scan (128 x 128 x 128 unknowns, 134M entries) the load replaces
+packing the matrix again, and its time is printed beside set_system's.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_1601_08201_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1601_08201_amd import sgtv
+    sgtv.lib()
+    return sgtv
+
+
+def direction_weights(prob):
+    return np.array([1.0, 0.7, 1.3, 0.9], np.float32)
+
+
+def full_weights(prob):
+    rng = np.random.Generator(np.random.PCG64(5))
+    return rng.uniform(0.5, 1.5, size=4 * prob.J).astype(np.float32)
+
+
+CASES = {
+    "tiled f32": dict(cfg="small", seed=1),
+    "tiled bf16": dict(cfg="small", seed=2, storage="bf16"),
+    "tiled f16 with direction weights": dict(cfg="teflon", seed=3, storage="f16", w=direction_weights),
+    "full weights": dict(cfg=dict(ny=9, nx=13, Q=24, I=1500, nnz_per_col=8, rects=3), seed=4, w=full_weights),
+    "sliced ELL": dict(cfg="small", seed=5, schedule=dict(format=1)),
+    "sliced ELL bf16": dict(cfg="small", seed=6, storage="bf16", schedule=dict(format=1)),
+    "fused update": dict(cfg="teflon", seed=7, fused=True),
+}
+
+
+def build(sg, prob, storage="f32", w=None, schedule=None):
+    R = sg.Reconstructor()
+    if schedule:
+        R.set_schedule(**schedule)
+    R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val, storage=storage,
+                 w=None if w is None else w(prob))
+    return R
+
+
+def run(R, prob, n, fused=False):
+    R.set_data(prob.y, prob.r, prob.beta, prob.rho, prob.sweeps)
+    if fused:
+        R.set_fused_update(True)
+    R.iterate(n)
+    return R.image(), R.objective()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_loaded_system_reproduces_the_saved_one(sg, tmp_path, name):
+    c = CASES[name]
+    prob = datagen.make_problem(c["cfg"], c["seed"])
+    A = build(sg, prob, c.get("storage", "f32"), c.get("w"), c.get("schedule"))
+    path = str(tmp_path / "system.bin")
+    A.save_system(path)
+    B = sg.Reconstructor()
+    B.load_system(path)
+    assert B.schedule() == A.schedule()
+    img_a, obj_a = run(A, prob, 20, c.get("fused", False))
+    img_b, obj_b = run(B, prob, 20, c.get("fused", False))
+    print(name, "file", os.path.getsize(path), "bytes, objective", obj_a["total"], flush=True)
+    assert A.fused_update() == B.fused_update()
+    np.testing.assert_array_equal(img_b, img_a)
+    assert obj_b["total"] == obj_a["total"]
+    np.testing.assert_array_equal(B.backprojection(), A.backprojection())
+    A.close()
+    B.close()
+
+
+def test_damaged_and_foreign_files_are_refused(sg, tmp_path):
+    prob = datagen.make_problem("small", 11)
+    A = build(sg, prob)
+    path = tmp_path / "system.bin"
+    A.save_system(str(path))
+    good = path.read_bytes()
+    other = datagen.make_problem("small", 12)
+    B = build(sg, other)
+    img_ref, obj_ref = run(B, other, 5)
+    bad = {}
+    flipped = bytearray(good)
+    flipped[len(good) - 100] ^= 0x10          # a byte of the last array
+    bad["array byte"] = bytes(flipped)
+    flipped = bytearray(good)
+    flipped[40] ^= 0x01                       # a byte of the description
+    bad["header byte"] = bytes(flipped)
+    bad["truncated"] = good[: len(good) // 2]
+    bad["header only"] = good[:64]
+    bad["foreign"] = b"not a system file" * 100
+    bad["empty"] = b""
+    for what, blob in bad.items():
+        p = tmp_path / ("bad_" + what.replace(" ", "_"))
+        p.write_bytes(blob)
+        with pytest.raises(RuntimeError):
+            B.load_system(str(p))
+        print("refused:", what, "-", sg.sgtv_last_error(), flush=True)
+    with pytest.raises(RuntimeError):
+        B.load_system(str(tmp_path / "missing.bin"))
+    # the context still holds its own system and data
+    B.set_init(None)
+    img, obj = run(B, other, 5)
+    np.testing.assert_array_equal(img, img_ref)
+    assert obj["total"] == obj_ref["total"]
+    fresh = sg.Reconstructor()
+    with pytest.raises(RuntimeError):
+        fresh.save_system(str(tmp_path / "none.bin"))
+    fresh.close()
+    A.close()
+    B.close()
+
+
+def test_paper_scale_system_loads_faster_than_it_packs(sg, tmp_path):
+    prob = datagen.make_problem("paper", 1)
+    t = time.perf_counter()
+    A = build(sg, prob)
+    t_pack = time.perf_counter() - t
+    path = str(tmp_path / "paper_system.bin")
+    t = time.perf_counter()
+    A.save_system(path)
+    t_save = time.perf_counter() - t
+    B = sg.Reconstructor()
+    t = time.perf_counter()
+    B.load_system(path)
+    t_load = time.perf_counter() - t
+    size = os.path.getsize(path)
+    print("paper scan: set_system %.2f s, save %.2f s, load %.2f s, file %.2f GB" % (
+        t_pack, t_save, t_load, size / 1e9), flush=True)
+    img_a, obj_a = run(A, prob, 3)
+    img_b, obj_b = run(B, prob, 3)
+    np.testing.assert_array_equal(img_b, img_a)
+    assert obj_b["total"] == obj_a["total"]
+    assert t_load < t_pack
+    A.close()
+    B.close()
+    os.remove(path)
