@@ -174,6 +174,67 @@ def _gen_batch_scan(args):
     return datagen.make_batch_scan(ny, nx, Q, seed=seed)
 
 
+def system_file_times(R, prob, stream):
+    """Save the packed system and load it into a second context: the set-up
+    of a fixed scanner after the first time."""
+    import shutil
+    import tempfile
+    from paper_1601_08201_amd import sgtv
+    tmp = tempfile.mkdtemp(prefix="sgtv_system_")
+    try:
+        if shutil.disk_usage(tmp).free < 1.5 * (16 * prob.nnz + 64 * prob.J):
+            log("system file skipped: not enough space in " + tmp)
+            return {}
+        path = os.path.join(tmp, "system.sys")
+        t0 = time.time()
+        R.save_system(path)
+        t_save = time.time() - t0
+        R2 = sgtv.Reconstructor(device=0, stream=stream.cuda_stream)
+        t0 = time.time()
+        R2.load_system(path)
+        t_load = time.time() - t0
+        R2.close()
+        size = os.path.getsize(path)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    log("system file: %.2f GB saved in %.2fs, loaded in %.3fs" % (size / 1e9, t_save, t_load))
+    return {"save_s": t_save, "load_system_s": t_load, "file_bytes": size}
+
+
+def batch_from_files(B, probs, index, stream, setup):
+    """Save every scan's packed system to a file, then build the batch again
+    from the files (the set-up of a fixed set of scanners after the first
+    time); returns the rebuilt batch, which iterates bit for bit like the
+    packed one, and the set-up times."""
+    import shutil
+    import tempfile
+    from paper_1601_08201_amd import sgtv
+    tmp = tempfile.mkdtemp(prefix="sgtv_systems_")
+    need = sum(16 * p.nnz + 64 * p.J for p in probs)
+    free = shutil.disk_usage(tmp).free
+    if free < 1.5 * need:
+        log("system files skipped: %.1f GB free in %s, %.1f GB needed" % (free / 1e9, tmp, need / 1e9))
+        shutil.rmtree(tmp, ignore_errors=True)
+        return B, setup
+    try:
+        paths = [os.path.join(tmp, "scan%03d.sys" % k) for k in range(len(probs))]
+        t0 = time.time()
+        for k, path in enumerate(paths):
+            B.save_scan(index[k], path)
+        t_save = time.time() - t0
+        size = sum(os.path.getsize(x) for x in paths)
+        B.close()
+        B = sgtv.Batch(stream=stream.cuda_stream)
+        t0 = time.time()
+        for path, p in zip(paths, probs):
+            B.add_system_file(path, p)
+        t_load = time.time() - t0
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    log("system files: saved %.1f GB in %.1fs, batch rebuilt from them in %.2fs" % (size / 1e9, t_save, t_load))
+    return B, dict(setup, from_files_s=t_load, save_s=t_save, file_bytes=size)
+
+
 def batch_main(args):
     """Batch of uneven scans: batched launches (one graph per call, the batch
     schedule) against the same scans iterated one after another, each with its
@@ -198,7 +259,12 @@ def batch_main(args):
     sched = autotune.batch_schedule([(p.I, p.J) for p in probs])
     with cf.ThreadPoolExecutor(8) as ex:
         index = list(ex.map(lambda p: B.add_scan(p, sched), probs))
-    log("batch built in %.1fs (schedule %s)" % (time.time() - t0, sched))
+    t_pack = time.time() - t0
+    log("batch built in %.1fs (schedule %s)" % (t_pack, sched))
+    setup = {"pack_s": t_pack, "from_files_s": None}
+    if not args.no_system_files:
+        B, setup = batch_from_files(B, probs, index, stream, setup)
+        index = list(range(len(probs)))
     B.iterate(args.warmup)
     B.prepare(args.steps)   # graph capture outside the timed region
     torch.cuda.synchronize()
@@ -232,7 +298,7 @@ def batch_main(args):
         nth = host_threads()
         for k in sorted(range(len(probs)), key=lambda k: probs[k].nnz)[:2]:
             p = oracle_problem(probs[k])
-            n_done = 2 * (args.warmup + args.steps)
+            n_done = int(B.objective(index[k])["iter"])   # iterations the scan has run
             f_or, _, _ = oracle_run(p, n_done, nth)
             e = oracle_error(p, B.image(index[k]), f_or)
             err.append(dict(e, scan="%dx%dx%d" % (p.ny, p.nx, p.Q), iterations=n_done))
@@ -275,6 +341,8 @@ def batch_main(args):
                                "call, which waits for the launch",
                        "phase_ms_per_iteration": phases},
         "speedup_vs_sequential": ms_seq / ms_batched,
+        "setup": dict(setup, note="pack_s: the systems packed on the host (8 scans at a time); "
+                                  "from_files_s: the same batch built from the saved packed systems"),
         "batch_iteration_alg_GBs": alg * args.steps / (ms_batched * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": "whole batched iteration",
                      "achieved": alg * args.steps / (ms_batched * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
@@ -347,6 +415,7 @@ def sweep_main(args):
         nth = host_threads()
         for i in (0, len(pairs) - 1):
             g, b = pairs[i]
+            assert int(B.objective(i)["iter"]) == n_total
             f_or, _, _ = oracle_run(p, n_total, nth, w=w, grouping=g, beta=b)
             e = oracle_error(p, B.image(i), f_or, w=w, grouping=g, beta=b)
             err.append(dict(e, grouping=study.GROUPINGS[g], beta=b, iterations=n_total))
@@ -615,6 +684,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-system-files", action="store_true",
+                    help="batch workload: skip saving the packed systems and rebuilding the batch from them")
     ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart", "sweep", "adaptive"],
                     help="scan: the paper-scale scan (default); batch: 64 uneven scans; "
                          "warmstart: learned start vs plain start; sweep: beta sweep of both "
@@ -677,8 +748,12 @@ def main():
     else:
         R.set_schedule(format=0 if args.format == "tiled" else 1)
     t0 = time.time()
-    R.set_problem(prob, storage=args.storage)
-    log("system and data set in %.1fs" % (time.time() - t0))
+    R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val, storage=args.storage)
+    setup = {"set_system_s": time.time() - t0}
+    R.set_data(prob.y, prob.r, prob.beta, prob.rho, prob.sweeps)
+    log("system set in %.2fs, data in %.2fs" % (setup["set_system_s"], time.time() - t0 - setup["set_system_s"]))
+    if not args.no_system_files:
+        setup.update(system_file_times(R, prob, stream))
 
     R.iterate(args.warmup)
     R.prepare(args.steps)   # graph capture outside the timed region
@@ -777,6 +852,8 @@ def main():
                                        + ", valid for the current kernels, builder and schedule"},
         "cpu_baseline": cpu,
         "oracle_error": err,
+        "setup": dict(setup, note="set_system_s: packing on the host and upload; load_system_s: the same "
+                                  "packed system read back from a file into a new context"),
     }
     print(json.dumps(out), flush=True)
     R.close()

@@ -377,6 +377,16 @@ int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t
                         int64_t nnz, const float *w, int64_t w_len, const float *y, const float *r,
                         double beta, double rho, int grouping, const sgtv_schedule *schedule,
                         int mem_kind, int32_t *index);
+/* Add one scan whose system comes from a file that sgtv_save_system (or
+ * sgtv_batch_save_scan) wrote: a tiled system with FP32 values whose
+ * schedule agrees with the batch on waves and variant; grouping and data as
+ * in sgtv_batch_add_scan.  The scan gives bit for bit the results of one
+ * added with the matrix that was saved.  Errors as sgtv_load_system, and
+ * SGTV_EINVAL for a system of another format or value type. */
+int sgtv_batch_add_system_file(sgtv_batch b, const char *path, const float *y, const float *r, double beta,
+                               double rho, int grouping, int mem_kind, int32_t *index);
+/* Write the packed system of scan `scan` to a file, as sgtv_save_system. */
+int sgtv_batch_save_scan(sgtv_batch b, int32_t scan, const char *path);
 int sgtv_batch_size(sgtv_batch b, int32_t *n_scans);
 /* n_iters iterations of every scan in batched launches (graph replay). */
 int sgtv_batch_iterate(sgtv_batch b, int n_iters);

@@ -2826,6 +2826,9 @@ int batch_persistent(sgtv_batch_s *b, int n_iters) {
     return SGTV_OK;
 }
 
+int batch_join(sgtv_batch_s *b, std::unique_ptr<sgtv_ctx_s> own, const float *y, const float *r, double beta,
+               double rho, int grouping, int mem_kind, int32_t *index);
+
 }  // namespace
 
 extern "C" {
@@ -2876,6 +2879,41 @@ int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t
     if (int e = sgtv_set_schedule(c, &sch)) return e;
     if (int e = sgtv_set_system(c, I, ny, nx, Q, row_ptr, col_idx, val, nnz, SGTV_F32, w, w_len, mem_kind))
         return e;
+    return batch_join(b, std::move(own), y, r, beta, rho, grouping, mem_kind, index);
+}
+
+int sgtv_batch_add_system_file(sgtv_batch b, const char *path, const float *y, const float *r, double beta,
+                               double rho, int grouping, int mem_kind, int32_t *index) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    sgtv_ctx c = nullptr;
+    if (int e = sgtv_create(&c, b->device, b->stream)) return e;
+    std::unique_ptr<sgtv_ctx_s> own(c);
+    if (int e = sgtv_load_system(c, path)) return e;
+    if (c->sys->format != SGTV_FORMAT_TILED || c->sys->vt != SGTV_F32)
+        return fail(SGTV_EINVAL, "scans of a batch need a tiled system with FP32 values");
+    return batch_join(b, std::move(own), y, r, beta, rho, grouping, mem_kind, index);
+}
+
+int sgtv_batch_save_scan(sgtv_batch b, int32_t scan, const char *path) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    sgtv_ctx_s *c = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(b->mu);
+        if (scan < 0 || static_cast<size_t>(scan) >= b->scans.size()) return fail(SGTV_EINVAL, "scan out of range");
+        c = b->scans[scan];
+    }
+    return sgtv_save_system(c, path);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Joins a scan whose system is set to the batch: grouping and data, then the
+// check that it shares waves and variant with the scans already there.
+int batch_join(sgtv_batch_s *b, std::unique_ptr<sgtv_ctx_s> own, const float *y, const float *r, double beta,
+               double rho, int grouping, int mem_kind, int32_t *index) {
+    sgtv_ctx_s *c = own.get();
     if (int e = sgtv_set_grouping(c, grouping)) return e;
     if (int e = sgtv_set_data(c, y, r, beta, rho, 1, mem_kind)) return e;
     std::lock_guard<std::mutex> lock(b->mu);
@@ -2895,6 +2933,10 @@ int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t
     if (index) *index = static_cast<int32_t>(b->scans.size() - 1);
     return SGTV_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int sgtv_batch_size(sgtv_batch b, int32_t *n_scans) {
     if (!b || !n_scans) return fail(SGTV_EINVAL, "null argument");

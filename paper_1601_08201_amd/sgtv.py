@@ -114,6 +114,9 @@ def lib():
             "sgtv_batch_destroy": (None, [_P]),
             "sgtv_batch_add_scan": (_I, [_P, _I64, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _I64, _P, _P,
                                          _D, _D, _I, ctypes.POINTER(Schedule), _I, ctypes.POINTER(_I32)]),
+            "sgtv_batch_add_system_file": (_I, [_P, ctypes.c_char_p, _P, _P, _D, _D, _I, _I,
+                                                ctypes.POINTER(_I32)]),
+            "sgtv_batch_save_scan": (_I, [_P, _I32, ctypes.c_char_p]),
             "sgtv_batch_size": (_I, [_P, ctypes.POINTER(_I32)]),
             "sgtv_batch_iterate": (_I, [_P, _I]),
             "sgtv_batch_prepare": (_I, [_P, _I, _I]),
@@ -586,6 +589,18 @@ def sgtv_batch_add_scan(b, I, ny, nx, Q, row_ptr, col_idx, val, y, r, beta, rho,
     return idx.value
 
 
+def sgtv_batch_add_system_file(b, path, y, r, beta, rho, grouping=0):
+    ya, ra = _arg(y, np.float32), _arg(r, np.float32)
+    idx = _I32()
+    _check(lib().sgtv_batch_add_system_file(b, os.fsencode(path), ya[0], ra[0], float(beta), float(rho),
+                                            int(grouping), _kind(ya, ra), ctypes.byref(idx)))
+    return idx.value
+
+
+def sgtv_batch_save_scan(b, scan, path):
+    _check(lib().sgtv_batch_save_scan(b, int(scan), os.fsencode(path)))
+
+
 def sgtv_batch_size(b):
     n = _I32()
     _check(lib().sgtv_batch_size(b, ctypes.byref(n)))
@@ -666,6 +681,18 @@ class Batch:
                                 schedule, w, grouping)
         self._J[i] = prob.ny * prob.nx * prob.Q
         return i
+
+    def add_system_file(self, path, prob, grouping=0, beta=None):
+        """Add a scan whose system a file holds (save_scan or
+        Reconstructor.save_system); data, beta and rho from prob."""
+        i = sgtv_batch_add_system_file(self._b, path, prob.y, prob.r, prob.beta if beta is None else beta,
+                                       prob.rho, grouping)
+        self._J[i] = prob.ny * prob.nx * prob.Q
+        return i
+
+    def save_scan(self, scan, path):
+        sgtv_batch_save_scan(self._b, scan, path)
+        return self
 
     def __len__(self):
         return sgtv_batch_size(self._b)

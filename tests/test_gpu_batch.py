@@ -162,3 +162,34 @@ def test_launch_mode_is_checked(sg):
     B.set_launch("persistent")
     B.iterate(3)          # empty batch: nothing to run
     assert B.launch()[0] == "persistent"
+
+
+def test_batch_from_saved_systems_equals_packed_batch(sg, tmp_path):
+    """Scans added from system files (saved from a packed batch) iterate bit for
+    bit like the packed batch; a file of another value type is refused."""
+    probs = scans()
+    A = sg.Batch()
+    for p in probs:
+        A.add_scan(p, schedule=SCHED)
+    paths = []
+    for i in range(len(probs)):
+        paths.append(str(tmp_path / ("scan%d.sys" % i)))
+        A.save_scan(i, paths[-1])
+    B = sg.Batch()
+    for path, p in zip(paths, probs):
+        B.add_system_file(path, p)
+    A.iterate(15)
+    B.iterate(15)
+    for i in range(len(probs)):
+        np.testing.assert_array_equal(B.image(i), A.image(i))
+        assert B.objective(i) == A.objective(i)
+    R = sg.Reconstructor()
+    R.set_system(probs[0].I, probs[0].ny, probs[0].nx, probs[0].Q, probs[0].rowptr, probs[0].col,
+                 probs[0].val, storage="bf16")
+    R.save_system(str(tmp_path / "bf16.sys"))
+    with pytest.raises(RuntimeError):
+        B.add_system_file(str(tmp_path / "bf16.sys"), probs[0])
+    assert len(B) == len(probs)
+    R.close()
+    A.close()
+    B.close()
