@@ -28,27 +28,38 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(prob, value_bytes, fmt, fused=False):
+def algorithmic_bytes(prob, value_bytes, fmt, fused=False, epilogues=False, full_weights=False):
     """Bytes each kernel must move per launch: every array it needs, touched once.
 
     Tiled format: forward = A (values + indices), x, p out; ratio = p, y, r,
-    ratio out; back = A, ratio, e out; image update = e, g, v, a, sens, H,
-    g out; split = f, v, a in and v, a out; the image and split update in one
-    pass (fused) = e, g, sens, g out, v and a in and out (48 J + 8 S bytes).
-    The sliced-ELL kernels fuse the ratio into the forward pass and the image
-    update into the back pass.
+    ratio out; back = A, ratio, e out; image update = e, g, v, a, sens, g out
+    (and H with full weights; with weights constant per direction H0 comes
+    from a 16-entry table); split = f, v, a in and v, a out; the image and
+    split update in one pass (fused) = e, g, sens, g out, v and a in and out
+    (48 J + 8 S bytes).  With the row-block epilogues the forward launch
+    includes the ratio (A, x, y, r in, ratio out) and the back launch the
+    image update (A, ratio, g, v, a, sens in, g out): the partial sums between
+    them are not part of the count.  The sliced-ELL kernels fuse the ratio
+    into the forward pass and the image update into the back pass.
     """
     I, J, nnz = prob.I, prob.J, prob.nnz
     S = prob.ny * prob.nx
     a = nnz * (value_bytes + 4)
+    h = 4 * J if full_weights else 0
     out = {"split_update": 4 * J + 16 * J + 4 * S + 16 * J + 4 * S}
     if fmt == "tiled":
         out["forward"] = a + 4 * J + 4 * I
         out["ratio"] = 16 * I
         out["back"] = a + 4 * I + 4 * J
-        out["image_update"] = 4 * J + 4 * J + 16 * J + 4 * S + 4 * J + 4 * J + 4 * J
+        out["image_update"] = 4 * J + 4 * J + 16 * J + 4 * S + 4 * J + h + 4 * J
+        if epilogues:
+            del out["ratio"], out["image_update"]
+            out["forward"] = a + 4 * J + 12 * I
+            out["back"] = a + 4 * I + 4 * J + 16 * J + 4 * S + 4 * J + h + 4 * J
         if fused:
-            del out["split_update"], out["image_update"]
+            out.pop("split_update")
+            out.pop("image_update", None)
+            out["back"] = a + 4 * I + 4 * J
             out["update_fused"] = 4 * J + 4 * J + 4 * J + 4 * J + 32 * J + 8 * S
     else:
         out["forward"] = a + 4 * (I + 1) + 4 * J + 12 * I
@@ -684,6 +695,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--epilogues", action="store_true",
+                    help="the ratio and the image update as row-block epilogues of the two products")
     ap.add_argument("--no-system-files", action="store_true",
                     help="batch workload: skip saving the packed systems and rebuilding the batch from them")
     ap.add_argument("--workload", default="scan", choices=["scan", "batch", "warmstart", "sweep", "adaptive"],
@@ -747,6 +760,8 @@ def main():
         log("tuned schedule from the autotuner cache: " + json.dumps(tuned))
     else:
         R.set_schedule(format=0 if args.format == "tiled" else 1)
+    if args.epilogues:
+        R.set_epilogues(True)
     t0 = time.time()
     R.set_system(prob.I, prob.ny, prob.nx, prob.Q, prob.rowptr, prob.col, prob.val, storage=args.storage)
     setup = {"set_system_s": time.time() - t0}
@@ -778,7 +793,7 @@ def main():
     R.set_profiling(False)
     vb = {"f32": 4, "bf16": 2, "f16": 2}[args.storage]
     fused = R.fused_update()[0]
-    alg = algorithmic_bytes(prob, vb, args.format, fused=fused)
+    alg = algorithmic_bytes(prob, vb, args.format, fused=fused, epilogues=args.format == "tiled" and R.epilogues())
     if fused:
         times["update_fused"] = times.pop("image_update")
     kern = {}
@@ -791,7 +806,7 @@ def main():
     achieved = kern[dom]["gbs"]
     log("kernels: " + json.dumps(kern))
     log("schedule: " + json.dumps(R.schedule()) + ", fused image and split update (tile): "
-        + json.dumps(R.fused_update()))
+        + json.dumps(R.fused_update()) + ", row-block epilogues: " + json.dumps(R.epilogues()))
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

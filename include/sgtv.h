@@ -169,6 +169,25 @@ int sgtv_set_graphs(sgtv_ctx ctx, int enable);
 int sgtv_set_fused_update(sgtv_ctx ctx, int enable);
 int sgtv_get_fused_update(sgtv_ctx ctx, int *active, int32_t *tile_x, int32_t *tile_y);
 
+/* Row-block epilogues of the tiled products (Section III: the ratio of the
+ * EM step and the image update follow the two products; default off).  The
+ * workgroup that writes the last slab's partial sums of a row block of A f
+ * computes the ratio y / (A f + r) of its rows in the same launch, and the
+ * one that completes a row block of A^T t the image update of its voxels,
+ * so an iteration is three launches (forward with ratio, back with image
+ * update, split and dual update) instead of five.  The arithmetic and the
+ * order of every sum are those of the separate launches: results are the
+ * same bit for bit.  Off: the separate launches.  The work of a row block
+ * waits for its last slab, so when all row blocks finish together (one wave
+ * of workgroups) the epilogues run on as many CUs as there are row blocks;
+ * on an MI355X they save a little on the smallest scans (9 x 41 x 54:
+ * 0.025 against 0.027 ms per iteration) and lose on larger ones (64^3:
+ * 0.067 against 0.051 ms; 128^3: 0.427 against 0.408 ms).  With the fused
+ * image and split update on, the last sweep's back product runs without its
+ * epilogue. */
+int sgtv_set_epilogues(sgtv_ctx ctx, int enable);
+int sgtv_get_epilogues(sgtv_ctx ctx, int *enabled);
+
 /* Objective and residuals of the current state (FP64 reductions); synchronises. */
 int sgtv_objective(sgtv_ctx ctx, sgtv_report *out);
 

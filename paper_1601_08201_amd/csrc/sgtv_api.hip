@@ -821,6 +821,7 @@ struct System {
     int64_t n_rslices = 0, n_cslices = 0;
     Tiled fwd, back;             // tiled format: A (rows = measurements), A^T (rows = voxels)
     DBuf fpart, bpart;           // per-slab partial sums
+    DBuf fcount, bcount;         // arrival counters of the row-block epilogues (zero between launches)
 
     sgtv::Sell rows() const {
         return {rs_ptr.as<int64_t>(), rs_idx.as<int32_t>(), rs_val.p, nullptr, I, n_rslices};
@@ -892,6 +893,7 @@ struct sgtv_ctx_s {
     // image and split updates in one pass (off by default: slower here, see
     // sgtv_set_fused_update)
     bool fused = false;
+    bool epilogues = false;      // tiled products finish their row blocks (ratio, image update)
     // graph replay of iterate(n)
     bool use_graphs = true;
     hipStream_t cap = nullptr;   // capture stream (own, created on first use)
@@ -1250,6 +1252,18 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
 
 int compute_sensitivity(sgtv_ctx_s *c, System &S, Arena *temp);
 
+// Arrival counters of the tiled products' row-block epilogues, one per row
+// block, cleared here (set-up, never inside a captured graph); every launch
+// leaves them at zero again.
+int alloc_counters(sgtv_ctx_s *c, System &S) {
+    HIP_TRY(S.fcount.alloc(sizeof(uint32_t) * static_cast<size_t>(std::max<int64_t>(S.fwd.map.n_rb, 1))));
+    HIP_TRY(S.bcount.alloc(sizeof(uint32_t) * static_cast<size_t>(std::max<int64_t>(S.back.map.n_rb, 1))));
+    if (counting()) return SGTV_OK;
+    HIP_TRY(hipMemsetAsync(S.fcount.p, 0, S.fcount.bytes, c->stream));
+    HIP_TRY(hipMemsetAsync(S.bcount.p, 0, S.bcount.bytes, c->stream));
+    return SGTV_OK;
+}
+
 // Put a packed system on the device: every buffer is allocated (from the
 // current arena, if any; a counting arena only adds up the bytes) and
 // filled, and the sensitivity s = A^T 1 is computed with the stored values
@@ -1263,6 +1277,7 @@ int upload_system(sgtv_ctx_s *c, Packed &PK, Arena *temp) {
         if (int e = upload_tiled(S.back, PK.back)) return e;
         HIP_TRY(S.fpart.alloc(sizeof(float) * PK.fpart_floats));
         HIP_TRY(S.bpart.alloc(sizeof(float) * PK.bpart_floats));
+        if (int e = alloc_counters(c, S)) return e;
     } else {
         if (S.vt == SGTV_F32) {
             HIP_TRY(upload(S.rs_val, PK.rsv32));
@@ -1357,21 +1372,50 @@ int step(sgtv_ctx_s *c) {
     for (int sw = 0; sw < c->sweeps; ++sw) {
         const float *x = S.vt == SGTV_F32 ? c->f[c->fcur].as<float>() : c->fs.as<float>();
         if (S.format == SGTV_FORMAT_TILED) {
-            {
+            const bool fused_last = sw + 1 == c->sweeps && fused_ok(c);
+            if (c->epilogues) {
+                // forward product and ratio in one launch
                 TimedLaunch t(c, 0);
-                HIP_TRY(sgtv::launch_tiled(S.fwd.map, S.vt, x, S.fpart.as<float>(), c->stream));
-            }
-            {
+                const sgtv::RatioEpilogue E{S.fcount.as<uint32_t>(), c->y.as<float>(), c->r.as<float>(),
+                                            c->ratio.as<float>()};
+                HIP_TRY(sgtv::launch_tiled_ratio(S.fwd.map, S.vt, x, S.fpart.as<float>(), E, c->stream));
+            } else {
+                {
+                    TimedLaunch t(c, 0);
+                    HIP_TRY(sgtv::launch_tiled(S.fwd.map, S.vt, x, S.fpart.as<float>(), c->stream));
+                }
                 TimedLaunch t(c, 3);
                 HIP_TRY(sgtv::launch_ratio_combine(S.fpart.as<float>(), S.fwd.map.ns, S.I, c->y.as<float>(),
                                                    c->r.as<float>(), c->ratio.as<float>(), nullptr, false,
                                                    c->stream, nullptr));
             }
+            if (c->epilogues && !fused_last) {
+                // back product and image update in one launch
+                TimedLaunch t(c, 1);
+                sgtv::UpdateEpilogue E{};
+                E.count = S.bcount.as<uint32_t>();
+                E.scale = scale;
+                E.g = c->f[c->fcur].as<float>();
+                E.g_next = c->f[c->fcur ^ 1].as<float>();
+                E.gs_next = gs_next;
+                E.v = c->v[c->vcur].as<float>();
+                E.a = c->a[c->vcur].as<float>();
+                E.sens = S.sens.as<float>();
+                E.H = S.H.as<float>();
+                E.htab = S.htab.as<float>();
+                E.grid = S.grid;
+                E.wts = w;
+                E.lam = lam;
+                HIP_TRY(sgtv::launch_tiled_update(S.back.map, S.vt, c->ratio.as<float>(), S.bpart.as<float>(), E,
+                                                  c->grouping, c->stream));
+                c->fcur ^= 1;
+                continue;
+            }
             {
                 TimedLaunch t(c, 1);
                 HIP_TRY(sgtv::launch_tiled(S.back.map, S.vt, c->ratio.as<float>(), S.bpart.as<float>(), c->stream));
             }
-            if (sw + 1 == c->sweeps && fused_ok(c)) {
+            if (fused_last) {
                 // last sweep: the image update fused with the split and dual update
                 TimedLaunch t(c, 4);
                 sgtv::FusedUpdate A{};
@@ -1980,6 +2024,7 @@ int sgtv_load_system(sgtv_ctx ctx, const char *path) {
             point_tiled(S.back);
             HIP_TRY(S.fpart.alloc(static_cast<size_t>(m.fpart_bytes)));
             HIP_TRY(S.bpart.alloc(static_cast<size_t>(m.bpart_bytes)));
+            if (int e = alloc_counters(ctx, S)) return e;
         }
         if (int e = compute_sensitivity(ctx, S, nullptr)) return e;
         install_system(ctx, std::move(Sp));
@@ -2221,6 +2266,20 @@ int sgtv_set_fused_update(sgtv_ctx ctx, int enable) {
     return SGTV_OK;
 }
 
+int sgtv_set_epilogues(sgtv_ctx ctx, int enable) {
+    if (!ctx) return fail(SGTV_EINVAL, "null context");
+    DeviceGuard g(ctx->device);
+    drop_graphs(ctx);
+    ctx->epilogues = enable != 0;
+    return SGTV_OK;
+}
+
+int sgtv_get_epilogues(sgtv_ctx ctx, int *enabled) {
+    if (!ctx || !enabled) return fail(SGTV_EINVAL, "null argument");
+    *enabled = ctx->epilogues ? 1 : 0;
+    return SGTV_OK;
+}
+
 int sgtv_get_fused_update(sgtv_ctx ctx, int *active, int32_t *tile_x, int32_t *tile_y) {
     if (!ctx || !active) return fail(SGTV_EINVAL, "null argument");
     *active = ctx->sys ? (fused_ok(ctx) ? 1 : 0) : (ctx->fused ? 1 : 0);
@@ -2438,7 +2497,7 @@ int sgtv_device_bytes(sgtv_ctx ctx, int64_t *bytes) {
         for (const DBuf *d : {&S.rs_ptr, &S.rs_idx, &S.rs_val, &S.cs_ptr, &S.cs_idx, &S.cs_val, &S.colscale,
                               &S.sens, &S.H, &S.htab, &S.wbuf, &S.fpart, &S.bpart, &S.fwd.pk, &S.fwd.val,
                               &S.fwd.goff, &S.fwd.poff, &S.fwd.slot, &S.back.pk, &S.back.val, &S.back.goff,
-                              &S.back.poff, &S.back.slot})
+                              &S.back.poff, &S.back.slot, &S.fcount, &S.bcount})
             add(d);
     }
     *bytes = b;

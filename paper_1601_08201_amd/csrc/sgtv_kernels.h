@@ -161,6 +161,32 @@ hipError_t launch_voxel_batch(const BatchBlock *blocks, int64_t n_blocks, const 
 hipError_t launch_split_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,
                               int fcur, int vcur, hipStream_t st);
 hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st);
+
+// A product whose row blocks are finished by the workgroup that completes
+// them (the last of the row block's slabs to arrive at its counter): the
+// forward product then computes the ratio of its rows, the back product the
+// image update of its rows (voxels), with the arithmetic of
+// launch_ratio_combine and launch_voxel_update.  count: n_rb counters, zero
+// before the launch and again after it.
+struct RatioEpilogue {
+    uint32_t *count;
+    const float *y, *r;
+    float *ratio;
+};
+struct UpdateEpilogue {
+    uint32_t *count;
+    const float *scale;       // per-column scale of 16-bit values (nullptr: FP32)
+    const float *g;           // image f^k
+    float *g_next, *gs_next;  // new image; its scaled copy for 16-bit values (or nullptr)
+    const float *v, *a, *sens, *H, *htab;
+    Grid grid;
+    Weights wts;
+    float lam;
+};
+hipError_t launch_tiled_ratio(const TileMap &M, int vt, const float *x, float *part, const RatioEpilogue &E,
+                              hipStream_t st);
+hipError_t launch_tiled_update(const TileMap &M, int vt, const float *x, float *part, const UpdateEpilogue &E,
+                               int grouping, hipStream_t st);
 hipError_t launch_ratio_combine(const float *part, int ns, int64_t n, const float *y,
                                 const float *r, float *ratio, double *partials, bool objective,
                                 hipStream_t st, int64_t *n_partials);

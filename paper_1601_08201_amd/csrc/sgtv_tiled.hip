@@ -474,29 +474,130 @@ __global__ __launch_bounds__(kBlock) void k_back_combine(const float *__restrict
     }
 }
 
+// Image update of voxel j from the back-product partial sums (ns slabs of J).
 // H0 comes from the array H (full weights) or, for weights constant per
 // direction, from the 16-entry table htab by neighbour pattern (the same
 // values; the J-float array is not read).
+template <int GROUPING, bool WFULL>
+__device__ __forceinline__ void voxel_update_elem(int64_t j, const float *__restrict__ part, int ns,
+                                                  const float *__restrict__ scale, const float *__restrict__ g,
+                                                  float *__restrict__ g_next, float *__restrict__ gs_next,
+                                                  const float *__restrict__ v, const float *__restrict__ a,
+                                                  const float *__restrict__ sens, const float *__restrict__ H,
+                                                  const float *__restrict__ htab, const Grid &grid,
+                                                  const Weights &wts, float lam) {
+    const int64_t n = grid.J;
+    auto e_of = [&]() {
+        float e = part[j];
+        for (int k = 1; k < ns; ++k) e += part[static_cast<int64_t>(k) * n + j];
+        return scale ? e * scale[j] : e;
+    };
+    const VoxelPos P = voxel_pos(j, grid);
+    auto h_of = [&]() { return WFULL ? H[j] : htab[neighbour_mask(grid, P.iy, P.ix)]; };
+    const float gnew = voxel_update_at<GROUPING, WFULL>(j, P, e_of, g, v, a, sens, h_of, grid, wts, lam);
+    g_next[j] = gnew;
+    if (gs_next) gs_next[j] = gnew * scale[j];
+}
+
 template <int GROUPING, bool WFULL>
 __global__ __launch_bounds__(kBlock) void k_voxel_update(
     const float *__restrict__ part, int ns, const float *__restrict__ scale,
     const float *__restrict__ g, float *__restrict__ g_next, float *__restrict__ gs_next,
     const float *__restrict__ v, const float *__restrict__ a, const float *__restrict__ sens,
     const float *__restrict__ H, const float *__restrict__ htab, Grid grid, Weights wts, float lam) {
-    const int64_t n = grid.J;
-    for (int64_t j = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x; j < n;
-         j += static_cast<int64_t>(gridDim.x) * kBlock) {
-        auto e_of = [&]() {
-            float e = part[j];
-            for (int k = 1; k < ns; ++k) e += part[static_cast<int64_t>(k) * n + j];
-            return scale ? e * scale[j] : e;
-        };
-        const VoxelPos P = voxel_pos(j, grid);
-        auto h_of = [&]() { return WFULL ? H[j] : htab[neighbour_mask(grid, P.iy, P.ix)]; };
-        const float gnew = voxel_update_at<GROUPING, WFULL>(j, P, e_of, g, v, a, sens, h_of, grid, wts, lam);
-        g_next[j] = gnew;
-        if (gs_next) gs_next[j] = gnew * scale[j];
+    for (int64_t j = static_cast<int64_t>(xcd_block()) * kBlock + threadIdx.x; j < grid.J;
+         j += static_cast<int64_t>(gridDim.x) * kBlock)
+        voxel_update_elem<GROUPING, WFULL>(j, part, ns, scale, g, g_next, gs_next, v, a, sens, H, htab, grid,
+                                           wts, lam);
+}
+
+// ---------------------------------------------------------------- row-block epilogues
+// The workgroup of one (row block, slab) tile arrives at its row block's
+// counter once its partial sums are written; the last of the ns arrivals
+// finishes the row block.  Each wave first waits for its own stores, then one
+// thread adds the arrival with release semantics at agent scope (the
+// workgroup's writes, held in this XCD's L2, become visible device-wide); the
+// last arrival then acquires at agent scope (the other slabs' writes become
+// visible here) and resets the counter for the next launch.  No workgroup
+// waits for another, so the epilogue cannot stall the launch.  flag: one LDS
+// word that no thread reads any more.
+__device__ __forceinline__ bool last_slab(uint32_t *count, int ns, int *flag) {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t old = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const bool last = old + 1 == static_cast<uint32_t>(ns);
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        *flag = last;
     }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// Forward product, then the ratio y / (A f + r) of the row block's rows (the
+// slab sums added in slab order, as launch_ratio_combine).  vec: every
+// array 16-byte aligned and n_rows a multiple of 4 (four rows per thread).
+template <int VT, int MODE>
+__global__ __launch_bounds__(1024) void k_tiled_ratio(TileMap M, const int32_t *__restrict__ pk,
+                                                      const typename Code<VT>::T *__restrict__ val,
+                                                      const int32_t *__restrict__ goff,
+                                                      const float *__restrict__ x, float *part,
+                                                      RatioEpilogue E, int vec) {
+    extern __shared__ float lds[];
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
+    const int64_t rb = blockIdx.x / M.ns;
+    if (!last_slab(E.count + rb, M.ns, reinterpret_cast<int *>(lds))) return;
+    const int64_t rows = static_cast<int64_t>(M.waves) * M.rw, row0 = rb * rows;
+    const int64_t end = row0 + rows < M.n_rows ? row0 + rows : M.n_rows;
+    const int64_t n = M.n_rows;
+    if (vec) {
+        const v4f *p4 = reinterpret_cast<const v4f *>(part);
+        for (int64_t i = row0 / 4 + threadIdx.x; i < end / 4; i += blockDim.x) {
+            const v4f ri = reinterpret_cast<const v4f *>(E.r)[i];
+            const v4f yi = reinterpret_cast<const v4f *>(E.y)[i];
+            v4f acc = p4[i];
+            for (int k = 1; k < M.ns; ++k) {
+                const v4f t = p4[static_cast<int64_t>(k) * (n / 4) + i];
+                acc.x += t.x;
+                acc.y += t.y;
+                acc.z += t.z;
+                acc.w += t.w;
+            }
+            v4f q;
+            q.x = yi.x / (acc.x + ri.x);
+            q.y = yi.y / (acc.y + ri.y);
+            q.z = yi.z / (acc.z + ri.z);
+            q.w = yi.w / (acc.w + ri.w);
+            reinterpret_cast<v4f *>(E.ratio)[i] = q;
+        }
+    } else {
+        for (int64_t i = row0 + threadIdx.x; i < end; i += blockDim.x) {
+            float acc = part[i];
+            for (int k = 1; k < M.ns; ++k) acc += part[static_cast<int64_t>(k) * n + i];
+            E.ratio[i] = E.y[i] / (acc + E.r[i]);
+        }
+    }
+}
+
+// Back product, then the image update of the row block's voxels.
+template <int VT, int MODE, int GROUPING, bool WFULL>
+__global__ __launch_bounds__(1024) void k_tiled_update(TileMap M, const int32_t *__restrict__ pk,
+                                                       const typename Code<VT>::T *__restrict__ val,
+                                                       const int32_t *__restrict__ goff,
+                                                       const float *__restrict__ x, float *part,
+                                                       UpdateEpilogue E) {
+    extern __shared__ float lds[];
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
+    const int64_t rb = blockIdx.x / M.ns;
+    if (!last_slab(E.count + rb, M.ns, reinterpret_cast<int *>(lds))) return;
+    const int64_t rows = static_cast<int64_t>(M.waves) * M.rw, row0 = rb * rows;
+    const int64_t end = row0 + rows < M.n_rows ? row0 + rows : M.n_rows;
+    for (int64_t j = row0 + threadIdx.x; j < end; j += blockDim.x)
+        voxel_update_elem<GROUPING, WFULL>(j, part, M.ns, E.scale, E.g, E.g_next, E.gs_next, E.v, E.a, E.sens,
+                                           E.H, E.htab, E.grid, E.wts, E.lam);
 }
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -511,35 +612,78 @@ static unsigned stride_blocks(int64_t n) {
 // Largest dynamic LDS of one workgroup on gfx950.
 constexpr int kMaxLds = 163840;
 
-template <int VT, int MODE>
-static hipError_t launch_tiled_t(const TileMap &M, const float *x, float *part, hipStream_t st) {
+// Raises a kernel's dynamic-LDS limit once (outside any graph capture that
+// may follow: the first launch of a context is never captured); the
+// initialisation of a function-local static runs once even when several
+// threads launch at the same time.
+template <auto KERN>
+static hipError_t raise_lds() {
+    static const hipError_t raised =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(KERN), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    return raised;
+}
+
+// The tiled product's launch: epilogue 0 none, 1 ratio, 2 image update (with
+// its grouping and weights as template arguments).
+template <int VT, int MODE, int EPI, int GROUPING, bool WFULL>
+static hipError_t launch_tiled_t(const TileMap &M, const float *x, float *part, const RatioEpilogue *R,
+                                 const UpdateEpilogue *U, hipStream_t st) {
+    typedef typename Code<VT>::T T;
+    const dim3 grid(static_cast<unsigned>(M.n_rb * M.ns)), block(static_cast<unsigned>(M.waves * kWave));
     const size_t lds = M.lds_bytes();
-    // raise the kernel's dynamic-LDS limit once (outside any graph capture
-    // that may follow: the first launch of a context is never captured); the
-    // initialisation of a function-local static runs once even when several
-    // threads launch at the same time
-    static const hipError_t raised = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&k_tiled<VT, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (raised != hipSuccess) return raised;
-    hipLaunchKernelGGL((k_tiled<VT, MODE>), dim3(static_cast<unsigned>(M.n_rb * M.ns)),
-                       dim3(static_cast<unsigned>(M.waves * kWave)), lds, st, M, M.pk,
-                       static_cast<const typename Code<VT>::T *>(M.val), M.goff, x, part);
+    const T *val = static_cast<const T *>(M.val);
+    if (EPI == 0) {
+        if (hipError_t e = raise_lds<&k_tiled<VT, MODE>>()) return e;
+        hipLaunchKernelGGL((k_tiled<VT, MODE>), grid, block, lds, st, M, M.pk, val, M.goff, x, part);
+    } else if (EPI == 1) {
+        const auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+        const int vec = M.n_rows % 4 == 0 && al(part) && al(R->y) && al(R->r) && al(R->ratio);
+        if (hipError_t e = raise_lds<&k_tiled_ratio<VT, MODE>>()) return e;
+        hipLaunchKernelGGL((k_tiled_ratio<VT, MODE>), grid, block, lds, st, M, M.pk, val, M.goff, x, part, *R,
+                           vec);
+    } else {
+        if (hipError_t e = raise_lds<&k_tiled_update<VT, MODE, GROUPING, WFULL>>()) return e;
+        hipLaunchKernelGGL((k_tiled_update<VT, MODE, GROUPING, WFULL>), grid, block, lds, st, M, M.pk, val,
+                           M.goff, x, part, *U);
+    }
     return hipGetLastError();
 }
 
-template <int VT>
-static hipError_t launch_tiled_v(const TileMap &M, const float *x, float *part, hipStream_t st) {
+template <int VT, int EPI, int GROUPING, bool WFULL>
+static hipError_t launch_tiled_v(const TileMap &M, const float *x, float *part, const RatioEpilogue *R,
+                                 const UpdateEpilogue *U, hipStream_t st) {
     const bool fits = M.cb <= kXPrefetch * 4 * M.waves * kWave;
-    if (M.variant == 1) return launch_tiled_t<VT, 1>(M, x, part, st);
-    if (M.variant == 2 && fits) return launch_tiled_t<VT, 2>(M, x, part, st);
-    return launch_tiled_t<VT, 0>(M, x, part, st);
+    if (M.variant == 1) return launch_tiled_t<VT, 1, EPI, GROUPING, WFULL>(M, x, part, R, U, st);
+    if (M.variant == 2 && fits) return launch_tiled_t<VT, 2, EPI, GROUPING, WFULL>(M, x, part, R, U, st);
+    return launch_tiled_t<VT, 0, EPI, GROUPING, WFULL>(M, x, part, R, U, st);
+}
+
+template <int EPI, int GROUPING, bool WFULL>
+static hipError_t launch_tiled_e(const TileMap &M, int vt, const float *x, float *part, const RatioEpilogue *R,
+                                 const UpdateEpilogue *U, hipStream_t st) {
+    if (M.n_rb * M.ns == 0) return hipSuccess;
+    if (vt == 0) return launch_tiled_v<0, EPI, GROUPING, WFULL>(M, x, part, R, U, st);
+    if (vt == 1) return launch_tiled_v<1, EPI, GROUPING, WFULL>(M, x, part, R, U, st);
+    return launch_tiled_v<2, EPI, GROUPING, WFULL>(M, x, part, R, U, st);
 }
 
 hipError_t launch_tiled(const TileMap &M, int vt, const float *x, float *part, hipStream_t st) {
-    if (M.n_rb * M.ns == 0) return hipSuccess;
-    if (vt == 0) return launch_tiled_v<0>(M, x, part, st);
-    if (vt == 1) return launch_tiled_v<1>(M, x, part, st);
-    return launch_tiled_v<2>(M, x, part, st);
+    return launch_tiled_e<0, 0, false>(M, vt, x, part, nullptr, nullptr, st);
+}
+
+hipError_t launch_tiled_ratio(const TileMap &M, int vt, const float *x, float *part, const RatioEpilogue &E,
+                              hipStream_t st) {
+    return launch_tiled_e<1, 0, false>(M, vt, x, part, &E, nullptr, st);
+}
+
+hipError_t launch_tiled_update(const TileMap &M, int vt, const float *x, float *part, const UpdateEpilogue &E,
+                               int grouping, hipStream_t st) {
+    const bool wf = E.wts.full != nullptr;
+    if (grouping == 0)
+        return wf ? launch_tiled_e<2, 0, true>(M, vt, x, part, nullptr, &E, st)
+                  : launch_tiled_e<2, 0, false>(M, vt, x, part, nullptr, &E, st);
+    return wf ? launch_tiled_e<2, 1, true>(M, vt, x, part, nullptr, &E, st)
+              : launch_tiled_e<2, 1, false>(M, vt, x, part, nullptr, &E, st);
 }
 
 template <int MODE>

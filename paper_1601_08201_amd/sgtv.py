@@ -107,6 +107,8 @@ def lib():
             "sgtv_backprojection": (_I, [_P, _P, _I]),
             "sgtv_backprojection_noalloc": (_I, [_P, _P, _I]),
             "sgtv_set_fused_update": (_I, [_P, _I]),
+            "sgtv_set_epilogues": (_I, [_P, _I]),
+            "sgtv_get_epilogues": (_I, [_P, ctypes.POINTER(_I)]),
             "sgtv_get_fused_update": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
             "sgtv_set_profiling": (_I, [_P, _I]),
             "sgtv_set_graphs": (_I, [_P, _I]),
@@ -386,6 +388,16 @@ def sgtv_backprojection_noalloc(ctx, out=None):
     return out
 
 
+def sgtv_set_epilogues(ctx, enable=True):
+    _check(lib().sgtv_set_epilogues(ctx, 1 if enable else 0))
+
+
+def sgtv_get_epilogues(ctx):
+    e = _I()
+    _check(lib().sgtv_get_epilogues(ctx, ctypes.byref(e)))
+    return bool(e.value)
+
+
 def sgtv_set_fused_update(ctx, enable=True):
     _check(lib().sgtv_set_fused_update(ctx, 1 if enable else 0))
 
@@ -544,6 +556,13 @@ class Reconstructor:
 
     def fused_update(self):
         return sgtv_get_fused_update(self._ctx)
+
+    def set_epilogues(self, enable=True):
+        sgtv_set_epilogues(self._ctx, enable)
+        return self
+
+    def epilogues(self):
+        return sgtv_get_epilogues(self._ctx)
 
     def schedule(self):
         return sgtv_get_schedule(self._ctx)
