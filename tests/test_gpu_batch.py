@@ -193,3 +193,36 @@ def test_batch_from_saved_systems_equals_packed_batch(sg, tmp_path):
     R.close()
     A.close()
     B.close()
+
+
+def test_batch_of_the_64_scan_workload_matches_single_runs_and_oracle(sg):
+    """The schedule the 64-scan benchmark batch uses (the batch rule over all
+    64 shapes: 1024 rows per wave, automatic 16380-column blocks and slabs) on
+    real scans of that workload: its three smallest scans (32 x 32 grids) and
+    one 64 x 64 x 128 scan in one batch equal their single-scan runs with the
+    same schedule bit for bit, and the two smallest the FP64 oracle at 1e-5."""
+    from paper_1601_08201_amd import autotune
+    shapes = datagen.batch_shapes(64, 300)
+    sched = autotune.batch_schedule([(ny * nx * Q // 2, ny * nx * Q) for ny, nx, Q in shapes])
+    assert sched["fwd_rows_per_wave"] == 1024
+    order = sorted(range(len(shapes)), key=lambda k: shapes[k][0] * shapes[k][1] * shapes[k][2])
+    picks = order[:3] + [next(k for k in order if shapes[k] == (64, 64, 128))]
+    probs = [datagen.make_batch_scan(*shapes[k], seed=300 + k) for k in picks]
+    B = sg.Batch()
+    for p in probs:
+        B.add_scan(p, schedule=sched)
+    B.iterate(25)
+    for i, p in enumerate(probs):
+        R = sg.Reconstructor()
+        R.set_schedule(format=0, **sched)
+        R.set_problem(p)
+        R.iterate(25)
+        np.testing.assert_array_equal(B.image(i), R.image())
+        assert B.objective(i) == R.objective()
+        R.close()
+        if i < 2:
+            f_o = oracle.admm(p, 25, report=False)[0]
+            err = np.linalg.norm(B.image(i) - f_o) / np.linalg.norm(f_o)
+            print("scan", shapes[picks[i]], "rel_l2 vs oracle", err, flush=True)
+            assert err <= 1e-5
+    B.close()
