@@ -267,11 +267,14 @@ def batch_main(args):
     stream = torch.cuda.current_stream()
     B = sgtv.Batch(stream=stream.cuda_stream)
     t0 = time.time()
-    sched = autotune.batch_schedule([(p.I, p.J) for p in probs])
+    sched = autotune.cached_batch_schedule(probs)
+    sched_source = "timed by the batch autotuner (cache)" if sched else "batch rule"
+    if not sched:
+        sched = autotune.batch_schedule([(p.I, p.J) for p in probs])
     with cf.ThreadPoolExecutor(8) as ex:
         index = list(ex.map(lambda p: B.add_scan(p, sched), probs))
     t_pack = time.time() - t0
-    log("batch built in %.1fs (schedule %s)" % (t_pack, sched))
+    log("batch built in %.1fs (schedule %s, %s)" % (t_pack, sched, sched_source))
     setup = {"pack_s": t_pack, "from_files_s": None}
     if not args.no_system_files:
         B, setup = batch_from_files(B, probs, index, stream, setup)
@@ -352,6 +355,7 @@ def batch_main(args):
                                "call, which waits for the launch",
                        "phase_ms_per_iteration": phases},
         "speedup_vs_sequential": ms_seq / ms_batched,
+        "schedule": dict(sched, source=sched_source),
         "setup": dict(setup, note="pack_s: the systems packed on the host (8 scans at a time); "
                                   "from_files_s: the same batch built from the saved packed systems"),
         "batch_iteration_alg_GBs": alg * args.steps / (ms_batched * 1e-3) / 1e9,

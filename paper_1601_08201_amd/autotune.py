@@ -87,6 +87,69 @@ def batch_schedule(sizes, waves=16, min_tiles=1024):
     return dict(fwd_rows_per_wave=rw, back_rows_per_wave=rw)
 
 
+def batch_key(probs):
+    """Cache key of a batch: its scans' shapes and entry counts, in order."""
+    import hashlib
+    desc = ";".join(shape_key(p.I, p.ny, p.nx, p.Q, p.nnz) for p in probs)
+    return "batch%d_%s" % (len(probs), hashlib.sha1(desc.encode()).hexdigest()[:16])
+
+
+def batch_candidates(sizes, waves=16):
+    """Schedules the batch tuner times: the rule's choice and the two next
+    shorter tile heights (column blocks and slabs automatic per scan)."""
+    rule = batch_schedule(sizes, waves)["fwd_rows_per_wave"]
+    out = []
+    for rw in (rule, rule // 2, rule // 4):
+        if rw >= 64:
+            out.append(dict(fwd_rows_per_wave=rw, back_rows_per_wave=rw))
+    return out
+
+
+def tune_batch(probs, reps=5, threads=8, log=None, cache_path=CACHE_PATH, stream=None):
+    """Time the batch (graph replay of `reps` iterations after 2 warm-up
+    iterations) under each candidate schedule and keep the fastest; the result
+    is cached under batch_key(probs)."""
+    import concurrent.futures as cf
+    import torch
+    sizes = [(p.I, p.J) for p in probs]
+    report = []
+    t0 = time.time()
+    for sched in batch_candidates(sizes):
+        B = sgtv.Batch(stream=stream)
+        tb = time.time()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda p: B.add_scan(p, sched), probs))
+        build = time.time() - tb
+        B.iterate(2)
+        B.prepare(reps)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st = torch.cuda.current_stream()
+        a.record(st)
+        B.iterate(reps)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        B.close()
+        report.append(dict(schedule=sched, ms_per_iteration=ms, build_seconds=build))
+        if log:
+            log("batch autotune %s: %.3f ms per iteration (built in %.1fs)" % (json.dumps(sched), ms, build))
+    best = min(report, key=lambda r: r["ms_per_iteration"])
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[batch_key(probs)] = dict(schedule=best["schedule"], ms_per_iteration=best["ms_per_iteration"],
+                                       candidates=report, seconds=time.time() - t0)
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+    return best["schedule"], report
+
+
+def cached_batch_schedule(probs, path=CACHE_PATH):
+    """The timed schedule of this batch, or None (then the batch rule applies)."""
+    rec = load_cache(path).get(batch_key(probs))
+    return rec["schedule"] if rec else None
+
+
 def _time_schedule(prob, sched, reps):
     R = sgtv.Reconstructor()
     R.set_schedule(format=0, **sched)
@@ -155,6 +218,11 @@ def cached_schedule(prob, path=CACHE_PATH):
     return rec["schedule"] if rec else None
 
 
+def _batch_scan(ny, nx, Q, seed):
+    from . import datagen
+    return datagen.make_batch_scan(ny, nx, Q, seed=seed)
+
+
 def _main():
     import argparse
     import sys
@@ -165,8 +233,19 @@ def _main():
     ap.add_argument("--out", default=CACHE_PATH)
     ap.add_argument("--candidates", type=int, default=8)
     ap.add_argument("--batch-scans", type=int, default=64)
+    ap.add_argument("--tune-batch", action="store_true",
+                    help="time the schedules of the whole batch workload (its scans, seeds 300 + k) instead")
     args = ap.parse_args()
     log = lambda m: print("[autotune] " + m, file=sys.stderr, flush=True)
+    if args.tune_batch:
+        import multiprocessing as mp
+        shapes = datagen.batch_shapes(args.batch_scans, 300)
+        with mp.get_context("fork").Pool(min(16, len(shapes))) as pool:
+            probs = pool.starmap(_batch_scan, [(ny, nx, Q, 300 + k) for k, (ny, nx, Q) in enumerate(shapes)])
+        log("generated %d scans" % len(probs))
+        best, _ = tune_batch(probs, log=log, cache_path=args.out)
+        log("batch of %d scans: best %s" % (len(probs), json.dumps(best)))
+        return
     probs = []
     for w in args.workloads.split(","):
         if w in ("paper", "warmstart", "small"):

@@ -32,3 +32,27 @@ def test_batch_schedule_prefers_long_tiles_for_big_batches():
     tiles = lambda r: sum(-(-I // (16 * r)) * autotune._auto_slabs(J) for I, J in mid)
     assert tiles(rw) >= 256 and (rw == 1024 or tiles(2 * rw) < 256 or
                                  sum(-(-J // (32 * rw)) * autotune._auto_slabs(I) for I, J in mid) < 256)
+
+
+def test_batch_tuner_candidates_and_cache_key(tmp_path):
+    """The batch tuner times the rule's tile height and the two next shorter
+    ones; its cache key depends on every scan's shape and entry count and on
+    their order, and a cached entry is returned for the same batch only."""
+    import json
+    from types import SimpleNamespace as NS
+    from paper_1601_08201_amd import autotune
+    sizes = [(32768, 65536)] * 64
+    cands = autotune.batch_candidates(sizes)
+    rule = autotune.batch_schedule(sizes)["fwd_rows_per_wave"]
+    assert [c["fwd_rows_per_wave"] for c in cands] == [r for r in (rule, rule // 2, rule // 4) if r >= 64]
+    assert all(c["fwd_rows_per_wave"] == c["back_rows_per_wave"] for c in cands)
+    a = [NS(I=100, ny=4, nx=5, Q=6, nnz=1000), NS(I=200, ny=8, nx=5, Q=6, nnz=2000)]
+    b = list(reversed(a))
+    c = [a[0], NS(I=200, ny=8, nx=5, Q=6, nnz=2001)]
+    keys = {autotune.batch_key(x) for x in (a, b, c)}
+    assert len(keys) == 3
+    path = str(tmp_path / "cache.json")
+    with open(path, "w") as fh:
+        json.dump({autotune.batch_key(a): {"schedule": {"fwd_rows_per_wave": 512, "back_rows_per_wave": 512}}}, fh)
+    assert autotune.cached_batch_schedule(a, path) == {"fwd_rows_per_wave": 512, "back_rows_per_wave": 512}
+    assert autotune.cached_batch_schedule(b, path) is None
