@@ -374,9 +374,10 @@ int sgtv_kernel_times(sgtv_ctx ctx, double *ms, int64_t *counts);
  * of the whole batch is five launches (forward products of every scan, the
  * ratios, the backprojections, the image updates, the split and dual
  * updates), each covering all scans; sgtv_batch_iterate captures the n
- * iterations into one HIP graph and launches it once.  Scans use FP32
- * values and one surrogate sweep; each scan may have its own grid, matrix,
- * weights, grouping, data, beta, rho and schedule.  A scan
+ * iterations into one HIP graph and launches it once.  All scans of a batch
+ * store their matrix values in one type (FP32 unless sgtv_batch_set_storage
+ * says otherwise) and use one surrogate sweep; each scan may have its own
+ * grid, matrix, weights, grouping, data, beta, rho and schedule.  A scan
  * of a batch gives bit-identical results to the same scan in its own context
  * with the same schedule.
  */
@@ -384,6 +385,11 @@ typedef struct sgtv_batch_s *sgtv_batch;
 
 int sgtv_batch_create(sgtv_batch *out, int device, void *hip_stream);
 void sgtv_batch_destroy(sgtv_batch b);
+/* Value type of the matrices of every scan added afterwards: SGTV_F32
+ * (default), SGTV_BF16 or SGTV_F16 with a per-column FP32 scale, as in
+ * sgtv_set_system.  Only before the first scan is added (SGTV_ESTATE after);
+ * the persistent launch takes FP32 batches only. */
+int sgtv_batch_set_storage(sgtv_batch b, int storage_dtype);
 /* Add one scan (arguments as sgtv_set_system / sgtv_set_grouping /
  * sgtv_set_data; schedule NULL: automatic; schedules of one batch must agree
  * on waves and variant).  The new scan starts from the uniform image; index

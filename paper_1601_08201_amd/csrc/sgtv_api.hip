@@ -2666,6 +2666,7 @@ struct sgtv_batch_s {
     int64_t n_tiles_f = 0, n_tiles_b = 0, n_rblocks = 0, n_vblocks = 0, n_sblocks = 0;
     size_t lds_f = 0, lds_b = 0;
     int waves = 16, variant = 1;
+    int storage = SGTV_F32;           // value type of every scan's matrix (one product launch per type)
     int fcur = 0, vcur = 0;
     hipStream_t cap = nullptr;
     std::vector<sgtv_ctx_s::Graph> graphs;
@@ -2711,8 +2712,9 @@ int batch_tables(sgtv_batch_s *b) {
         const System &S = *c->sys;
         mf[i] = S.fwd.map;
         mb[i] = S.back.map;
-        xf0[i] = c->f[0].as<float>();
-        xf1[i] = c->f[1].as<float>();
+        // the forward product reads the image, or its scaled copy for 16-bit values
+        xf0[i] = S.vt == SGTV_F32 ? c->f[0].as<float>() : c->fs.as<float>();
+        xf1[i] = S.vt == SGTV_F32 ? c->f[1].as<float>() : c->fs.as<float>();
         xb[i] = c->ratio.as<float>();
         pf[i] = S.fpart.as<float>();
         pb[i] = S.bpart.as<float>();
@@ -2731,6 +2733,9 @@ int batch_tables(sgtv_batch_s *b) {
         }
         d.sens = S.sens.as<float>();
         d.H = S.H.as<float>();
+        d.htab = S.htab.as<float>();
+        d.scale = S.vt == SGTV_F32 ? nullptr : S.colscale.as<float>();
+        d.fs = S.vt == SGTV_F32 ? nullptr : c->fs.as<float>();
         d.grid = S.grid;
         d.wts = S.weights();
         d.grouping = c->grouping;
@@ -2787,12 +2792,12 @@ int batch_step(sgtv_batch_s *b) {
     hipStream_t st = b->stream;
     HIP_TRY(sgtv::launch_tiled_batch(b->tiles_f.as<sgtv::BatchTile>(), b->n_tiles_f,
                                      b->maps_f.as<sgtv::TileMap>(), b->xs_f[b->fcur].as<const float *>(),
-                                     b->parts_f.as<float *>(), b->waves, b->lds_f, b->variant, st));
+                                     b->parts_f.as<float *>(), b->waves, b->lds_f, b->variant, b->storage, st));
     HIP_TRY(sgtv::launch_ratio_batch(b->rblocks.as<sgtv::BatchBlock>(), b->n_rblocks,
                                      b->scandev.as<sgtv::ScanDev>(), st));
     HIP_TRY(sgtv::launch_tiled_batch(b->tiles_b.as<sgtv::BatchTile>(), b->n_tiles_b,
                                      b->maps_b.as<sgtv::TileMap>(), b->xs_b.as<const float *>(),
-                                     b->parts_b.as<float *>(), b->waves, b->lds_b, b->variant, st));
+                                     b->parts_b.as<float *>(), b->waves, b->lds_b, b->variant, b->storage, st));
     HIP_TRY(sgtv::launch_voxel_batch(b->vblocks.as<sgtv::BatchBlock>(), b->n_vblocks,
                                      b->scandev.as<sgtv::ScanDev>(), b->fcur, b->vcur, st));
     b->fcur ^= 1;
@@ -2819,6 +2824,7 @@ constexpr double kBarrierLimitSeconds = 2.0;
 // n_iters iterations of every scan in cooperative launches of the persistent
 // kernel; waits for them and reports a barrier that timed out.
 int batch_persistent(sgtv_batch_s *b, int n_iters) {
+    if (b->storage != SGTV_F32) return fail(SGTV_EINVAL, "the persistent launch runs batches of FP32 values only");
     if (b->dirty)
         if (int e = batch_tables(b)) return e;
     if (b->waves % 4 != 0)
@@ -2936,7 +2942,7 @@ int sgtv_batch_add_scan(sgtv_batch b, int64_t I, int32_t ny, int32_t nx, int32_t
     if (schedule) sch = *schedule;
     sch.format = SGTV_FORMAT_TILED;
     if (int e = sgtv_set_schedule(c, &sch)) return e;
-    if (int e = sgtv_set_system(c, I, ny, nx, Q, row_ptr, col_idx, val, nnz, SGTV_F32, w, w_len, mem_kind))
+    if (int e = sgtv_set_system(c, I, ny, nx, Q, row_ptr, col_idx, val, nnz, b->storage, w, w_len, mem_kind))
         return e;
     return batch_join(b, std::move(own), y, r, beta, rho, grouping, mem_kind, index);
 }
@@ -2948,8 +2954,8 @@ int sgtv_batch_add_system_file(sgtv_batch b, const char *path, const float *y, c
     if (int e = sgtv_create(&c, b->device, b->stream)) return e;
     std::unique_ptr<sgtv_ctx_s> own(c);
     if (int e = sgtv_load_system(c, path)) return e;
-    if (c->sys->format != SGTV_FORMAT_TILED || c->sys->vt != SGTV_F32)
-        return fail(SGTV_EINVAL, "scans of a batch need a tiled system with FP32 values");
+    if (c->sys->format != SGTV_FORMAT_TILED || c->sys->vt != b->storage)
+        return fail(SGTV_EINVAL, "scans of a batch need a tiled system with the batch's value type");
     return batch_join(b, std::move(own), y, r, beta, rho, grouping, mem_kind, index);
 }
 
@@ -3088,6 +3094,16 @@ int sgtv_batch_iterate_sequential(sgtv_batch b, int n_iters) {
         b->fcur = b->scans.front()->fcur;
         b->vcur = b->scans.front()->vcur;
     }
+    return SGTV_OK;
+}
+
+int sgtv_batch_set_storage(sgtv_batch b, int storage_dtype) {
+    if (!b) return fail(SGTV_EINVAL, "null batch");
+    if (storage_dtype != SGTV_F32 && storage_dtype != SGTV_BF16 && storage_dtype != SGTV_F16)
+        return fail(SGTV_EINVAL, "unknown storage dtype");
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (!b->scans.empty()) return fail(SGTV_ESTATE, "the value type is set before the first scan is added");
+    b->storage = storage_dtype;
     return SGTV_OK;
 }
 

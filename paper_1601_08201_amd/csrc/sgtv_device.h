@@ -266,23 +266,28 @@ __device__ __forceinline__ void batch_ratio_elem(const ScanDev &S, int64_t i) {
     S.ratio[i] = S.y[i] / p;
 }
 
-// image update of hyper-voxel j: reads f[fcur], writes f[fcur ^ 1] (FP32 values)
+// image update of hyper-voxel j: reads f[fcur], writes f[fcur ^ 1] (and, for
+// 16-bit values, the scaled copy fs); the arithmetic of the single-scan image
+// update (the same H0 source: the table unless the weights are full)
 __device__ __forceinline__ void batch_voxel_elem(const ScanDev &S, int64_t j, int fcur, int vcur) {
     if (j >= S.grid.J) return;
     auto e = [&]() {
         float s = S.bpart[j];
         for (int k = 1; k < S.ns_b; ++k) s += S.bpart[static_cast<int64_t>(k) * S.grid.J + j];
-        return s;
+        return S.scale ? s * S.scale[j] : s;
     };
     const float *g = S.f[fcur], *v = S.v[vcur], *a = S.a[vcur];
+    const VoxelPos P = voxel_pos(j, S.grid);
+    auto h = [&]() { return S.wts.full ? S.H[j] : S.htab[neighbour_mask(S.grid, P.iy, P.ix)]; };
     float gnew;
     if (S.grouping == 0)
-        gnew = S.wts.full ? voxel_update_value<0, true>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam)
-                          : voxel_update_value<0, false>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam);
+        gnew = S.wts.full ? voxel_update_at<0, true>(j, P, e, g, v, a, S.sens, h, S.grid, S.wts, S.lam)
+                          : voxel_update_at<0, false>(j, P, e, g, v, a, S.sens, h, S.grid, S.wts, S.lam);
     else
-        gnew = S.wts.full ? voxel_update_value<1, true>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam)
-                          : voxel_update_value<1, false>(j, e, g, v, a, S.sens, S.H, S.grid, S.wts, S.lam);
+        gnew = S.wts.full ? voxel_update_at<1, true>(j, P, e, g, v, a, S.sens, h, S.grid, S.wts, S.lam)
+                          : voxel_update_at<1, false>(j, P, e, g, v, a, S.sens, h, S.grid, S.wts, S.lam);
     S.f[fcur ^ 1][j] = gnew;
+    if (S.fs) S.fs[j] = gnew * S.scale[j];
 }
 
 // split and dual update of the 256-thread block that starts at spatial bin s0

@@ -82,6 +82,9 @@ struct ScanDev {
     float *ratio, *fpart, *bpart;
     float *f[2], *v[2], *a[2];
     const float *sens, *H;
+    const float *htab;          // H0 by neighbour pattern (weights constant per direction)
+    const float *scale;         // per-column scale of 16-bit values (nullptr: FP32) ...
+    float *fs;                  // ... and the scaled image the forward product reads
     Grid grid;
     Weights wts;
     int64_t I;
@@ -153,7 +156,7 @@ hipError_t launch_admm_persistent(const PersistentDev *D, const PersistentPlan &
                                   int threads, int variant, int grid, hipStream_t st);
 hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
                               const float *const *xs, float *const *parts, int waves, size_t lds,
-                              int variant, hipStream_t st);
+                              int variant, int vt, hipStream_t st);
 hipError_t launch_ratio_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,
                               hipStream_t st);
 hipError_t launch_voxel_batch(const BatchBlock *blocks, int64_t n_blocks, const ScanDev *scans,

@@ -686,25 +686,31 @@ hipError_t launch_tiled_update(const TileMap &M, int vt, const float *x, float *
               : launch_tiled_e<2, 1, false>(M, vt, x, part, nullptr, &E, st);
 }
 
-template <int MODE>
+template <int VT, int MODE>
 static hipError_t launch_tiled_batch_t(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
                                        const float *const *xs, float *const *parts, int waves,
                                        size_t lds, hipStream_t st) {
-    static const hipError_t raised = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&k_tiled_batch<0, MODE>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    if (raised != hipSuccess) return raised;
-    hipLaunchKernelGGL((k_tiled_batch<0, MODE>), dim3(static_cast<unsigned>(n_tiles)),
+    if (hipError_t e = raise_lds<&k_tiled_batch<VT, MODE>>()) return e;
+    hipLaunchKernelGGL((k_tiled_batch<VT, MODE>), dim3(static_cast<unsigned>(n_tiles)),
                        dim3(static_cast<unsigned>(waves * kWave)), lds, st, tiles, maps, xs, parts);
     return hipGetLastError();
 }
 
+template <int VT>
+static hipError_t launch_tiled_batch_v(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
+                                       const float *const *xs, float *const *parts, int waves, size_t lds,
+                                       int variant, hipStream_t st) {
+    if (variant == 1) return launch_tiled_batch_t<VT, 1>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
+    return launch_tiled_batch_t<VT, 0>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
+}
+
 hipError_t launch_tiled_batch(const BatchTile *tiles, int64_t n_tiles, const TileMap *maps,
                               const float *const *xs, float *const *parts, int waves, size_t lds,
-                              int variant, hipStream_t st) {
+                              int variant, int vt, hipStream_t st) {
     if (n_tiles == 0) return hipSuccess;
-    if (variant == 1)
-        return launch_tiled_batch_t<1>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
-    return launch_tiled_batch_t<0>(tiles, n_tiles, maps, xs, parts, waves, lds, st);
+    if (vt == 1) return launch_tiled_batch_v<1>(tiles, n_tiles, maps, xs, parts, waves, lds, variant, st);
+    if (vt == 2) return launch_tiled_batch_v<2>(tiles, n_tiles, maps, xs, parts, waves, lds, variant, st);
+    return launch_tiled_batch_v<0>(tiles, n_tiles, maps, xs, parts, waves, lds, variant, st);
 }
 
 template <int MODE>

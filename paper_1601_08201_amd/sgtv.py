@@ -119,6 +119,7 @@ def lib():
             "sgtv_batch_add_system_file": (_I, [_P, ctypes.c_char_p, _P, _P, _D, _D, _I, _I,
                                                 ctypes.POINTER(_I32)]),
             "sgtv_batch_save_scan": (_I, [_P, _I32, ctypes.c_char_p]),
+            "sgtv_batch_set_storage": (_I, [_P, _I]),
             "sgtv_batch_size": (_I, [_P, ctypes.POINTER(_I32)]),
             "sgtv_batch_iterate": (_I, [_P, _I]),
             "sgtv_batch_prepare": (_I, [_P, _I, _I]),
@@ -616,6 +617,10 @@ def sgtv_batch_add_system_file(b, path, y, r, beta, rho, grouping=0):
     return idx.value
 
 
+def sgtv_batch_set_storage(b, storage="f32"):
+    _check(lib().sgtv_batch_set_storage(b, STORAGE.get(storage, storage)))
+
+
 def sgtv_batch_save_scan(b, scan, path):
     _check(lib().sgtv_batch_save_scan(b, int(scan), os.fsencode(path)))
 
@@ -679,9 +684,11 @@ def sgtv_batch_get_image(b, scan, n, out=None):
 class Batch:
     """Owning handle around a batch of scans iterated together."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, storage="f32"):
         self._b = sgtv_batch_create(device, stream)
         self._J = {}     # batch index -> unknowns (add_scan may run on several threads)
+        if storage != "f32":
+            sgtv_batch_set_storage(self._b, storage)
 
     def close(self):
         if self._b is not None:

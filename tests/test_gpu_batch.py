@@ -226,3 +226,30 @@ def test_batch_of_the_64_scan_workload_matches_single_runs_and_oracle(sg):
             print("scan", shapes[picks[i]], "rel_l2 vs oracle", err, flush=True)
             assert err <= 1e-5
     B.close()
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_batch_of_16_bit_scans_matches_single_scans(sg, storage):
+    """Scans with 16-bit matrix values (per-column FP32 scale) in one batch
+    equal their single-scan runs bit for bit (graph replays and eager
+    launches), and the persistent launch refuses them with an error."""
+    probs = scans()
+    B = sg.Batch(storage=storage)
+    for p in probs:
+        B.add_scan(p, schedule=SCHED)
+    B.iterate(12)
+    B.iterate(8)
+    for i, p in enumerate(probs):
+        R = sg.Reconstructor()
+        R.set_schedule(**SCHED)
+        R.set_problem(p, storage=storage)
+        R.iterate(20)
+        np.testing.assert_array_equal(B.image(i), R.image())
+        assert B.objective(i) == R.objective()
+        R.close()
+    with pytest.raises(RuntimeError):
+        sg.sgtv_batch_set_storage(B._b, "f32")      # scans are already there
+    B.set_launch("persistent")
+    with pytest.raises(RuntimeError):
+        B.iterate(2)
+    B.close()
