@@ -5,11 +5,10 @@
 //
 // Convolution as implicit GEMM: output pixels x output channels, reduction
 // over (tap, input channel), K = 9 * 64 = 576.  Persistent workgroups of four
-// waves stage all weights in LDS once and then walk over steps of four image
-// rows: the six input rows a step needs are staged in LDS (the next step's
-// rows are loaded into registers while the current step computes), and wave w
-// computes row w of the step, 64 pixels x 64 channels, as 4 x 4 tiles of
-// v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+8],
+// waves stage all weights in LDS once and then walk over steps of eight image
+// rows: the ten input rows a step needs are staged in LDS, and wave w
+// computes rows 2w and 2w + 1 of the step, 128 pixels x 64 channels, as
+// 2 x 4 x 4 tiles of v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..+8],
 // B[8(l/16)..+8][l%16], D[4(l/16)..+4][l%16]).
 #include "sgtv_device.h"
 #include "sgtv_wsnet.h"
@@ -23,127 +22,214 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kC = 64;                 // channels
 constexpr int kK = 9 * kC;             // reduction length of one output
-constexpr int kPixPad = kC + 8;        // bf16 per staged pixel (keeps 16-byte alignment)
-constexpr int kWPad = kK + 8;          // bf16 per staged weight row
 
 __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
 __device__ __forceinline__ float sigmoidf(float z) {
     return z >= 0.0f ? 1.0f / (1.0f + expf(-z)) : expf(z) / (1.0f + expf(z));
 }
 
-constexpr int kStepRows = 4;                       // output rows per step (one per wave)
+constexpr int kStepRows = 8;                       // output rows per step (two per wave)
 constexpr int kStageRows = kStepRows + 2;          // input rows a step reads
 constexpr int kRowPix = kC + 2;                    // staged pixels per row (width 64 + halo)
-constexpr int kStageChunks = kStageRows * kRowPix * (kC / 8);   // 16-byte chunks per step
-constexpr int kChunksPerThread = (kStageChunks + 255) / 256;
+constexpr int kChunks = kC / 8;                    // 16-byte chunks per pixel (8 channels each)
 
+// LDS layout: the weights [co][tap][ci] (576 bf16 per output channel) and the
+// step's input rows [row][pixel][ci], both without padding.  A 16-byte chunk
+// is stored at its index XOR (row or pixel index mod 8) within each group of
+// 8 chunks, so the 16 lanes that read one MFMA fragment (16 pixels or 16
+// output channels at the same channel offset) hit 8 distinct 16-byte bank
+// groups per half instead of one.
 size_t conv_lds_bytes(int) {
-    return (static_cast<size_t>(kStageRows) * kRowPix * kPixPad + static_cast<size_t>(kC) * kWPad) * 2;
+    return (static_cast<size_t>(kC) * kK + static_cast<size_t>(kStageRows) * kRowPix * kC) * 2;
 }
+
+__device__ __forceinline__ int swz(int chunk, int key) { return (chunk & ~7) | ((chunk ^ key) & 7); }
 
 // EP_RELU: out_bf16 = relu(z + b) (hidden layer); EP_SOFTPLUS: out_z = z + b,
 // out_sp = softplus(z + b) (last layer); EP_MASK: out_bf16 = z if mask > 0
 // else 0 (gradient through the ReLU of the previous layer, no bias).
+//
+// Workgroup of 8 waves (two per SIMD, so one wave's LDS reads overlap the
+// other's MFMAs), one per CU; a step is 8 output rows of one image and wave w
+// computes row w of it: 64 pixels x 64 output channels as 4 x 4 tiles of
+// 16 x 16, each k-step of 32 (one tap, 32 input channels) reading 4 pixel and
+// 4 weight fragments from LDS for 16 MFMAs.
+constexpr int kConvThreads = 64 * kStepRows;
+
 template <int EP>
-__global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ X,
-                                                 const __bf16 *__restrict__ Wk,
-                                                 const float *__restrict__ bias, int B, int H,
-                                                 __bf16 *__restrict__ out_bf16,
-                                                 float *__restrict__ out_z,
-                                                 float *__restrict__ out_sp,
-                                                 const __bf16 *__restrict__ mask) {
+__global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restrict__ X,
+                                                          const __bf16 *__restrict__ Wk,
+                                                          const float *__restrict__ bias, int B, int H,
+                                                          __bf16 *__restrict__ out_bf16,
+                                                          float *__restrict__ out_z,
+                                                          float *__restrict__ out_sp,
+                                                          const __bf16 *__restrict__ mask) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *ws = reinterpret_cast<__bf16 *>(smem);                  // [co][tap * 64 + ci]
-    __bf16 *xs = ws + static_cast<size_t>(kC) * kWPad;              // [row][pixel + 1][ci]
+    __bf16 *ws = reinterpret_cast<__bf16 *>(smem);                  // [co][576], swizzled chunks
+    __bf16 *xs = ws + static_cast<size_t>(kC) * kK;                 // [row][pixel][64], swizzled
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int steps_per_img = (H + kStepRows - 1) / kStepRows;
     const int n_steps = B * steps_per_img;
 
-    for (int i = tid; i < kC * kK / 8; i += 256) {
-        const int co = i / (kK / 8), k8 = i % (kK / 8);
-        *reinterpret_cast<u16x8 *>(ws + co * kWPad + k8 * 8) =
-            *reinterpret_cast<const u16x8 *>(Wk + static_cast<size_t>(co) * kK + k8 * 8);
-    }
-
-    u16x8 pre[kChunksPerThread];
+    // the input rows of a step, loaded into registers (all loads in flight at once)
+    constexpr int kRChunks = kStageRows * kRowPix * kChunks, kRPer = (kRChunks + kConvThreads - 1) / kConvThreads;
+    u16x8 rv[kRPer];
     auto load_rows = [&](int step) {
         const int n = step / steps_per_img, y0 = (step % steps_per_img) * kStepRows;
 #pragma unroll
-        for (int k = 0; k < kChunksPerThread; ++k) {
-            const int i = tid + k * 256;
-            const int c8 = i % (kC / 8), rest = i / (kC / 8);
+        for (int k = 0; k < kRPer; ++k) {
+            const int i = tid + k * kConvThreads;
+            const int c8 = i % kChunks, rest = i / kChunks;
             const int xc = rest % kRowPix, r = rest / kRowPix;
             const int sy = y0 - 1 + r, sx = xc - 1;
             u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (i < kStageChunks && sy >= 0 && sy < H && sx >= 0 && sx < kC)
+            if (i < kRChunks && sy >= 0 && sy < H && sx >= 0 && sx < kC)
                 v = *reinterpret_cast<const u16x8 *>(X + ((static_cast<size_t>(n) * H + sy) * kC + sx) * kC + c8 * 8);
-            pre[k] = v;
+            rv[k] = v;
         }
     };
 
-    const int li = lane & 15, lk = (lane >> 4) * 8;
-    int step = blockIdx.x;
-    if (step < n_steps) load_rows(step);
-    for (; step < n_steps; step += gridDim.x) {
-        __syncthreads();                               // every wave is done with the staged rows
+    // the weights and the first step's rows in flight together, then the
+    // weights to LDS
+    constexpr int kWChunks = kC * (kK / 8), kWPer = kWChunks / kConvThreads;
+    static_assert(kWChunks % kConvThreads == 0, "weight chunks per thread");
+    {
+        u16x8 wr[kWPer];
 #pragma unroll
-        for (int k = 0; k < kChunksPerThread; ++k) {
-            const int i = tid + k * 256;
-            if (i < kStageChunks) {
-                const int c8 = i % (kC / 8), rest = i / (kC / 8);
-                *reinterpret_cast<u16x8 *>(xs + rest * kPixPad + c8 * 8) = pre[k];
-            }
+        for (int k = 0; k < kWPer; ++k) {
+            const int i = tid + k * kConvThreads, co = i / (kK / 8), k8 = i % (kK / 8);
+            wr[k] = *reinterpret_cast<const u16x8 *>(Wk + static_cast<size_t>(co) * kK + k8 * 8);
+        }
+        if (static_cast<int>(blockIdx.x) < n_steps) load_rows(blockIdx.x);
+#pragma unroll
+        for (int k = 0; k < kWPer; ++k) {
+            const int i = tid + k * kConvThreads, co = i / (kK / 8), k8 = i % (kK / 8);
+            *reinterpret_cast<u16x8 *>(ws + co * kK + swz(k8, co) * 8) = wr[k];
+        }
+    }
+
+    const int li = lane & 15, g = lane >> 4;
+    for (int step = blockIdx.x; step < n_steps; step += gridDim.x) {
+        const int n = step / steps_per_img, y0 = (step % steps_per_img) * kStepRows;
+        __syncthreads();                               // every wave is done with the previous step's LDS
+#pragma unroll
+        for (int k = 0; k < kRPer; ++k) {
+            const int i = tid + k * kConvThreads;
+            const int c8 = i % kChunks, rest = i / kChunks, xc = rest % kRowPix;
+            if (i < kRChunks) *reinterpret_cast<u16x8 *>(xs + rest * kC + swz(c8, xc) * 8) = rv[k];
         }
         __syncthreads();
+        // the next step's rows load while this one computes
         if (step + static_cast<int>(gridDim.x) < n_steps) load_rows(step + gridDim.x);
 
-        const int n = step / steps_per_img;
-        const int y = (step % steps_per_img) * kStepRows + wv;
-        if (y >= H) continue;                          // last step of an image with H % 4 == 2
+        const int y = y0 + wv;
+        const bool active = y < H;
         f32x4 acc[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int tap = 0; tap < 9; ++tap) {
-            const int ky = tap / 3, kx = tap % 3;
-            const __bf16 *xrow = xs + ((wv + ky) * kRowPix + kx) * kPixPad;
+        if (active) {
+#pragma unroll 1
+            for (int tap = 0; tap < 9; ++tap) {
+                const int ky = tap / 3, kx = tap % 3;
+                const __bf16 *row = xs + (wv + ky) * kRowPix * kC;
 #pragma unroll
-            for (int c0 = 0; c0 < kC; c0 += 32) {
-                bf16x8 a[4], b[4];
+                for (int c0 = 0; c0 < kC; c0 += 32) {
+                    const int cc = c0 / 8 + g;         // chunk of this lane's 8 input channels
+                    bf16x8 a[4], b[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    a[t] = *reinterpret_cast<const bf16x8 *>(xrow + (16 * t + li) * kPixPad + c0 + lk);
+                    for (int t = 0; t < 4; ++t) {
+                        const int px = 16 * t + li + kx;
+                        a[t] = *reinterpret_cast<const bf16x8 *>(row + px * kC + swz(cc, px) * 8);
+                    }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    b[u] = *reinterpret_cast<const bf16x8 *>(ws + (16 * u + li) * kWPad + tap * kC + c0 + lk);
+                    for (int u = 0; u < 4; ++u) {
+                        const int co = 16 * u + li;
+                        b[u] = *reinterpret_cast<const bf16x8 *>(ws + co * kK + swz(tap * kChunks + cc, co) * 8);
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[u], acc[t][u], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();                               // the staged rows are free: the outputs pass through them
+
+        // Epilogue through LDS: the wave's tile is written to its own part of
+        // the row area in the output's layout, then read back and stored as
+        // 16-byte chunks, so every store instruction covers whole lines.
+        const size_t base = (static_cast<size_t>(n) * H + y) * kC * kC;   // first element of row y
+        if (EP != 1) {
+            __bf16 *tile = xs + wv * (kC * kC);        // 8 KB per wave
+            if (active) {
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[u], acc[t][u], 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int px = 16 * t + g * 4 + r, co = 16 * u + li;
+                            float z = acc[t][u][r];
+                            if (EP == 0) z = fmaxf(z + bias[co], 0.0f);
+                            tile[px * kC + co] = static_cast<__bf16>(z);
+                        }
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll 4
+                for (int c = lane; c < kC * kC / 8; c += 64) {
+                    u16x8 v = *reinterpret_cast<const u16x8 *>(tile + c * 8);
+                    if (EP == 2) {
+                        const u16x8 m = *reinterpret_cast<const u16x8 *>(mask + base + c * 8);
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            __bf16 mb;
+                            const unsigned short mu = m[e];
+                            __builtin_memcpy(&mb, &mu, 2);
+                            if (!(static_cast<float>(mb) > 0.0f)) v[e] = 0;
+                        }
+                    }
+                    *reinterpret_cast<u16x8 *>(out_bf16 + base + c * 8) = v;
+                }
+            }
+        } else {
+            // FP32 z and softplus(z), 32 pixels at a time (8 KB of FP32 per wave)
+            float *tile = reinterpret_cast<float *>(xs) + wv * (kC * kC / 2);
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                if (active) {
+#pragma unroll
+                    for (int t = 2 * hh; t < 2 * hh + 2; ++t)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int px = 16 * t + g * 4 + r - 32 * hh, co = 16 * u + li;
+                                tile[px * kC + co] = acc[t][u][r] + bias[co];
+                            }
+                }
+                __syncthreads();
+                if (active) {
+                    const size_t hb = base + static_cast<size_t>(hh) * 32 * kC;
+#pragma unroll 4
+                    for (int c = lane; c < 32 * kC / 4; c += 64) {
+                        const f32x4 z = *reinterpret_cast<const f32x4 *>(tile + c * 4);
+                        f32x4 sp;
+                        sp[0] = softplusf(z[0]);
+                        sp[1] = softplusf(z[1]);
+                        sp[2] = softplusf(z[2]);
+                        sp[3] = softplusf(z[3]);
+                        *reinterpret_cast<f32x4 *>(out_z + hb + c * 4) = z;
+                        *reinterpret_cast<f32x4 *>(out_sp + hb + c * 4) = sp;
+                    }
+                }
+                __syncthreads();
             }
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int px = 16 * t + (lane >> 4) * 4 + r;
-                    const int co = 16 * u + li;
-                    const size_t o = ((static_cast<size_t>(n) * H + y) * kC + px) * kC + co;
-                    float z = acc[t][u][r];
-                    if (EP != 2) z += bias[co];
-                    if (EP == 0) out_bf16[o] = static_cast<__bf16>(fmaxf(z, 0.0f));
-                    if (EP == 1) {
-                        out_z[o] = z;
-                        out_sp[o] = softplusf(z);
-                    }
-                    if (EP == 2)
-                        out_bf16[o] = static_cast<float>(mask[o]) > 0.0f ? static_cast<__bf16>(z) : static_cast<__bf16>(0.0f);
-                }
     }
 }
 
@@ -263,8 +349,18 @@ __global__ __launch_bounds__(256) void k_block_sum(const float *__restrict__ par
     const int per = (n_blocks + 3) / 4;
     const int b0 = qt * per, b1 = min(n_blocks, b0 + per);
     float acc = 0.0f;
-    if (k < len)
-        for (int b = b0; b < b1; ++b) acc += part[static_cast<int64_t>(b) * len + k];
+    if (k < len) {
+        // eight loads in flight, then their additions in block order
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            float t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = part[static_cast<int64_t>(b + u) * len + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t[u];
+        }
+        for (; b < b1; ++b) acc += part[static_cast<int64_t>(b) * len + k];
+    }
     s4[qt][kl] = acc;
     __syncthreads();
     if (qt == 0 && k < len) grad[k] = (s4[0][kl] + s4[1][kl]) + (s4[2][kl] + s4[3][kl]);
@@ -380,9 +476,9 @@ static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, i
     if (raised != hipSuccess) return raised;
     const int n_steps = B * ((H + kStepRows - 1) / kStepRows);
     if (n_steps == 0) return hipSuccess;
-    // one workgroup per CU (the staged weights and rows take 129 KB of LDS)
+    // one workgroup per CU (the staged weights and rows take 155 KB of LDS)
     const int grid = std::min(n_steps, conv_workgroups());
-    hipLaunchKernelGGL((k_conv3x3<EP>), dim3(static_cast<unsigned>(grid)), dim3(256), lds, st, X, Wk,
+    hipLaunchKernelGGL((k_conv3x3<EP>), dim3(static_cast<unsigned>(grid)), dim3(kConvThreads), lds, st, X, Wk,
                        bias, B, H, ob, oz, osp, mask);
     return hipGetLastError();
 }
