@@ -275,12 +275,19 @@ __global__ __launch_bounds__(256) void k_rows_cmajor(const __bf16 *__restrict__ 
 // Partial dW over R image rows (block b: rows b R .. b R + R - 1 of one image);
 // wave t = tap (ky, kx) accumulates all 64 x 64 (co, ci) outputs of its tap as
 // 4 x 4 tiles of v_mfma_f32_16x16x32_bf16.  DT = dZ channel-major [row][co][x],
-// XT = X channel-major with the three shifts [row][kx][ci][x].  The wave of the
-// centre tap (which reads every row) also sums its dZ fragments: the block's
-// bias partials follow its weight partials.  Row stride of part: C*9*C + C.
-__global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ DT,
-                                                    const __bf16 *__restrict__ XT, int H, int R,
-                                                    float *__restrict__ part) {
+// XT = X channel-major with the three shifts [row][kx][ci][x].  The block's R
+// rows of DT, which every tap's wave reads, are staged in LDS once (16-byte
+// chunks at their index XOR (co mod 8)); the X fragments, different for every
+// tap, come from memory.  The wave of the centre tap (which reads every row)
+// also sums its dZ fragments: the block's bias partials follow its weight
+// partials.  Row stride of part: C*9*C + C.
+constexpr int kWgradThreads = 9 * 64;
+constexpr int kWgradMaxRows = 8;
+
+__global__ __launch_bounds__(kWgradThreads) void k_wgrad_taps(const __bf16 *__restrict__ DT,
+                                                              const __bf16 *__restrict__ XT, int H, int R,
+                                                              float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) __bf16 ds[kWgradMaxRows * kC * kC];   // 64 KB
     const int lane = threadIdx.x & 63;
     const int t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ky = t / 3, kx = t % 3;
@@ -288,6 +295,15 @@ __global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ D
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * R;
     const int64_t n = row0 / H;
     const int y0 = static_cast<int>(row0 - n * H);
+    {
+        const __bf16 *src = DT + row0 * kC * kC;
+        for (int i = threadIdx.x; i < R * kC * kC / 8; i += kWgradThreads) {
+            const int x8 = i & 7, co = (i >> 3) & (kC - 1), r = i >> 9;
+            *reinterpret_cast<u16x8 *>(ds + (r * kC + co) * kC + ((x8 ^ co) & 7) * 8) =
+                *reinterpret_cast<const u16x8 *>(src + static_cast<int64_t>(i) * 8);
+        }
+    }
+    __syncthreads();
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -297,15 +313,19 @@ __global__ __launch_bounds__(576) void k_wgrad_taps(const __bf16 *__restrict__ D
     for (int yy = 0; yy < R; ++yy) {
         const int y = y0 + yy, sy = y + ky - 1;
         if (sy < 0 || sy >= H) continue;
-        const __bf16 *drow = DT + (n * H + y) * kC * kC;
+        const __bf16 *drow = ds + yy * kC * kC;
         const __bf16 *xrow = XT + ((n * H + sy) * 3 + kx) * kC * kC;
 #pragma unroll
         for (int p0 = 0; p0 < kC; p0 += 32) {
+            const int x8 = (p0 + lk) / 8;
             bf16x8 a[4], b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(drow + (16 * i + li) * kC + p0 + lk);
-#pragma unroll
             for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(xrow + (16 * j + li) * kC + p0 + lk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = 16 * i + li;
+                a[i] = *reinterpret_cast<const bf16x8 *>(drow + co * kC + ((x8 ^ co) & 7) * 8);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -511,7 +531,8 @@ hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int R = wgrad_rows(H);
     const int nb = rows / R;
-    hipLaunchKernelGGL(k_wgrad_taps, dim3(static_cast<unsigned>(nb)), dim3(576), 0, st, DT, XT, H, R, wpart);
+    if (R > kWgradMaxRows) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_wgrad_taps, dim3(static_cast<unsigned>(nb)), dim3(kWgradThreads), 0, st, DT, XT, H, R, wpart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t len = static_cast<int64_t>(kC) * kK + kC;
     hipLaunchKernelGGL(k_block_sum, dim3(static_cast<unsigned>((len + 63) / 64)), dim3(256), 0, st,
