@@ -270,6 +270,17 @@ int main() {
     check_threads("threads, long row runs", b, TileParams{64, 8, 512, 1});
     const Csr d = make_csr(40000, 30000, 16, 4, false);
     check_threads("threads, many row blocks", d, TileParams{128, 16, 4096, 4});
+    // degenerate matrices: no entries at all, one row, one column
+    Csr e;
+    e.n_rows = 300;
+    e.n_cols = 500;
+    e.rp.assign(301, 0);
+    check_case("24-bit, no entries", e, TileParams{64, 4, 128, 2}, true, true);
+    check_case("32-bit, no entries", e, TileParams{100, 4, 127, 2}, false, false);
+    const Csr one_row = make_csr(1, 4000, 900, 5, false);
+    check_case("24-bit, one row", one_row, TileParams{64, 4, 1024, 2}, true, true);
+    const Csr one_col = make_csr(3000, 1, 1, 6, false);
+    check_case("24-bit, one column", one_col, TileParams{64, 4, 4, 1}, true, true);
     if (failures) return 1;
     std::printf("ok\n");
     return 0;

@@ -518,3 +518,30 @@ def test_workspace_of_the_paper_scale_scan(sg):
     assert R.device_bytes() == 0 and ref.device_bytes() > 0.8 * nbytes
     R.close()
     ref.close()
+
+
+def _degenerate(kind):
+    import dataclasses
+    if kind == "no entries":
+        p = datagen.make_problem("small", 41)
+        return dataclasses.replace(p, rowptr=np.zeros(p.I + 1, np.int64), col=np.zeros(0, np.int32),
+                                   val=np.zeros(0, np.float32))
+    if kind == "one measurement":
+        p = datagen.make_problem(dict(ny=6, nx=5, Q=8, I=1, nnz_per_col=1, rects=2), 42)
+        return p
+    if kind == "one voxel":
+        return datagen.make_problem(dict(ny=1, nx=1, Q=1, I=50, nnz_per_col=7, rects=1), 43)
+    if kind == "one spatial bin":
+        return datagen.make_problem(dict(ny=1, nx=1, Q=40, I=300, nnz_per_col=5, rects=1), 44)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["no entries", "one measurement", "one voxel", "one spatial bin"])
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_degenerate_systems(sg, kind, fmt):
+    """A matrix without entries (the image stays at the zero start: the uniform
+    start is 0 when A^T 1 = 0, the EM step keeps 0), a single measurement, a
+    single voxel and a single spatial bin (no neighbours: the penalty
+    vanishes), in both formats, against the oracle."""
+    prob = _degenerate(kind)
+    check_against_oracle(sg, prob, 15, schedule=dict(format=fmt))
