@@ -508,6 +508,16 @@ int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t ba
 /* One Adam step with the last gradient (Kingma and Ba); the step counter
  * starts at 1 after set_params or reset. */
 int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps);
+/* wsnet_backward followed by wsnet_adam_step without waiting for the
+ * device: the step's mean squared error (as wsnet_backward reports it) is
+ * added to a running FP64 sum on the device instead of being returned, so a
+ * training loop issues its steps back to back.  Parameters, gradients and
+ * moments evolve exactly as with the two calls.  wsnet_loss_sum waits for
+ * the device and returns the running sum and the number of steps in it
+ * (reset != 0: both to zero afterwards). */
+int wsnet_train_step(wsnet net, const float *x_in, const float *target, int32_t batch, double lr, double beta1,
+                     double beta2, double eps, int mem_kind);
+int wsnet_loss_sum(wsnet net, double *sum, int64_t *steps, int reset);
 int wsnet_reset_adam(wsnet net);
 
 #ifdef __cplusplus

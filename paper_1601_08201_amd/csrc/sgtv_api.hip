@@ -3166,6 +3166,7 @@ struct wsnet_s {
     DBuf z_last, out, xin, tgt;                     // FP32
     DBuf dz[2];                                     // bf16 gradients w.r.t. pre-activations
     DBuf wpart, lpart, lred;
+    DBuf lsum;                                      // FP64 sum of the training steps' losses and their count
     DBuf xt, dt;                                    // weight-gradient scratch
     DBuf ipart, isum;                               // per-image FP64 sums (start images)
     int64_t step = 0;
@@ -3269,6 +3270,8 @@ int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32
         HIP_TRY(n->dt.alloc(2 * big));
         HIP_TRY(n->lpart.alloc(sizeof(double) * kLossBlocks));
         HIP_TRY(n->lred.alloc(sizeof(double) * 4));
+        HIP_TRY(n->lsum.alloc(sizeof(double) * 2));
+        HIP_TRY(hipMemsetAsync(n->lsum.p, 0, sizeof(double) * 2, n->stream));
         HIP_TRY(n->ipart.alloc(sizeof(double) * kImageBlocks * max_batch));
         HIP_TRY(n->isum.alloc(sizeof(double) * max_batch));
         *out = n.release();
@@ -3397,15 +3400,16 @@ int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out
     return SGTV_OK;
 }
 
-int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t batch,
-                   double *loss, float *grad, int mem_kind) {
-    if (int e = net_check(net, batch, mem_kind)) return e;
-    if (!x_in || !target) return fail(SGTV_EINVAL, "null argument");
-    DeviceGuard g(net->device);
+}  // extern "C"
+
+namespace {
+
+// Forward and backward pass of a staged batch (inputs in xin, targets in
+// tgt): the gradient in grad, the summed squared error in lred[0]; nothing
+// waits for the device.
+int net_backward(wsnet_s *net, int32_t batch) {
     const int64_t cnt = batch * net->img;
     const int64_t CK = static_cast<int64_t>(net->C) * 9 * net->C;
-    if (int e = net_stage(net, net->xin, x_in, cnt, mem_kind)) return e;
-    if (int e = net_stage(net, net->tgt, target, cnt, mem_kind)) return e;
     if (int e = net_forward(net, batch)) return e;
     int cur = 0;
     HIP_TRY(sgtv::wsn::mse_grad(net->out.as<float>(), net->tgt.as<float>(), net->z_last.as<float>(), cnt,
@@ -3421,22 +3425,18 @@ int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t ba
                                        bf(net->dz[cur ^ 1]), net->stream));
         cur ^= 1;
     }
-    double h = 0.0;
-    HIP_TRY(hipMemcpyAsync(&h, net->lred.p, sizeof(double), hipMemcpyDeviceToHost, net->stream));
-    if (grad)
-        HIP_TRY(hipMemcpyAsync(grad, net->grad.p, sizeof(float) * net->n_param, to_caller(mem_kind), net->stream));
-    HIP_TRY(hipStreamSynchronize(net->stream));
-    if (loss) *loss = h / static_cast<double>(cnt);
     net->have_grad = true;
     return SGTV_OK;
 }
 
-int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps) {
-    if (!net) return fail(SGTV_EINVAL, "null network");
-    if (!net->have_grad) return fail(SGTV_ESTATE, "no gradient (call wsnet_backward first)");
+int check_adam(double lr, double beta1, double beta2, double eps) {
     if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
         return fail(SGTV_EINVAL, "Adam needs lr > 0, 0 <= beta1, beta2 < 1 and eps > 0");
-    DeviceGuard g(net->device);
+    return SGTV_OK;
+}
+
+// One Adam step on the gradient in grad (Kingma and Ba), then the bf16 weights.
+int net_adam(wsnet_s *net, double lr, double beta1, double beta2, double eps) {
     net->step += 1;
     const double c1 = 1.0 - std::pow(beta1, static_cast<double>(net->step));
     const double c2 = 1.0 - std::pow(beta2, static_cast<double>(net->step));
@@ -3445,7 +3445,66 @@ int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps
                             static_cast<float>(beta2), static_cast<float>(1.0 - beta1),
                             static_cast<float>(1.0 - beta2), static_cast<float>(eps), static_cast<float>(c1),
                             static_cast<float>(c2), net->stream));
-    if (int e = net_weights(net)) return e;
+    return net_weights(net);
+}
+
+}  // namespace
+
+extern "C" {
+
+int wsnet_backward(wsnet net, const float *x_in, const float *target, int32_t batch,
+                   double *loss, float *grad, int mem_kind) {
+    if (int e = net_check(net, batch, mem_kind)) return e;
+    if (!x_in || !target) return fail(SGTV_EINVAL, "null argument");
+    DeviceGuard g(net->device);
+    const int64_t cnt = batch * net->img;
+    if (int e = net_stage(net, net->xin, x_in, cnt, mem_kind)) return e;
+    if (int e = net_stage(net, net->tgt, target, cnt, mem_kind)) return e;
+    if (int e = net_backward(net, batch)) return e;
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, net->lred.p, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+    if (grad)
+        HIP_TRY(hipMemcpyAsync(grad, net->grad.p, sizeof(float) * net->n_param, to_caller(mem_kind), net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    if (loss) *loss = h / static_cast<double>(cnt);
+    return SGTV_OK;
+}
+
+int wsnet_adam_step(wsnet net, double lr, double beta1, double beta2, double eps) {
+    if (!net) return fail(SGTV_EINVAL, "null network");
+    if (!net->have_grad) return fail(SGTV_ESTATE, "no gradient (call wsnet_backward first)");
+    if (int e = check_adam(lr, beta1, beta2, eps)) return e;
+    DeviceGuard g(net->device);
+    return net_adam(net, lr, beta1, beta2, eps);
+}
+
+int wsnet_train_step(wsnet net, const float *x_in, const float *target, int32_t batch, double lr, double beta1,
+                     double beta2, double eps, int mem_kind) {
+    if (int e = net_check(net, batch, mem_kind)) return e;
+    if (!x_in || !target) return fail(SGTV_EINVAL, "null argument");
+    if (int e = check_adam(lr, beta1, beta2, eps)) return e;
+    DeviceGuard g(net->device);
+    const int64_t cnt = batch * net->img;
+    if (int e = net_stage(net, net->xin, x_in, cnt, mem_kind)) return e;
+    if (int e = net_stage(net, net->tgt, target, cnt, mem_kind)) return e;
+    if (int e = net_backward(net, batch)) return e;
+    HIP_TRY(sgtv::wsn::loss_accumulate(net->lred.as<double>(), static_cast<double>(cnt), net->lsum.as<double>(),
+                                       net->stream));
+    return net_adam(net, lr, beta1, beta2, eps);
+}
+
+int wsnet_loss_sum(wsnet net, double *sum, int64_t *steps, int reset) {
+    if (!net || !sum) return fail(SGTV_EINVAL, "null argument");
+    DeviceGuard g(net->device);
+    double h[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(h, net->lsum.p, sizeof(h), hipMemcpyDeviceToHost, net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(net->lsum.p, 0, sizeof(h), net->stream));
+        HIP_TRY(hipStreamSynchronize(net->stream));
+    }
+    *sum = h[0];
+    if (steps) *steps = static_cast<int64_t>(h[1]);
     return SGTV_OK;
 }
 

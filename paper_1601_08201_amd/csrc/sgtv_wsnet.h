@@ -36,6 +36,8 @@ hipError_t start_image(const float *f, const float *s, const double *sums, int64
                        float c_out, int ratio, float *x0, hipStream_t st);
 hipError_t mse_grad(const float *out, const float *target, const float *z, int64_t n, __bf16 *dz,
                     double *partials, int n_blocks, hipStream_t st);
+// acc[0] += l[0] / cnt, acc[1] += 1 (FP64, one thread)
+hipError_t loss_accumulate(const double *l, double cnt, double *acc, hipStream_t st);
 hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                 float b2, float omb1, float omb2, float eps, float c1, float c2, hipStream_t st);
 hipError_t weights_bf16(const float *w, __bf16 *wf, __bf16 *wb, hipStream_t st);

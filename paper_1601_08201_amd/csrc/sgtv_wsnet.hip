@@ -445,6 +445,15 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ out,
     block_sum_store(acc, partials + blockIdx.x);
 }
 
+// One training step's mean squared error (its sum l[0] over cnt values) added
+// to the running sum acc[0], and the step to the count acc[1].
+__global__ void k_loss_accumulate(const double *__restrict__ l, double cnt, double *__restrict__ acc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        acc[0] += l[0] / cnt;
+        acc[1] += 1.0;
+    }
+}
+
 // 1 - beta1 and 1 - beta2 come from the host, formed in FP64: 1 - 0.999f in
 // FP32 would be 0.000999987, a 1.3e-5 relative error in every second moment.
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -574,6 +583,11 @@ hipError_t mse_grad(const float *out, const float *target, const float *z, int64
                     double *partials, int n_blocks, hipStream_t st) {
     hipLaunchKernelGGL(k_mse_grad, dim3(static_cast<unsigned>(n_blocks)), dim3(256), 0, st, out,
                        target, z, n, dz, partials);
+    return hipGetLastError();
+}
+
+hipError_t loss_accumulate(const double *l, double cnt, double *acc, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss_accumulate, dim3(1), dim3(64), 0, st, l, cnt, acc);
     return hipGetLastError();
 }
 

@@ -138,6 +138,8 @@ def lib():
             "wsnet_start": (_I, [_P, _P, _I32, _I, _D, _P, _I]),
             "wsnet_backward": (_I, [_P, _P, _P, _I32, ctypes.POINTER(_D), _P, _I]),
             "wsnet_adam_step": (_I, [_P, _D, _D, _D, _D]),
+            "wsnet_train_step": (_I, [_P, _P, _P, _I32, _D, _D, _D, _D, _I]),
+            "wsnet_loss_sum": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), _I]),
             "wsnet_reset_adam": (_I, [_P]),
             "sgtv_set_schedule": (_I, [_P, ctypes.POINTER(Schedule)]),
             "sgtv_set_penalty": (_I, [_P, _D]),
@@ -818,6 +820,18 @@ def wsnet_adam_step(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(lib().wsnet_adam_step(net, float(lr), float(beta1), float(beta2), float(eps)))
 
 
+def wsnet_train_step(net, x_in, target, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    a, t = _arg(x_in, np.float32), _arg(target, np.float32)
+    _check(lib().wsnet_train_step(net, a[0], t[0], int(batch), float(lr), float(beta1), float(beta2),
+                                  float(eps), _kind(a, t)))
+
+
+def wsnet_loss_sum(net, reset=True):
+    s, n = ctypes.c_double(), _I64()
+    _check(lib().wsnet_loss_sum(net, ctypes.byref(s), ctypes.byref(n), 1 if reset else 0))
+    return s.value, n.value
+
+
 def wsnet_reset_adam(net):
     _check(lib().wsnet_reset_adam(net))
 
@@ -879,6 +893,16 @@ class WarmStartNet:
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         wsnet_adam_step(self._n, lr, beta1, beta2, eps)
         return self
+
+    def train_step(self, x_in, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """backward + adam_step without waiting for the device; the loss goes
+        to a running sum (loss_sum)."""
+        wsnet_train_step(self._n, x_in, target, x_in.shape[0], lr, beta1, beta2, eps)
+        return self
+
+    def loss_sum(self, reset=True):
+        """(sum of the train_step losses, number of steps) since the last reset."""
+        return wsnet_loss_sum(self._n, reset)
 
     def reset_adam(self):
         wsnet_reset_adam(self._n)

@@ -186,16 +186,14 @@ def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, 
     t0 = time.time()
     for ep in range(epochs):
         order = torch.from_numpy(rng.permutation(N)).to(dev)
-        tot = 0.0
         for b in range(N // batch):
             idx = order[b * batch:(b + 1) * batch]
             xb = X.index_select(0, idx).contiguous()
             tb = T.index_select(0, idx).contiguous()
-            loss = net.backward(xb, tb)
             cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(steps, 1)))
-            net.adam_step(lr=cur)
-            tot += loss
+            net.train_step(xb, tb, lr=cur)      # no wait for the device: the losses add up there
             step += 1
+        tot, _ = net.loss_sum(reset=True)
         history.append(tot / max(N // batch, 1))
         if log and (ep + 1) % 5 == 0:
             log("train: epoch %d / %d, loss %.5f (%.1fs)" % (ep + 1, epochs, history[-1], time.time() - t0))

@@ -248,3 +248,33 @@ def test_save_and_load_round_trip(sg, tmp_path):
     bad.write_bytes(b"not a network")
     with pytest.raises(sg.SgtvError):
         M.load(bad)
+
+
+def test_train_step_equals_backward_and_adam(sg):
+    """wsnet_train_step (no wait for the device, the loss summed on it) leaves
+    parameters bit for bit where backward + adam_step leave them, and its loss
+    sum equals the sum of the losses backward returns, in the same order."""
+    import torch
+    p = layer_params(sg, 2, 11)
+    A = sg.WarmStartNet(layers=2, height=8, max_batch=4).set_params(p)
+    B = sg.WarmStartNet(layers=2, height=8, max_batch=4).set_params(p)
+    losses = []
+    for k in range(6):
+        x, t = data(20 + k, B=3 if k % 2 else 4, H=8)
+        lr = 1e-3 * (1.0 - 0.1 * k)
+        losses.append(A.backward(x, t))
+        A.adam_step(lr=lr)
+        xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+        B.train_step(xd, td, lr=lr)
+    s, n = B.loss_sum(reset=True)
+    assert n == 6
+    tot = 0.0
+    for l in losses:
+        tot += l
+    assert s == tot
+    np.testing.assert_array_equal(B.params(), A.params())
+    assert B.loss_sum() == (0.0, 0)
+    with pytest.raises(RuntimeError):
+        B.train_step(xd, td, lr=-1.0)
+    A.close()
+    B.close()
