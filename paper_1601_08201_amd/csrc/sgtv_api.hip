@@ -3417,12 +3417,13 @@ int net_backward(wsnet_s *net, int32_t batch) {
     HIP_TRY(sgtv::launch_reduce(net->lpart.as<double>(), kLossBlocks, 1, net->lred.as<double>(), net->stream));
     for (int l = net->L - 1; l >= 0; --l) {
         const __bf16 *X = bf(net->acts, l * net->max_batch * net->img);
+        // below the last layer, the backward-data convolution has written dZ channel-major into dt
         HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, net->xt.as<float>(),
                                       net->dt.as<float>(), net->wpart.as<float>(),
-                                      net->grad.as<float>() + l * net->per_layer, net->stream));
+                                      net->grad.as<float>() + l * net->per_layer, l + 1 < net->L, net->stream));
         if (l == 0) break;
         HIP_TRY(sgtv::wsn::conv_masked(bf(net->dz[cur]), bf(net->wb, l * CK), batch, net->H, net->W, X,
-                                       bf(net->dz[cur ^ 1]), net->stream));
+                                       bf(net->dz[cur ^ 1]), bf(net->dt), net->stream));
         cur ^= 1;
     }
     net->have_grad = true;

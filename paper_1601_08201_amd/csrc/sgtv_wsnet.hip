@@ -47,7 +47,9 @@ __device__ __forceinline__ int swz(int chunk, int key) { return (chunk & ~7) | (
 
 // EP_RELU: out_bf16 = relu(z + b) (hidden layer); EP_SOFTPLUS: out_z = z + b,
 // out_sp = softplus(z + b) (last layer); EP_MASK: out_bf16 = z if mask > 0
-// else 0 (gradient through the ReLU of the previous layer, no bias).
+// else 0 (gradient through the ReLU of the previous layer, no bias), and,
+// when dt_out is not null, the same values channel-major per image row
+// ([row][channel][x], the layout the weight gradient reads).
 //
 // Workgroup of 8 waves (two per SIMD, so one wave's LDS reads overlap the
 // other's MFMAs), one per CU; a step is 8 output rows of one image and wave w
@@ -63,7 +65,8 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restri
                                                           __bf16 *__restrict__ out_bf16,
                                                           float *__restrict__ out_z,
                                                           float *__restrict__ out_sp,
-                                                          const __bf16 *__restrict__ mask) {
+                                                          const __bf16 *__restrict__ mask,
+                                                          __bf16 *__restrict__ dt_out) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16 *ws = reinterpret_cast<__bf16 *>(smem);                  // [co][576], swizzled chunks
     __bf16 *xs = ws + static_cast<size_t>(kC) * kK;                 // [row][pixel][64], swizzled
@@ -192,8 +195,26 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restri
                             __builtin_memcpy(&mb, &mu, 2);
                             if (!(static_cast<float>(mb) > 0.0f)) v[e] = 0;
                         }
+                        if (dt_out) *reinterpret_cast<u16x8 *>(tile + c * 8) = v;   // masked, for the copy below
                     }
                     *reinterpret_cast<u16x8 *>(out_bf16 + base + c * 8) = v;
+                }
+            }
+            if (EP == 2 && dt_out) {
+                __syncthreads();
+                if (active) {
+                    // eight lanes per channel, each eight pixels of the tile's column, so every
+                    // store instruction writes eight whole 128-byte channel rows
+                    const unsigned short *tu = reinterpret_cast<const unsigned short *>(tile);
+                    const int x8 = lane & 7;
+#pragma unroll 2
+                    for (int k = 0; k < 8; ++k) {
+                        const int co = (lane >> 3) + 8 * k;
+                        u16x8 w;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) w[j] = tu[(x8 * 8 + j) * kC + co];
+                        *reinterpret_cast<u16x8 *>(dt_out + base + static_cast<size_t>(co) * kC + x8 * 8) = w;
+                    }
                 }
             }
         } else {
@@ -497,7 +518,7 @@ int conv_workgroups() {
 
 template <int EP>
 static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
-                         int W, __bf16 *ob, float *oz, float *osp, const __bf16 *mask,
+                         int W, __bf16 *ob, float *oz, float *osp, const __bf16 *mask, __bf16 *dt,
                          hipStream_t st) {
     const size_t lds = conv_lds_bytes(W);
     static const hipError_t raised = hipFuncSetAttribute(
@@ -508,34 +529,36 @@ static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, i
     // one workgroup per CU (the staged weights and rows take 155 KB of LDS)
     const int grid = std::min(n_steps, conv_workgroups());
     hipLaunchKernelGGL((k_conv3x3<EP>), dim3(static_cast<unsigned>(grid)), dim3(kConvThreads), lds, st, X, Wk,
-                       bias, B, H, ob, oz, osp, mask);
+                       bias, B, H, ob, oz, osp, mask, dt);
     return hipGetLastError();
 }
 
 hipError_t conv_relu(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H, int W,
                      __bf16 *out, hipStream_t st) {
-    return conv_t<0>(X, Wk, bias, B, H, W, out, nullptr, nullptr, nullptr, st);
+    return conv_t<0>(X, Wk, bias, B, H, W, out, nullptr, nullptr, nullptr, nullptr, st);
 }
 hipError_t conv_softplus(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
                          int W, float *z, float *sp, hipStream_t st) {
-    return conv_t<1>(X, Wk, bias, B, H, W, nullptr, z, sp, nullptr, st);
+    return conv_t<1>(X, Wk, bias, B, H, W, nullptr, z, sp, nullptr, nullptr, st);
 }
 hipError_t conv_masked(const __bf16 *X, const __bf16 *Wk, int B, int H, int W, const __bf16 *mask,
-                       __bf16 *out, hipStream_t st) {
-    return conv_t<2>(X, Wk, nullptr, B, H, W, out, nullptr, nullptr, mask, st);
+                       __bf16 *out, __bf16 *dt, hipStream_t st) {
+    return conv_t<2>(X, Wk, nullptr, B, H, W, out, nullptr, nullptr, mask, dt, st);
 }
 
 int wgrad_rows(int H) { return H % 8 == 0 ? 8 : (H % 4 == 0 ? 4 : 2); }
 
 hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt, float *dt,
-                      float *wpart, float *grad, hipStream_t st) {
+                      float *wpart, float *grad, bool dt_ready, hipStream_t st) {
     const int rows = B * H;
     if (rows == 0) return hipSuccess;
     __bf16 *XT = reinterpret_cast<__bf16 *>(xt);
     __bf16 *DT = reinterpret_cast<__bf16 *>(dt);
-    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, DZ, 1, DT);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (!dt_ready) {
+        hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, DZ, 1, DT);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, X, 3, XT);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int R = wgrad_rows(H);
