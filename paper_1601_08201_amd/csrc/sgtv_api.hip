@@ -3167,7 +3167,8 @@ struct wsnet_s {
     DBuf dz[2];                                     // bf16 gradients w.r.t. pre-activations
     DBuf wpart, lpart, lred;
     DBuf lsum;                                      // FP64 sum of the training steps' losses and their count
-    DBuf xt, dt;                                    // weight-gradient scratch
+    DBuf xt, dt;                                    // weight gradient: X of every layer in three
+                                                    // shifted channel-major copies; dZ channel-major
     DBuf ipart, isum;                               // per-image FP64 sums (start images)
     int64_t step = 0;
     bool have_grad = false, have_params = false;
@@ -3194,15 +3195,19 @@ int net_stage(wsnet_s *n, DBuf &dst, const float *src, int64_t count, int mk) {
     return SGTV_OK;
 }
 
-// the layers, from the bf16 input already in the first activation buffer
-int net_layers(wsnet_s *n, int B) {
+// the layers, from the bf16 input already in the first activation buffer;
+// training: the hidden layers also write their outputs' shifted channel-major
+// copies for the weight gradients
+int net_layers(wsnet_s *n, int B, bool training = false) {
     const int64_t CK = static_cast<int64_t>(n->C) * 9 * n->C;
     for (int l = 0; l < n->L; ++l) {
         const float *bias = n->params.as<float>() + l * n->per_layer + CK;
         const __bf16 *X = bf(n->acts, l * n->max_batch * n->img);
         if (l + 1 < n->L)
             HIP_TRY(sgtv::wsn::conv_relu(X, bf(n->wf, l * CK), bias, B, n->H, n->W,
-                                         bf(n->acts, (l + 1) * n->max_batch * n->img), n->stream));
+                                         bf(n->acts, (l + 1) * n->max_batch * n->img),
+                                         training ? bf(n->xt, (l + 1) * 3 * n->max_batch * n->img) : nullptr,
+                                         n->stream));
         else
             HIP_TRY(sgtv::wsn::conv_softplus(X, bf(n->wf, l * CK), bias, B, n->H, n->W,
                                              n->z_last.as<float>(), n->out.as<float>(), n->stream));
@@ -3210,9 +3215,9 @@ int net_layers(wsnet_s *n, int B) {
     return SGTV_OK;
 }
 
-int net_forward(wsnet_s *n, int B) {
+int net_forward(wsnet_s *n, int B, bool training = false) {
     HIP_TRY(sgtv::wsn::to_bf16(n->xin.as<float>(), bf(n->acts), B * n->img, n->stream));
-    return net_layers(n, B);
+    return net_layers(n, B, training);
 }
 
 int net_check(wsnet_s *n, int B, int mk) {
@@ -3266,7 +3271,7 @@ int wsnet_create(wsnet *out, int device, void *hip_stream, int32_t layers, int32
         HIP_TRY(n->dz[0].alloc(2 * big));
         HIP_TRY(n->dz[1].alloc(2 * big));
         HIP_TRY(n->wpart.alloc(sizeof(float) * (CK + channels) * max_batch * (height / sgtv::wsn::wgrad_rows(height))));
-        HIP_TRY(n->xt.alloc(2 * 3 * big));
+        HIP_TRY(n->xt.alloc(2 * 3 * big * layers));
         HIP_TRY(n->dt.alloc(2 * big));
         HIP_TRY(n->lpart.alloc(sizeof(double) * kLossBlocks));
         HIP_TRY(n->lred.alloc(sizeof(double) * 4));
@@ -3410,17 +3415,19 @@ namespace {
 int net_backward(wsnet_s *net, int32_t batch) {
     const int64_t cnt = batch * net->img;
     const int64_t CK = static_cast<int64_t>(net->C) * 9 * net->C;
-    if (int e = net_forward(net, batch)) return e;
+    if (int e = net_forward(net, batch, true)) return e;
     int cur = 0;
     HIP_TRY(sgtv::wsn::mse_grad(net->out.as<float>(), net->tgt.as<float>(), net->z_last.as<float>(), cnt,
                                 bf(net->dz[cur]), net->lpart.as<double>(), kLossBlocks, net->stream));
     HIP_TRY(sgtv::launch_reduce(net->lpart.as<double>(), kLossBlocks, 1, net->lred.as<double>(), net->stream));
     for (int l = net->L - 1; l >= 0; --l) {
         const __bf16 *X = bf(net->acts, l * net->max_batch * net->img);
-        // below the last layer, the backward-data convolution has written dZ channel-major into dt
-        HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, net->xt.as<float>(),
-                                      net->dt.as<float>(), net->wpart.as<float>(),
-                                      net->grad.as<float>() + l * net->per_layer, l + 1 < net->L, net->stream));
+        // the forward pass wrote X's shifted copies for every layer but the first, and
+        // below the last layer the backward-data convolution has written dZ channel-major
+        float *xt = reinterpret_cast<float *>(bf(net->xt, l * 3 * net->max_batch * net->img));
+        HIP_TRY(sgtv::wsn::conv_wgrad(X, bf(net->dz[cur]), batch, net->H, xt, net->dt.as<float>(),
+                                      net->wpart.as<float>(), net->grad.as<float>() + l * net->per_layer, l > 0,
+                                      l + 1 < net->L, net->stream));
         if (l == 0) break;
         HIP_TRY(sgtv::wsn::conv_masked(bf(net->dz[cur]), bf(net->wb, l * CK), batch, net->H, net->W, X,
                                        bf(net->dz[cur ^ 1]), bf(net->dt), net->stream));

@@ -11,8 +11,10 @@ namespace wsn {
 
 size_t conv_lds_bytes(int W);
 
+// out = relu(conv(X) + bias); xt (or nullptr): out channel-major in three shifted
+// copies (3*B*H*W*C bf16), ready for the next layer's conv_wgrad
 hipError_t conv_relu(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H, int W,
-                     __bf16 *out, hipStream_t st);
+                     __bf16 *out, __bf16 *xt, hipStream_t st);
 hipError_t conv_softplus(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
                          int W, float *z, float *sp, hipStream_t st);
 // out = conv(X) masked by mask > 0; dt (or nullptr): the same values channel-major
@@ -23,9 +25,10 @@ hipError_t conv_masked(const __bf16 *X, const __bf16 *Wk, int B, int H, int W, c
 int wgrad_rows(int H);
 // weight and bias gradient of one layer into grad (C*9*C weights, then C biases);
 // xt: 3*B*H*W*C bf16, dt: B*H*W*C bf16, wpart: (B*H / wgrad_rows(H)) * (C*9*C + C)
-// floats (all scratch); dt_ready: dt already holds DZ channel-major (conv_masked wrote it)
+// floats (all scratch); xt_ready / dt_ready: xt already holds X's shifted copies
+// (conv_relu wrote them) / dt already holds DZ channel-major (conv_masked wrote it)
 hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt, float *dt,
-                      float *wpart, float *grad, bool dt_ready, hipStream_t st);
+                      float *wpart, float *grad, bool xt_ready, bool dt_ready, hipStream_t st);
 hipError_t to_bf16(const float *x, __bf16 *y, int64_t n, hipStream_t st);
 // per-image FP64 partial sums (n_blocks per image, image-major)
 hipError_t image_partials(const float *x, int64_t img, int n_images, int n_blocks, double *partials,

@@ -47,9 +47,12 @@ __device__ __forceinline__ int swz(int chunk, int key) { return (chunk & ~7) | (
 
 // EP_RELU: out_bf16 = relu(z + b) (hidden layer); EP_SOFTPLUS: out_z = z + b,
 // out_sp = softplus(z + b) (last layer); EP_MASK: out_bf16 = z if mask > 0
-// else 0 (gradient through the ReLU of the previous layer, no bias), and,
-// when dt_out is not null, the same values channel-major per image row
-// ([row][channel][x], the layout the weight gradient reads).
+// else 0 (gradient through the ReLU of the previous layer, no bias).  When
+// cm_out is not null, the bf16 output also goes out channel-major per image
+// row, in the layouts the weight gradient reads: for EP_MASK once
+// ([row][channel][x], its dZ), for EP_RELU in three copies shifted by
+// kx - 1 = -1, 0, 1 pixels ([row][kx][channel][x], zero outside the row:
+// the next layer's X).
 //
 // Workgroup of 8 waves (two per SIMD, so one wave's LDS reads overlap the
 // other's MFMAs), one per CU; a step is 8 output rows of one image and wave w
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restri
                                                           float *__restrict__ out_z,
                                                           float *__restrict__ out_sp,
                                                           const __bf16 *__restrict__ mask,
-                                                          __bf16 *__restrict__ dt_out) {
+                                                          __bf16 *__restrict__ cm_out) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16 *ws = reinterpret_cast<__bf16 *>(smem);                  // [co][576], swizzled chunks
     __bf16 *xs = ws + static_cast<size_t>(kC) * kK;                 // [row][pixel][64], swizzled
@@ -195,12 +198,12 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restri
                             __builtin_memcpy(&mb, &mu, 2);
                             if (!(static_cast<float>(mb) > 0.0f)) v[e] = 0;
                         }
-                        if (dt_out) *reinterpret_cast<u16x8 *>(tile + c * 8) = v;   // masked, for the copy below
+                        if (cm_out) *reinterpret_cast<u16x8 *>(tile + c * 8) = v;   // masked, for the copy below
                     }
                     *reinterpret_cast<u16x8 *>(out_bf16 + base + c * 8) = v;
                 }
             }
-            if (EP == 2 && dt_out) {
+            if (cm_out) {
                 __syncthreads();
                 if (active) {
                     // eight lanes per channel, each eight pixels of the tile's column, so every
@@ -210,10 +213,28 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restri
 #pragma unroll 2
                     for (int k = 0; k < 8; ++k) {
                         const int co = (lane >> 3) + 8 * k;
-                        u16x8 w;
+                        if (EP == 2) {
+                            u16x8 w;
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) w[j] = tu[(x8 * 8 + j) * kC + co];
-                        *reinterpret_cast<u16x8 *>(dt_out + base + static_cast<size_t>(co) * kC + x8 * 8) = w;
+                            for (int j = 0; j < 8; ++j) w[j] = tu[(x8 * 8 + j) * kC + co];
+                            *reinterpret_cast<u16x8 *>(cm_out + base + static_cast<size_t>(co) * kC + x8 * 8) = w;
+                        } else {
+                            // pixels x8 * 8 - 1 .. x8 * 8 + 8 of the channel, 0 outside the row
+                            unsigned short pv[10];
+#pragma unroll
+                            for (int j = 0; j < 10; ++j) {
+                                const int px = x8 * 8 - 1 + j;
+                                pv[j] = (px >= 0 && px < kC) ? tu[px * kC + co] : static_cast<unsigned short>(0);
+                            }
+#pragma unroll
+                            for (int sh = 0; sh < 3; ++sh) {
+                                u16x8 w;
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) w[j] = pv[j + sh];
+                                *reinterpret_cast<u16x8 *>(cm_out + 3 * base + static_cast<size_t>(sh) * kC * kC +
+                                                           static_cast<size_t>(co) * kC + x8 * 8) = w;
+                            }
+                        }
                     }
                 }
             }
@@ -518,7 +539,7 @@ int conv_workgroups() {
 
 template <int EP>
 static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
-                         int W, __bf16 *ob, float *oz, float *osp, const __bf16 *mask, __bf16 *dt,
+                         int W, __bf16 *ob, float *oz, float *osp, const __bf16 *mask, __bf16 *cm,
                          hipStream_t st) {
     const size_t lds = conv_lds_bytes(W);
     static const hipError_t raised = hipFuncSetAttribute(
@@ -529,13 +550,13 @@ static hipError_t conv_t(const __bf16 *X, const __bf16 *Wk, const float *bias, i
     // one workgroup per CU (the staged weights and rows take 155 KB of LDS)
     const int grid = std::min(n_steps, conv_workgroups());
     hipLaunchKernelGGL((k_conv3x3<EP>), dim3(static_cast<unsigned>(grid)), dim3(kConvThreads), lds, st, X, Wk,
-                       bias, B, H, ob, oz, osp, mask, dt);
+                       bias, B, H, ob, oz, osp, mask, cm);
     return hipGetLastError();
 }
 
 hipError_t conv_relu(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H, int W,
-                     __bf16 *out, hipStream_t st) {
-    return conv_t<0>(X, Wk, bias, B, H, W, out, nullptr, nullptr, nullptr, nullptr, st);
+                     __bf16 *out, __bf16 *xt, hipStream_t st) {
+    return conv_t<0>(X, Wk, bias, B, H, W, out, nullptr, nullptr, nullptr, xt, st);
 }
 hipError_t conv_softplus(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
                          int W, float *z, float *sp, hipStream_t st) {
@@ -549,7 +570,7 @@ hipError_t conv_masked(const __bf16 *X, const __bf16 *Wk, int B, int H, int W, c
 int wgrad_rows(int H) { return H % 8 == 0 ? 8 : (H % 4 == 0 ? 4 : 2); }
 
 hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt, float *dt,
-                      float *wpart, float *grad, bool dt_ready, hipStream_t st) {
+                      float *wpart, float *grad, bool xt_ready, bool dt_ready, hipStream_t st) {
     const int rows = B * H;
     if (rows == 0) return hipSuccess;
     __bf16 *XT = reinterpret_cast<__bf16 *>(xt);
@@ -559,8 +580,10 @@ hipError_t conv_wgrad(const __bf16 *X, const __bf16 *DZ, int B, int H, float *xt
         hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, DZ, 1, DT);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, X, 3, XT);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!xt_ready) {
+        hipLaunchKernelGGL(k_rows_cmajor, dim3(static_cast<unsigned>(rows)), dim3(256), 0, st, X, 3, XT);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const int R = wgrad_rows(H);
     const int nb = rows / R;
     if (R > kWgradMaxRows) return hipErrorInvalidValue;
