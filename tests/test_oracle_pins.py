@@ -439,6 +439,81 @@ def test_kkt_at_convergence(seed):
     assert rep[-1, 3] <= tol and rep[-1, 4] <= tol
 
 
+def groups_of_rows(ny, nx, Q, grouping):
+    """Group of every row (s, p, q) of D: the spatial bin s (spectral grouping)
+    or the voxel (s, q) (standard TV), and the number of groups."""
+    rho = np.arange(ny * nx * 4 * Q)
+    s, q = rho // (4 * Q), rho % Q
+    return (s, ny * nx) if grouping == 0 else (s * Q + q, ny * nx * Q)
+
+
+def smoothed_objective_general(prob, A, D, eps, beta, grp, n_groups):
+    def fun(f):
+        p = A @ f + prob.r
+        data = np.sum(p - prob.y + np.where(prob.y > 0, prob.y * np.log(np.where(prob.y > 0, prob.y, 1) / p), 0))
+        g = D @ f
+        nrm = np.sqrt(np.bincount(grp, g * g, minlength=n_groups) + eps * eps)
+        return data + beta * nrm.sum(), A.T @ (1 - prob.y / p) + beta * (D.T @ (g / nrm[grp]))
+    return fun
+
+
+W4 = np.array([1.0, 0.7, 1.3, 0.9])
+
+
+@pytest.mark.parametrize("seed,shape,grouping,weighted", [(5, (2, 2, 2), 1, False), (6, (2, 3, 2), 1, False),
+                                                          (7, (2, 2, 3), 0, True), (8, (1, 3, 2), 1, True)])
+def test_converged_value_brackets_brute_force_standard_tv_and_weights(seed, shape, grouping, weighted):
+    """P11 for standard TV (groups of four differences per voxel) and for
+    direction weights (w G f in the penalty and in the constraint)."""
+    ny, nx, Q = shape
+    J = ny * nx * Q
+    prob, A = tiny_problem(seed, ny=ny, nx=nx, Q=Q, I=max(6, J - 2), beta=0.5)
+    w4 = W4 if weighted else None
+    wfull = np.broadcast_to(W4[None, :, None], (ny * nx, 4, Q)).ravel() if weighted else None
+    D = explicit_D(ny, nx, Q, wfull)
+    grp, n_groups = groups_of_rows(ny, nx, Q, grouping)
+    f, d, c, rep = oracle.admm(prob, 20000, w=w4, grouping=grouping)
+    phi_admm = oracle.objective(prob, f, w=w4, grouping=grouping)[0]
+    eps = 1e-5
+    fun = smoothed_objective_general(prob, A, D, eps, prob.beta, grp, n_groups)
+    best = None
+    for x0 in (np.ones(J), f + 1e-3, np.full(J, 3.0)):
+        res = so.minimize(fun, x0, jac=True, method="L-BFGS-B", bounds=[(0, None)] * J,
+                          options=dict(ftol=1e-16, gtol=1e-13, maxiter=50000, maxcor=30))
+        best = res.fun if best is None else min(best, res.fun)
+    tol = 1e-9 * abs(best)
+    assert phi_admm <= best + tol
+    assert phi_admm >= best - prob.beta * n_groups * eps - tol
+
+
+@pytest.mark.parametrize("seed,grouping,weighted", [(9, 1, False), (10, 0, True), (11, 1, True)])
+def test_kkt_at_convergence_standard_tv_and_weights(seed, grouping, weighted):
+    """P12 for standard TV and direction weights: stationarity with D the
+    weighted operator, d = D f, and per group lam ||c_g|| <= beta with
+    lam c_g = beta d_g / ||d_g|| where d_g is not zero."""
+    prob, A = tiny_problem(seed, ny=2, nx=3, Q=2, I=10, beta=0.3)
+    ny, nx, Q = prob.ny, prob.nx, prob.Q
+    w4 = W4 if weighted else None
+    wfull = np.broadcast_to(W4[None, :, None], (ny * nx, 4, Q)).ravel() if weighted else None
+    D = explicit_D(ny, nx, Q, wfull)
+    lam = prob.rho
+    f, d, c, rep = oracle.admm(prob, 30000, w=w4, grouping=grouping)
+    grad = A.T @ (1 - prob.y / (A @ f + prob.r)) + lam * (D.T @ c)
+    tol = 1e-7
+    pos = f > 1e-9
+    assert np.all(np.abs(grad[pos]) <= tol)
+    assert np.all(grad[~pos] >= -tol)
+    assert np.linalg.norm(D @ f - d) <= tol
+    grp, n_groups = groups_of_rows(ny, nx, Q, grouping)
+    for gi in range(n_groups):
+        idx = grp == gi
+        assert lam * np.linalg.norm(c[idx]) <= prob.beta + tol
+        nd = np.linalg.norm(d[idx])
+        if nd > 1e-9:
+            np.testing.assert_allclose(lam * c[idx], prob.beta * d[idx] / nd, atol=tol)
+    assert rep[-1, 3] <= tol and rep[-1, 4] <= tol
+
+
 def test_report_matches_definitions():
     prob, A = tiny_problem(6, ny=2, nx=2, Q=3, I=9, beta=0.2)
     D = explicit_D(prob.ny, prob.nx, prob.Q)
