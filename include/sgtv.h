@@ -31,8 +31,10 @@
  * message for the last failing call on the calling thread.
  *
  * Ownership: every pointer argument belongs to the caller and is read (or
- * written) only during the call; the library copies what it keeps into its
- * own device memory.  mem_kind says whether a pointer is host memory
+ * written) only during the call; the library copies what it keeps into
+ * device memory it allocates itself, or into the caller's workspace after
+ * sgtv_commit_system (the one exception: that buffer is used for the
+ * context's lifetime).  mem_kind says whether a pointer is host memory
  * (SGTV_HOST) or device memory of the context's GPU (SGTV_DEVICE).  All work
  * is ordered on the stream given to sgtv_create; functions that return data
  * to the host synchronise that stream.
