@@ -336,12 +336,16 @@ int sgtv_backprojection_noalloc(sgtv_ctx ctx, float *x, int mem_kind);
  *     flight per wave, 2 two batches, 3 two batches plus the next column block
  *     read ahead into registers (0: automatic).  Variant 1 stores the
  *     entries' indices in 24 bits (three bytes per entry instead of four)
- *     when 64 <= rows_per_wave <= 1024 and block_cols <= 16380.
+ *     when 64 <= rows_per_wave <= 1024 and block_cols <= 16380, or
+ *     1024 < rows_per_wave <= 2048 and block_cols <= 8188.
  * Limits: waves in [1, 16]; rows_per_wave in [1, 32767]; block_cols a
  * multiple of 4 in [4, 65536]; slabs in [1, 16]; the LDS of one workgroup,
- * 4 * (waves * (rows_per_wave + 1) rounded up to 4 + block_cols) + 16 bytes,
- * at most 163840.  Violations give SGTV_EINVAL at set_schedule (field ranges) or
- * set_system (LDS size).
+ * 4 * (waves * rows_per_wave rounded up to 4 + block_cols) + 16 bytes with
+ * 24-bit indices, 4 * (waves * (rows_per_wave + 1) rounded up to 4 +
+ * block_cols) bytes with 32-bit ones, at most 163840.  Violations give
+ * SGTV_EINVAL at set_schedule (field ranges) or set_system (LDS size).  The
+ * persistent batch launch keeps 16 bytes of LDS of its own and refuses tiles
+ * that leave less (sgtv_batch_iterate returns SGTV_EDEVICE).
  */
 enum { SGTV_FORMAT_TILED = 0, SGTV_FORMAT_SELL = 1 };
 typedef struct {

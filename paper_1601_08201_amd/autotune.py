@@ -20,10 +20,19 @@ CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules
 MAX_LDS = 163840
 
 
-def lds_bytes(waves, rw, cb):
-    a = waves * (rw + 1) * 4
+def idx24_fits(rw, cb):
+    """Whether the simple loop stores this tile's indices in 24 bits: row in
+    10 bits and column in 14 up to 1024 rows per wave, 11 and 13 up to 2048."""
+    return 64 <= rw <= 2048 and cb % 4 == 0 and cb <= (1 << (14 if rw <= 1024 else 13)) - 4
+
+
+def lds_bytes(waves, rw, cb, variant=1):
+    """LDS of one workgroup: the row sums (a spare row per wave with 32-bit
+    indices), the column block and the zero slot of the 24-bit format."""
+    i24 = variant == 1 and idx24_fits(rw, cb)
+    a = waves * (rw + (0 if i24 else 1)) * 4
     a = (a + 15) // 16 * 16
-    return a + cb * 4
+    return a + cb * 4 + (16 if i24 else 0)
 
 
 def shape_key(I, ny, nx, Q, nnz):
@@ -37,8 +46,8 @@ def candidates(I, J, waves=16, per_side=10):
 
     def side(n_rows, n_cols):
         out = []
-        for rw in (64, 128, 256, 512, 1024):
-            for cb in (4096, 8192, 16380):
+        for rw in (64, 128, 256, 512, 1024, 2048):
+            for cb in (4096, 8188, 16380):
                 cb_eff = min(cb, max(4, 1 << (max(n_cols, 4) - 1).bit_length()))
                 if lds_bytes(waves, rw, cb_eff) > MAX_LDS:
                     continue

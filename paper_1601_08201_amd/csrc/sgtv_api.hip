@@ -279,10 +279,10 @@ TileParams choose_tiles(int64_t n_rows, int64_t n_cols, int waves, int rw, int c
     return t;
 }
 
-size_t tile_lds_bytes(const TileParams &t) {
-    size_t a = static_cast<size_t>(t.waves) * (t.rw + 1) * 4;
-    a = (a + 15) / 16 * 16;
-    return a + static_cast<size_t>(t.cb) * 4 + 16;   // + the zero slot of the 24-bit format
+// LDS of a workgroup of the tiled product; idx24: the inner loop reads 24-bit
+// indices where the tile fits them
+size_t tile_lds_bytes(const TileParams &t, bool idx24) {
+    return sgtv::tiled_lds_bytes(t.waves, t.rw, t.cb, idx24 && sgtv::idx24_fits(t.rw, t.cb));
 }
 
 // Wall times of the steps of the host-side packing, printed to stderr when
@@ -383,12 +383,13 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
                 const std::vector<int32_t> &ci, const std::vector<V> &vals, const TileParams &t,
                 bool idx24, std::vector<int32_t> &pk, std::vector<V> &pv, std::vector<int32_t> &goff,
                 std::vector<int32_t> &poff, std::vector<uint16_t> &slot_of, sgtv::TileMap &map) {
-    // 24-bit indices: row in 10 bits, column in 14 with the code cb left for
-    // the zero slot.  Their lists are lane-owned: all entries of a row within a
-    // list sit in one lane, in row order, so a lane can read every accumulator
-    // of a window of entries at once (no other lane touches its rows)
-    idx24 = idx24 && t.rw >= 64 && t.rw <= 1024 && t.cb % 4 == 0 && t.cb <= 16380;
-    const int row_shift = idx24 ? 14 : 16;
+    // 24-bit indices: row in 10 bits and column in 14 (up to 1024 rows per
+    // wave), or 11 and 13 (up to 2048), with the code cb left for the zero
+    // slot.  Their lists are lane-owned: all entries of a row within a list sit
+    // in one lane, in row order, so a lane can read every accumulator of a
+    // window of entries at once (no other lane touches its rows)
+    idx24 = idx24 && sgtv::idx24_fits(t.rw, t.cb);
+    const int row_shift = idx24 ? sgtv::idx24_col_bits(t.rw) : 16;
     SetupClock clk;
     const int64_t RB = static_cast<int64_t>(t.waves) * t.rw;
     const int64_t n_rb = (n_rows + RB - 1) / RB;
@@ -410,10 +411,10 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     // smaller total, then lower wave).  slot_of[tile * RB + i] is the slot
     // w * rw + l of row offset i (the kernel writes the row sums out in row
     // order through it).  The 32-bit lists, and schedules whose per-row-block
-    // counts would pass 2^22 (tiny column blocks of a large matrix), keep row
+    // counts would pass 2^24 (tiny column blocks of a large matrix), keep row
     // offset i in slot i.
     slot_of.clear();
-    const bool balance = idx24 && static_cast<int64_t>(ns) * RB * cbs_max <= (int64_t(1) << 22);
+    const bool balance = idx24 && static_cast<int64_t>(ns) * RB * cbs_max <= (int64_t(1) << 24);
     if (balance) {
         slot_of.assign(static_cast<size_t>(n_rb * ns * RB), 0);
         // row blocks are independent: each worker takes every nth one
@@ -760,6 +761,7 @@ int build_tiled(int64_t n_rows, int64_t n_cols, const std::vector<int64_t> &rp,
     map.ns = ns;
     map.cbs_max = cbs_max;
     map.variant = 0;
+    map.cbits = idx24 ? row_shift : 0;
     for (int k = 0; k <= ns; ++k) map.slab_begin[k] = slab_begin[k];
     return SGTV_OK;
 }
@@ -1141,7 +1143,8 @@ int pack_system(sgtv_ctx_s *c, Packed &PK, int64_t I, int32_t ny, int32_t nx, in
         const sgtv_schedule &q = c->want;
         const TileParams tf = choose_tiles(I, J, q.waves, q.fwd_rows_per_wave, q.fwd_block_cols, q.fwd_slabs);
         const TileParams tb = choose_tiles(J, I, q.waves, q.back_rows_per_wave, q.back_block_cols, q.back_slabs);
-        if (tile_lds_bytes(tf) > 163840 || tile_lds_bytes(tb) > 163840)
+        const bool var1 = q.variant <= 1;   // the simple loop, the only one on 24-bit indices
+        if (tile_lds_bytes(tf, var1) > 163840 || tile_lds_bytes(tb, var1) > 163840)
             return fail(SGTV_EINVAL, "schedule needs more than 160 KiB of LDS per workgroup");
         S->sched.waves = tf.waves;
         S->sched.fwd_rows_per_wave = tf.rw; S->sched.fwd_block_cols = tf.cb; S->sched.fwd_slabs = tf.ns;
@@ -1703,7 +1706,7 @@ namespace {
 // per host thread, and every chunk is hashed on the way; an array's hash
 // folds its chunk hashes in order, so it does not depend on the threads.
 constexpr char kSysMagic[8] = {'S', 'G', 'T', 'V', 'S', 'Y', 'S', '1'};
-constexpr uint32_t kSysVersion = 2;
+constexpr uint32_t kSysVersion = 3;
 constexpr size_t kIoChunk = size_t(8) << 20;
 constexpr int kSysArrays = 20;
 
@@ -2468,7 +2471,7 @@ int64_t sgtv_workspace_bytes(int64_t I, int64_t J, int64_t nnz, int storage_dtyp
         const double e = static_cast<double>(nnz) / lists;
         const double groups = std::max(std::ceil(e / 64.0) + 1.0, std::ceil(lam + 2.5 * std::sqrt(lam) + 1.0));
         const double stored = std::min(lists * 64.0 * groups, 64.0 * static_cast<double>(nnz) + 256.0);
-        const bool i24 = t.rw >= 64 && t.rw <= 1024 && t.cb <= 16380;
+        const bool i24 = sgtv::idx24_fits(t.rw, t.cb);
         const double idx_bytes = i24 ? 3.0 : 4.0;
         // 24-bit lists also keep the row order of every tile (2 bytes per row and slab)
         const double order = i24 ? 2.0 * n_rb * 16.0 * t.rw * t.ns : 0.0;

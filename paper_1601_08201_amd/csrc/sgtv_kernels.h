@@ -47,6 +47,22 @@ struct Sell {
 // column block, wave) list are stored in groups of 64 with 64 distinct rows,
 // four groups interleaved per 16-byte load; packed index = row << 16 | col.
 constexpr int kMaxSlabs = 16;
+
+// The 24-bit index format: e = row << c | column with c = 14 column bits for
+// up to 1024 rows per wave and c = 13 for up to 2048; the widest block leaves
+// code cb for the zero slot (cb a multiple of 4, at most 2^c - 4).
+inline int idx24_col_bits(int rw) { return rw <= 1024 ? 14 : 13; }
+inline bool idx24_fits(int rw, int cb) {
+    return rw >= 64 && rw <= 2048 && cb % 4 == 0 && cb <= (1 << idx24_col_bits(rw)) - 4;
+}
+// LDS of one tiled workgroup: the row sums (a spare padding row per wave with
+// 32-bit indices), then the column block (and the zero slot with 24-bit ones)
+inline size_t tiled_lds_bytes(int waves, int rw, int cb, bool idx24) {
+    size_t a = static_cast<size_t>(waves) * (rw + (idx24 ? 0 : 1)) * 4;
+    a = (a + 15) / 16 * 16;
+    return a + static_cast<size_t>(cb) * 4 + (idx24 ? 16 : 0);
+}
+
 struct TileMap {
     const int32_t *pk;      // packed (row in wave, column in block), padding: row = rw
     const void *val;        // values or 16-bit codes, padding: 0
@@ -54,19 +70,16 @@ struct TileMap {
     const int32_t *poff;    // 24-bit indices: offset (in dwords) of every list's indices
     const uint16_t *slot;   // 24-bit indices: per tile, the slot w * rw + l (wave w, row l
                             // in the wave) of every row of the row block; nullptr: identity
-    int idx24;              // 1: indices row << 14 | column, three dwords per lane and batch;
+    int idx24;              // 1: indices row << cbits | column, three dwords per lane and batch;
                             // padding: a row unused in its group, column cb (a zero in LDS)
     int64_t n_rows, n_cols;
     int64_t n_rb;           // row blocks
     int64_t pad;            // entry offset of one all-padding batch (256 entries)
     int rw, waves, cb, ns, cbs_max;
     int variant;            // kernel variant (0 simple, 1 pipelined, 2 + block prefetch)
+    int cbits;              // 24-bit indices: column bits (idx24_col_bits(rw))
     int slab_begin[kMaxSlabs + 1];   // first column block of each slab
-    size_t lds_bytes() const {
-        size_t a = static_cast<size_t>(waves) * (rw + 1) * 4;
-        a = (a + 15) / 16 * 16;
-        return a + static_cast<size_t>(cb) * 4 + (idx24 ? 16 : 0);
-    }
+    size_t lds_bytes() const { return tiled_lds_bytes(waves, rw, cb, idx24 != 0); }
 };
 
 // Batched launches: one work item per workgroup.

@@ -27,9 +27,10 @@ constexpr int kXPrefetch = 4;
 // the wave's LDS accumulators; rows within a group are distinct.
 //
 // Index formats.  32-bit: one dword (row << 16 | column) per entry, padding
-// in the extra row rw.  24-bit (64 <= rows per wave <= 1024, block columns a
-// multiple of 4 up to 16380): e = row << 14 | column, padding in a row the
-// group does not use, reading the zero at column cb; and
+// in the extra row rw.  24-bit (64 <= rows per wave <= 2048, block columns a
+// multiple of 4 up to 2^c - 4): e = row << c | column with c = 14 column bits
+// (up to 1024 rows per wave) or 13 (up to 2048), padding in a row the group
+// does not use, reading the zero at column cb; and
 // the four entries a lane holds in one batch share three dwords
 // w0 = e0 | e1 << 24, w1 = e1 >> 8 | e2 << 16, w2 = e2 >> 16 | e3 << 8.  Four
 // consecutive batches form a super-batch whose 12 dwords per lane are stored
@@ -54,19 +55,20 @@ __device__ __forceinline__ void tile_batch(const v4i p, const typename Code<VT>:
 // sums keep their order: entry after entry).
 template <int VT, int N>
 __device__ __forceinline__ void window24(const uint32_t (&e)[N], const typename Code<VT>::T (&a)[N],
-                                         const float *xs, float *my) {
+                                         const float *xs, float *my, uint32_t cbits) {
+    const uint32_t cmask = (1u << cbits) - 1u;
     float t[N], m[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) t[i] = xs[e[i] & 0x3FFF];
+    for (int i = 0; i < N; ++i) t[i] = xs[e[i] & cmask];
 #pragma unroll
-    for (int i = 0; i < N; ++i) m[i] = my[e[i] >> 14];
+    for (int i = 0; i < N; ++i) m[i] = my[e[i] >> cbits];
     float run = 0.0f;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        const uint32_t row = e[i] >> 14;
-        const bool cont = i > 0 && row == (e[i - 1] >> 14);
+        const uint32_t row = e[i] >> cbits;
+        const bool cont = i > 0 && row == (e[i - 1] >> cbits);
         run = fmaf(Code<VT>::dec(a[i]), t[i], cont ? run : m[i]);
-        if (i + 1 == N || (e[i + 1] >> 14) != row) my[row] = run;
+        if (i + 1 == N || (e[i + 1] >> cbits) != row) my[row] = run;
     }
 }
 
@@ -81,11 +83,11 @@ __device__ __forceinline__ void unpack4(uint32_t w0, uint32_t w1, uint32_t w2, u
 template <int VT>
 __device__ __forceinline__ void tile_batch24(uint32_t w0, uint32_t w1, uint32_t w2,
                                              const typename Code<VT>::V4 a, const float *xs,
-                                             float *my) {
+                                             float *my, uint32_t cbits) {
     uint32_t e[4];
     unpack4(w0, w1, w2, e);
     const typename Code<VT>::T av[4] = {a.x, a.y, a.z, a.w};
-    window24<VT, 4>(e, av, xs, my);
+    window24<VT, 4>(e, av, xs, my, cbits);
 }
 
 // one super-batch (16 entries per lane: three 16-byte index planes, four value batches)
@@ -95,7 +97,7 @@ __device__ __forceinline__ void tile_super24(const U4 A, const U4 B, const U4 C,
                                              const typename Code<VT>::V4 a1,
                                              const typename Code<VT>::V4 a2,
                                              const typename Code<VT>::V4 a3, const float *xs,
-                                             float *my) {
+                                             float *my, uint32_t cbits) {
     uint32_t e[16];
     unpack4(A.x, A.y, A.z, e);
     unpack4(A.w, B.x, B.y, e + 4);
@@ -103,7 +105,7 @@ __device__ __forceinline__ void tile_super24(const U4 A, const U4 B, const U4 C,
     unpack4(C.y, C.z, C.w, e + 12);
     const typename Code<VT>::T av[16] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
                                          a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
-    window24<VT, 16>(e, av, xs, my);
+    window24<VT, 16>(e, av, xs, my, cbits);
 }
 
 // MODE 0: one batch at a time, the next column block staged after the
@@ -124,7 +126,9 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     typedef typename Code<VT>::T T;
     typedef typename Code<VT>::V4 V4;
     extern __shared__ float lds[];
-    const int rw1 = M.rw + 1;
+    // row sums: rw per wave, plus the padding row of the 32-bit format
+    const int rw1 = M.rw + (M.idx24 ? 0 : 1);
+    const uint32_t cbits = static_cast<uint32_t>(M.cbits);
     float *acc = lds;
     const size_t acc_floats = (static_cast<size_t>(M.waves) * rw1 + 3) / 4 * 4;
     float *xs = lds + acc_floats;
@@ -162,7 +166,10 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
 
     // the next column block is read into registers before the block barrier
     // (so its latency overlaps the wait there): MODE 2, and the simple loop on
-    // 24-bit lists when the block fits the prefetch registers
+    // 24-bit lists when the block fits the prefetch registers.  All kXPrefetch
+    // loads are issued unconditionally (a chunk past a narrow block rereads
+    // the block's first float4): loads under a branch would be waited for
+    // where the branches join, before the barrier
     const bool pre = PREFETCH && (MODE == 2 || (MODE == 0 && M.idx24 && M.cb <= kXPrefetch * 4 * nthr));
     for (int c = 0; c < ncbs; ++c) {
         const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
@@ -192,7 +199,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
                 const V4 a1 = __builtin_nontemporal_load(v4 + (4 * sb + 1) * kWave);
                 const V4 a2 = __builtin_nontemporal_load(v4 + (4 * sb + 2) * kWave);
                 const V4 a3 = __builtin_nontemporal_load(v4 + (4 * sb + 3) * kWave);
-                tile_super24<VT>(A, B, C, a0, a1, a2, a3, xs, my);
+                tile_super24<VT>(A, B, C, a0, a1, a2, a3, xs, my, cbits);
             }
             const uint32_t *q2 = p3 + static_cast<int64_t>(nsb) * 12 * kWave;
             const v2u *qa = reinterpret_cast<const v2u *>(q2) + lane;
@@ -202,7 +209,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
                 const v2u w01 = __builtin_nontemporal_load(qa + rb4 * (3 * kWave / 2));
                 const uint32_t w2 = __builtin_nontemporal_load(qb + rb4 * 3 * kWave);
                 const V4 a = __builtin_nontemporal_load(v4 + b * kWave);
-                tile_batch24<VT>(w01.x, w01.y, w2, a, xs, my);
+                tile_batch24<VT>(w01.x, w01.y, w2, a, xs, my, cbits);
             }
         } else if (MODE == 0) {
             for (int b = 0; b < nb4; ++b) {
@@ -238,8 +245,8 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
             for (int g = nb4 * 4; g < ng; ++g) {
                 const uint32_t p = __builtin_nontemporal_load(pt + (g - nb4 * 4) * kWave);
                 const T a = __builtin_nontemporal_load(val + tail + static_cast<int64_t>(g - nb4 * 4) * kWave);
-                const float t = xs[p & 0x3FFF];
-                my[p >> 14] = fmaf(Code<VT>::dec(a), t, my[p >> 14]);
+                const float t = xs[p & ((1u << cbits) - 1u)];
+                my[p >> cbits] = fmaf(Code<VT>::dec(a), t, my[p >> cbits]);
             }
         } else {
             for (int g = nb4 * 4; g < ng; ++g) {
@@ -743,7 +750,8 @@ hipError_t persistent_grid(int variant, int threads, size_t lds, int *grid, cons
     *what = "hipOccupancyMaxActiveBlocksPerMultiprocessor";
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
     if (e != hipSuccess) return e;
-    *what = "occupancy of the persistent kernel";
+    *what = "occupancy of the persistent kernel (the largest tile's LDS and the kernel's own 16 bytes "
+            "must fit the 160 KiB of a CU)";
     if (per_cu < 1 || cus < 1) return hipErrorCooperativeLaunchTooLarge;
     *grid = per_cu * cus;
     return hipSuccess;

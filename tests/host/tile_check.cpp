@@ -156,7 +156,8 @@ void check_case(const char *name, const Csr &m, TileParams t, bool want24, bool 
                                     ((w1 >> 16) | (w2 << 16)) & 0xFFFFFFu, w2 >> 8};
             code = e4[m4];
         };
-        const int sh = map.idx24 ? 14 : 16;
+        CHECK(!map.idx24 || map.cbits == (t.rw <= 1024 ? 14 : 13), "%s: column bits %d", name, map.cbits);
+        const int sh = map.idx24 ? map.cbits : 16;
         const uint32_t cmask = (1u << sh) - 1;
         std::map<int64_t, int> owner;             // local row -> lane (24-bit lists)
         std::vector<std::vector<int64_t>> lane_rows(64);
@@ -264,7 +265,7 @@ int main() {
     const Csr b = make_csr(3000, 4000, 24, 2, true);
     check_case("24-bit, long row runs and duplicates", b, TileParams{64, 8, 512, 1}, true, true);
     const Csr c = make_csr(2048, 200000, 30, 3, false);
-    check_case("24-bit, counts past 2^22: contiguous rows", c, TileParams{64, 16, 12, 1}, true, false);
+    check_case("24-bit, counts past 2^24: contiguous rows", c, TileParams{64, 16, 12, 1}, true, false);
     check_threads("threads, 24-bit dealt rows", a, TileParams{64, 4, 1024, 2});
     check_threads("threads, 32-bit", a, TileParams{100, 4, 1023, 2});
     check_threads("threads, long row runs", b, TileParams{64, 8, 512, 1});
@@ -281,6 +282,13 @@ int main() {
     check_case("24-bit, one row", one_row, TileParams{64, 4, 1024, 2}, true, true);
     const Csr one_col = make_csr(3000, 1, 1, 6, false);
     check_case("24-bit, one column", one_col, TileParams{64, 4, 4, 1}, true, true);
+    // 11-bit rows and 13-bit columns: up to 2048 rows per wave, blocks of at
+    // most 8188 columns; wider blocks take the 32-bit format
+    const Csr f = make_csr(9000, 20000, 40, 7, true);
+    check_case("24-bit, 2048 rows per wave, dealt rows", f, TileParams{2048, 4, 8188, 2}, true, true);
+    check_case("24-bit, 1500 rows per wave, dealt rows", f, TileParams{1500, 3, 4000, 3}, true, true);
+    check_case("32-bit, 2048 rows per wave, 8192-column blocks", f, TileParams{2048, 2, 8192, 2}, false, false);
+    check_threads("threads, 2048 rows per wave", f, TileParams{2048, 4, 8188, 2});
     if (failures) return 1;
     std::printf("ok\n");
     return 0;

@@ -154,6 +154,45 @@ def test_persistent_launch_weights_and_groupings(sg):
         assert err <= 1e-5
 
 
+def test_batch_of_mixed_tile_formats(sg):
+    """Scans with 24-bit indices of 14 and of 13 column bits (1024 and 2048
+    rows per wave) and with 32-bit indices in one batch: graph and persistent
+    launches both reproduce every scan's single run bit for bit.  A tile that
+    fills the whole 160 KiB of LDS (16 waves of 2048 rows, 8188-column
+    blocks) runs in the graph launch; the persistent kernel, which keeps 16
+    bytes of LDS of its own, refuses it."""
+    probs = scans()[:3]
+    full = [dict(fwd_rows_per_wave=1024, back_rows_per_wave=512, fwd_block_cols=4096, back_block_cols=16380),
+            dict(fwd_rows_per_wave=2048, back_rows_per_wave=2048, fwd_block_cols=8188, back_block_cols=1000),
+            dict(fwd_rows_per_wave=1024, back_rows_per_wave=1500, fwd_block_cols=16384, back_block_cols=8192)]
+    fits = [dict(s) for s in full]
+    fits[1]["fwd_block_cols"] = 4000
+    for launch, scheds in (("graph", full), ("persistent", fits)):
+        B = sg.Batch()
+        for p, s in zip(probs, scheds):
+            B.add_scan(p, schedule=s)
+        B.set_launch(launch)
+        B.iterate(25)
+        for i, (p, s) in enumerate(zip(probs, scheds)):
+            R = sg.Reconstructor()
+            R.set_schedule(**s)
+            R.set_problem(p)
+            R.iterate(25)
+            print(launch, "scan", i, R.schedule(), flush=True)
+            np.testing.assert_array_equal(B.image(i), R.image())
+            assert B.objective(i) == R.objective()
+            R.close()
+        B.close()
+    B = sg.Batch()
+    for p, s in zip(probs, full):
+        B.add_scan(p, schedule=s)
+    B.set_launch("persistent")
+    with pytest.raises(sg.SgtvError) as ei:
+        B.iterate(1)
+    print("refused:", ei.value, flush=True)
+    B.close()
+
+
 def test_launch_mode_is_checked(sg):
     B = sg.Batch()
     assert B.launch() == ("graph", 0)

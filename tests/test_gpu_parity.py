@@ -97,6 +97,14 @@ SCHEDULES = {
                             back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=2),
     "tiles-prefetch": dict(format=0, waves=8, fwd_rows_per_wave=128, fwd_block_cols=2048, fwd_slabs=2,
                            back_rows_per_wave=256, back_block_cols=1024, back_slabs=2, variant=3),
+    # 24-bit indices with 11-bit rows and 13-bit columns: 2048 rows per wave
+    # and an 8188-column block (ragged 4-column tail), 1536 rows per wave over
+    # two ragged row blocks
+    "tiles-2048-rows": dict(format=0, waves=4, fwd_rows_per_wave=2048, fwd_block_cols=8188, fwd_slabs=1,
+                            back_rows_per_wave=1536, back_block_cols=1000, back_slabs=2),
+    # blocks too wide for 13-bit columns: the 32-bit format at 2048 rows per wave
+    "tiles-2048-rows-32bit": dict(format=0, waves=2, fwd_rows_per_wave=2048, fwd_block_cols=16380,
+                                  fwd_slabs=1, back_rows_per_wave=2048, back_block_cols=8192, back_slabs=2),
 }
 
 
@@ -104,6 +112,31 @@ SCHEDULES = {
 def test_schedules_agree_with_oracle(sg, name):
     prob = datagen.make_problem("small", 11)
     check_against_oracle(sg, prob, 30, schedule=SCHEDULES[name])
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_full_lds_tiles_of_2048_rows(sg, storage):
+    """16 waves of 2048 rows with 8188-column blocks fill the 160 KiB of LDS
+    (128 KiB of row sums, 32 KiB of block) on the 64^3 scanner (262144 voxels,
+    131072 measurements); 16-bit values against the oracle on the quantised
+    matrix."""
+    prob = datagen.make_problem("warmstart", 3)
+    sched = dict(format=0, waves=16, fwd_rows_per_wave=2048, fwd_block_cols=8188, fwd_slabs=4,
+                 back_rows_per_wave=2048, back_block_cols=8188, back_slabs=2)
+    if storage == "f32":
+        check_against_oracle(sg, prob, 20, schedule=sched)
+        return
+    R = run_gpu(sg, prob, 20, storage=storage, schedule=sched)
+    got = R.schedule()
+    assert got["fwd_rows_per_wave"] == 2048 and got["back_block_cols"] == 8188
+    import copy
+    q = copy.copy(prob)
+    q.val = oracle.quantise(prob.col, prob.val, prob.J, storage)[2]
+    f_o = oracle.admm(q, 20, report=False)[0]
+    err = rel_l2(R.image(), f_o)
+    print("bf16 values, 2048-row tiles: rel_l2 vs oracle on the quantised matrix", err, flush=True)
+    assert err <= IMG_TOL
+    R.close()
 
 
 def test_non_square_grid_and_ragged_tails(sg):
