@@ -159,12 +159,14 @@ def cached_batch_schedule(probs, path=CACHE_PATH):
     return rec["schedule"] if rec else None
 
 
-def _time_schedule(prob, sched, reps):
+def _time_schedule(prob, sched, reps, warmup=10):
+    """Average forward and back product times (us) over `reps` iterations
+    after `warmup` iterations, HIP events around every launch."""
     R = sgtv.Reconstructor()
     R.set_schedule(format=0, **sched)
     R.set_problem(prob)
     R.set_graphs(False)
-    R.iterate(1)
+    R.iterate(warmup)
     R.set_profiling(True)
     R.iterate(reps)
     t = R.kernel_times()
@@ -172,14 +174,43 @@ def _time_schedule(prob, sched, reps):
     return t["forward"][0] / t["forward"][1] * 1e3, t["back"][0] / t["back"][1] * 1e3
 
 
-def tune(prob, reps=8, max_candidates=10, variants=(1,), log=None, cache_path=CACHE_PATH):
-    """Time candidate schedules on the device; return (schedule dict, report)."""
+def _time_iteration(prob, sched, reps, warmup=10):
+    """Milliseconds per ADMM iteration (graph replay of `reps` iterations
+    after `warmup`): the products and the ratio and update kernels, whose
+    partial-sum reads grow with the slab counts."""
+    import torch
+    R = sgtv.Reconstructor()
+    R.set_schedule(format=0, **sched)
+    R.set_problem(prob)
+    R.iterate(warmup)
+    R.prepare(reps)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    R.iterate(reps)
+    b.record()
+    torch.cuda.synchronize()
+    R.close()
+    return a.elapsed_time(b) / reps
+
+
+def tune(prob, reps=20, max_candidates=10, variants=(1,), log=None, cache_path=CACHE_PATH, finalists=2,
+         iter_reps=100):
+    """Time candidate schedules on the device; return (schedule dict, report).
+
+    Every candidate's forward and back products are timed; the `finalists`
+    fastest parameters of each product are then combined and the whole
+    iteration of every combination is timed, and the fastest iteration wins
+    (more slabs make the products faster but give the ratio and image update
+    more partial sums to add)."""
+    import torch
+    torch.cuda.init()   # before the library's first HIP call (the iteration timing uses torch events)
     I, J = prob.I, prob.J
     fw, bk = candidates(I, J, per_side=max_candidates)
     # pair forward and back candidates so each build measures both products
     n = max(len(fw), len(bk))
     pairs = [(fw[k % len(fw)], bk[k % len(bk)]) for k in range(n)][:max_candidates]
-    best_f, best_b = None, None
+    timed_f, timed_b = [], []
     report = []
     t0 = time.time()
     for (f, b) in pairs:
@@ -194,24 +225,39 @@ def tune(prob, reps=8, max_candidates=10, variants=(1,), log=None, cache_path=CA
             report.append(dict(schedule=sched, forward_us=tf, back_us=tb))
             if log:
                 log("autotune %s: forward %.1f us, back %.1f us" % (json.dumps(sched), tf, tb))
-            if best_f is None or tf < best_f[0]:
-                best_f = (tf, f, v)
-            if best_b is None or tb < best_b[0]:
-                best_b = (tb, b, v)
-    if best_f is None:
+            timed_f.append((tf, f, v))
+            timed_b.append((tb, b, v))
+    if not timed_f:
         return {}, report
-    # one variant per launch family: take the forward product's
-    best = dict(waves=16, variant=best_f[2],
-                fwd_rows_per_wave=best_f[1][0], fwd_block_cols=best_f[1][1], fwd_slabs=best_f[1][2],
-                back_rows_per_wave=best_b[1][0], back_block_cols=best_b[1][1], back_slabs=best_b[1][2])
+    # finalists of each product (distinct parameters, fastest first), combined
+    def top(timed):
+        out, seen = [], set()
+        for t in sorted(timed, key=lambda e: e[0]):
+            if (t[1], t[2]) not in seen:
+                seen.add((t[1], t[2]))
+                out.append(t)
+        return out[:finalists]
+    best = None
+    for ff in top(timed_f):
+        for bb in top(timed_b):
+            # one variant per launch family: take the forward product's
+            sched = dict(waves=16, variant=ff[2],
+                         fwd_rows_per_wave=ff[1][0], fwd_block_cols=ff[1][1], fwd_slabs=ff[1][2],
+                         back_rows_per_wave=bb[1][0], back_block_cols=bb[1][1], back_slabs=bb[1][2])
+            ms = _time_iteration(prob, sched, iter_reps)
+            report.append(dict(schedule=sched, iteration_ms=ms))
+            if log:
+                log("autotune %s: %.4f ms per iteration" % (json.dumps(sched), ms))
+            if best is None or ms < best[0]:
+                best = (ms, sched, ff[0], bb[0])
     if cache_path:
         cache = load_cache(cache_path)
         cache[shape_key(I, prob.ny, prob.nx, prob.Q, prob.nnz)] = dict(
-            schedule=best, forward_us=best_f[0], back_us=best_b[0], seconds=time.time() - t0,
-            candidates=len(report))
+            schedule=best[1], forward_us=best[2], back_us=best[3], iteration_ms=best[0],
+            seconds=time.time() - t0, candidates=len(report))
         with open(cache_path, "w") as fh:
             json.dump(cache, fh, indent=1, sort_keys=True)
-    return best, report
+    return best[1], report
 
 
 def load_cache(path=CACHE_PATH):

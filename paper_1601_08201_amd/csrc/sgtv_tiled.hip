@@ -121,6 +121,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
                                            const int32_t *__restrict__ pk,
                                            const typename Code<VT>::T *__restrict__ val,
                                            const int32_t *__restrict__ goff,
+                                           const int32_t *__restrict__ poff,
                                            const float *__restrict__ x,
                                            float *__restrict__ part) {
     typedef typename Code<VT>::T T;
@@ -171,10 +172,30 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     // the block's first float4): loads under a branch would be waited for
     // where the branches join, before the barrier
     const bool pre = PREFETCH && (MODE == 2 || (MODE == 0 && M.idx24 && M.cb <= kXPrefetch * 4 * nthr));
+    // The offsets of a block's list (group offset, length, and where its
+    // 24-bit indices start) are read one block ahead, while the previous
+    // block streams: read after the block barrier, every wave of the
+    // workgroup would wait for them at once with nothing else in flight.
+    // The reads are unconditional (the last block rereads its own list;
+    // 32-bit lists read goff in place of poff and ignore the value).
+    const int32_t *lp = M.idx24 ? poff : goff;
+    int nx_g0 = 0, nx_g1 = 0, nx_po = 0;
+    if (ncbs > 0) {
+        nx_g0 = goff[list0];
+        nx_g1 = goff[list0 + 1];
+        nx_po = lp[list0];
+    }
     for (int c = 0; c < ncbs; ++c) {
         const int64_t L = list0 + static_cast<int64_t>(c) * M.waves;
-        const int g0 = goff[L];
-        const int ng = goff[L + 1] - g0;
+        const int g0 = __builtin_amdgcn_readfirstlane(nx_g0);
+        const int ng = __builtin_amdgcn_readfirstlane(nx_g1) - g0;
+        const int po = __builtin_amdgcn_readfirstlane(nx_po);
+        {
+            const int64_t Ln = c + 1 < ncbs ? L + M.waves : L;
+            nx_g0 = goff[Ln];
+            nx_g1 = goff[Ln + 1];
+            nx_po = lp[Ln];
+        }
         const int nb4 = ng >> 2;
         const int64_t base = static_cast<int64_t>(g0) * kWave;
         const v4i *p4 = reinterpret_cast<const v4i *>(pk + base) + lane;
@@ -187,7 +208,7 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
         v4f xr[kXPrefetch];
         const bool i24 = MODE == 0 && M.idx24;
         const uint32_t *p3 = nullptr;
-        if (i24) p3 = reinterpret_cast<const uint32_t *>(pk + M.poff[L]);
+        if (i24) p3 = reinterpret_cast<const uint32_t *>(pk + po);
         if (MODE == 0 && i24) {
             const int nsb = nb4 >> 2;
             const v4u *qs = reinterpret_cast<const v4u *>(p3) + lane;
@@ -287,9 +308,10 @@ template <int VT, int MODE>
 __global__ __launch_bounds__(1024) void k_tiled(TileMap M, const int32_t *__restrict__ pk,
                                                 const typename Code<VT>::T *__restrict__ val,
                                                 const int32_t *__restrict__ goff,
+                                                const int32_t *__restrict__ poff,
                                                 const float *__restrict__ x,
                                                 float *__restrict__ part) {
-    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, poff, x, part);
 }
 
 // Many scans in one launch: workgroup b runs tile tiles[b].local of scan
@@ -305,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_tiled_batch(const BatchTile *__restric
     // are read with scalar loads instead of living in scratch memory
     const TileMap &M = maps[bt.scan];
     tiled_body<VT, MODE>(M, bt.local, M.pk, static_cast<const typename Code<VT>::T *>(M.val),
-                         M.goff, xs[bt.scan], parts[bt.scan]);
+                         M.goff, M.poff, xs[bt.scan], parts[bt.scan]);
 }
 
 // ---------------------------------------------------------------- persistent batch
@@ -350,7 +372,8 @@ struct PersistentWork {
         // registers would push the walk past the 128 of a 16-wave workgroup
         // (same sums in the same order, only the timing of the staging loads
         // differs).  grab() synchronised the workgroup before this tile.
-        tiled_body<0, MODE, false>(M, bt.local, M.pk, static_cast<const float *>(M.val), M.goff, x, part);
+        tiled_body<0, MODE, false>(M, bt.local, M.pk, static_cast<const float *>(M.val), M.goff, M.poff, x,
+                                   part);
     }
     __device__ __forceinline__ void blocks(int phase, int64_t first, int64_t stride, int64_t n, int fc, int vc) {
         const int q = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
@@ -551,10 +574,11 @@ template <int VT, int MODE>
 __global__ __launch_bounds__(1024) void k_tiled_ratio(TileMap M, const int32_t *__restrict__ pk,
                                                       const typename Code<VT>::T *__restrict__ val,
                                                       const int32_t *__restrict__ goff,
+                                                      const int32_t *__restrict__ poff,
                                                       const float *__restrict__ x, float *part,
                                                       RatioEpilogue E, int vec) {
     extern __shared__ float lds[];
-    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, poff, x, part);
     const int64_t rb = blockIdx.x / M.ns;
     if (!last_slab(E.count + rb, M.ns, reinterpret_cast<int *>(lds))) return;
     const int64_t rows = static_cast<int64_t>(M.waves) * M.rw, row0 = rb * rows;
@@ -594,10 +618,11 @@ template <int VT, int MODE, int GROUPING, bool WFULL>
 __global__ __launch_bounds__(1024) void k_tiled_update(TileMap M, const int32_t *__restrict__ pk,
                                                        const typename Code<VT>::T *__restrict__ val,
                                                        const int32_t *__restrict__ goff,
+                                                       const int32_t *__restrict__ poff,
                                                        const float *__restrict__ x, float *part,
                                                        UpdateEpilogue E) {
     extern __shared__ float lds[];
-    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, x, part);
+    tiled_body<VT, MODE>(M, blockIdx.x, pk, val, goff, poff, x, part);
     const int64_t rb = blockIdx.x / M.ns;
     if (!last_slab(E.count + rb, M.ns, reinterpret_cast<int *>(lds))) return;
     const int64_t rows = static_cast<int64_t>(M.waves) * M.rw, row0 = rb * rows;
@@ -641,17 +666,17 @@ static hipError_t launch_tiled_t(const TileMap &M, const float *x, float *part, 
     const T *val = static_cast<const T *>(M.val);
     if (EPI == 0) {
         if (hipError_t e = raise_lds<&k_tiled<VT, MODE>>()) return e;
-        hipLaunchKernelGGL((k_tiled<VT, MODE>), grid, block, lds, st, M, M.pk, val, M.goff, x, part);
+        hipLaunchKernelGGL((k_tiled<VT, MODE>), grid, block, lds, st, M, M.pk, val, M.goff, M.poff, x, part);
     } else if (EPI == 1) {
         const auto al = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
         const int vec = M.n_rows % 4 == 0 && al(part) && al(R->y) && al(R->r) && al(R->ratio);
         if (hipError_t e = raise_lds<&k_tiled_ratio<VT, MODE>>()) return e;
-        hipLaunchKernelGGL((k_tiled_ratio<VT, MODE>), grid, block, lds, st, M, M.pk, val, M.goff, x, part, *R,
-                           vec);
+        hipLaunchKernelGGL((k_tiled_ratio<VT, MODE>), grid, block, lds, st, M, M.pk, val, M.goff, M.poff, x,
+                           part, *R, vec);
     } else {
         if (hipError_t e = raise_lds<&k_tiled_update<VT, MODE, GROUPING, WFULL>>()) return e;
         hipLaunchKernelGGL((k_tiled_update<VT, MODE, GROUPING, WFULL>), grid, block, lds, st, M, M.pk, val,
-                           M.goff, x, part, *U);
+                           M.goff, M.poff, x, part, *U);
     }
     return hipGetLastError();
 }
