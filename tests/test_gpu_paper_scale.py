@@ -1,5 +1,6 @@
 """Paper-scale scan (128 x 128 x 128, 1,048,576 measurements, 134M nonzeros):
-FP32 parity after 200 iterations and the error of the 16-bit-value paths
+FP32 parity after 200 iterations (automatic schedule, and the tuned schedule
+the benchmark runs) and the error of the 16-bit-value paths
 against the FP64 oracle on the exact FP32 matrix at iterations 50 and 200.
 
 The FP64 oracle runs 200 iterations of the full problem once (about a minute
@@ -43,9 +44,14 @@ def sg():
     return sgtv
 
 
-def gpu_images(sg, prob, storage):
+def gpu_images(sg, prob, storage, schedule=None):
     R = sg.Reconstructor()
+    if schedule:
+        R.set_schedule(format=0, **schedule)
     R.set_problem(prob, storage=storage)
+    if schedule:
+        got = R.schedule()
+        assert all(got[k] == v for k, v in schedule.items()), got
     R.iterate(50)
     f50 = R.image()
     R.iterate(150)
@@ -55,12 +61,22 @@ def gpu_images(sg, prob, storage):
     return {50: f50, 200: f200}, rep
 
 
-def test_fp32_matches_oracle_after_200_iterations(sg, paper):
+@pytest.mark.parametrize("schedule", ["automatic", "tuned"])
+def test_fp32_matches_oracle_after_200_iterations(sg, paper, schedule):
+    """The automatic schedule (1024 rows per wave, 4 and 2 slabs) and the one
+    the benchmark runs (the autotuner's cached schedule for this shape: 2048
+    rows per wave, 8188-column blocks, 8 and 4 slabs)."""
     prob, f_or, obj = paper
-    f_g, rep = gpu_images(sg, prob, "f32")
+    sched = None
+    if schedule == "tuned":
+        from paper_1601_08201_amd import autotune
+        sched = autotune.cached_schedule(prob)
+        assert sched is not None
+        print("tuned schedule", json.dumps(sched), flush=True)
+    f_g, rep = gpu_images(sg, prob, "f32", sched)
     for k in (50, 200):
         err = rel_l2(f_g[k], f_or[k])
-        print("fp32 iteration %d: image rel L2 %.3e" % (k, err), flush=True)
+        print("fp32 (%s schedule) iteration %d: image rel L2 %.3e" % (schedule, k, err), flush=True)
         assert err <= 1e-5
     assert rep["total"] == pytest.approx(obj[200], rel=1e-6)
 
