@@ -758,7 +758,7 @@ def main():
     stream = torch.cuda.current_stream()
     R = sgtv.Reconstructor(device=0, stream=stream.cuda_stream)
     from paper_1601_08201_amd import autotune
-    tuned = autotune.cached_schedule(prob) if args.format == "tiled" else None
+    tuned = autotune.cached_schedule(prob, storage=args.storage) if args.format == "tiled" else None
     if tuned:
         R.set_schedule(format=0, **tuned)
         log("tuned schedule from the autotuner cache: " + json.dumps(tuned))

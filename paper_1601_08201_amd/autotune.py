@@ -35,8 +35,11 @@ def lds_bytes(waves, rw, cb, variant=1):
     return a + cb * 4 + (16 if i24 else 0)
 
 
-def shape_key(I, ny, nx, Q, nnz):
-    return "I%d_g%dx%dx%d_nnz%d" % (I, ny, nx, Q, nnz)
+def shape_key(I, ny, nx, Q, nnz, storage="f32"):
+    """Cache key of a problem shape; 16-bit value types have entries of their
+    own (their products and image update weigh differently)."""
+    key = "I%d_g%dx%dx%d_nnz%d" % (I, ny, nx, Q, nnz)
+    return key if storage == "f32" else key + "_" + storage
 
 
 def candidates(I, J, waves=16, per_side=10):
@@ -159,12 +162,12 @@ def cached_batch_schedule(probs, path=CACHE_PATH):
     return rec["schedule"] if rec else None
 
 
-def _time_schedule(prob, sched, reps, warmup=10):
+def _time_schedule(prob, sched, reps, warmup=10, storage="f32"):
     """Average forward and back product times (us) over `reps` iterations
     after `warmup` iterations, HIP events around every launch."""
     R = sgtv.Reconstructor()
     R.set_schedule(format=0, **sched)
-    R.set_problem(prob)
+    R.set_problem(prob, storage=storage)
     R.set_graphs(False)
     R.iterate(warmup)
     R.set_profiling(True)
@@ -174,14 +177,14 @@ def _time_schedule(prob, sched, reps, warmup=10):
     return t["forward"][0] / t["forward"][1] * 1e3, t["back"][0] / t["back"][1] * 1e3
 
 
-def _time_iteration(prob, sched, reps, warmup=10):
+def _time_iteration(prob, sched, reps, warmup=10, storage="f32"):
     """Milliseconds per ADMM iteration (graph replay of `reps` iterations
     after `warmup`): the products and the ratio and update kernels, whose
     partial-sum reads grow with the slab counts."""
     import torch
     R = sgtv.Reconstructor()
     R.set_schedule(format=0, **sched)
-    R.set_problem(prob)
+    R.set_problem(prob, storage=storage)
     R.iterate(warmup)
     R.prepare(reps)
     torch.cuda.synchronize()
@@ -195,7 +198,7 @@ def _time_iteration(prob, sched, reps, warmup=10):
 
 
 def tune(prob, reps=20, max_candidates=10, variants=(1,), log=None, cache_path=CACHE_PATH, finalists=2,
-         iter_reps=100):
+         iter_reps=100, storage="f32"):
     """Time candidate schedules on the device; return (schedule dict, report).
 
     Every candidate's forward and back products are timed; the `finalists`
@@ -218,7 +221,7 @@ def tune(prob, reps=20, max_candidates=10, variants=(1,), log=None, cache_path=C
             sched = dict(waves=16, variant=v, fwd_rows_per_wave=f[0], fwd_block_cols=f[1], fwd_slabs=f[2],
                          back_rows_per_wave=b[0], back_block_cols=b[1], back_slabs=b[2])
             try:
-                tf, tb = _time_schedule(prob, sched, reps)
+                tf, tb = _time_schedule(prob, sched, reps, storage=storage)
             except sgtv.SgtvError as e:
                 report.append(dict(schedule=sched, error=str(e)))
                 continue
@@ -244,7 +247,7 @@ def tune(prob, reps=20, max_candidates=10, variants=(1,), log=None, cache_path=C
             sched = dict(waves=16, variant=ff[2],
                          fwd_rows_per_wave=ff[1][0], fwd_block_cols=ff[1][1], fwd_slabs=ff[1][2],
                          back_rows_per_wave=bb[1][0], back_block_cols=bb[1][1], back_slabs=bb[1][2])
-            ms = _time_iteration(prob, sched, iter_reps)
+            ms = _time_iteration(prob, sched, iter_reps, storage=storage)
             report.append(dict(schedule=sched, iteration_ms=ms))
             if log:
                 log("autotune %s: %.4f ms per iteration" % (json.dumps(sched), ms))
@@ -252,7 +255,7 @@ def tune(prob, reps=20, max_candidates=10, variants=(1,), log=None, cache_path=C
                 best = (ms, sched, ff[0], bb[0])
     if cache_path:
         cache = load_cache(cache_path)
-        cache[shape_key(I, prob.ny, prob.nx, prob.Q, prob.nnz)] = dict(
+        cache[shape_key(I, prob.ny, prob.nx, prob.Q, prob.nnz, storage)] = dict(
             schedule=best[1], forward_us=best[2], back_us=best[3], iteration_ms=best[0],
             seconds=time.time() - t0, candidates=len(report))
         with open(cache_path, "w") as fh:
@@ -267,9 +270,12 @@ def load_cache(path=CACHE_PATH):
     return {}
 
 
-def cached_schedule(prob, path=CACHE_PATH):
+def cached_schedule(prob, path=CACHE_PATH, storage="f32"):
     """The tuned schedule for this problem's shape, or None (automatic)."""
-    rec = load_cache(path).get(shape_key(prob.I, prob.ny, prob.nx, prob.Q, prob.nnz))
+    cache = load_cache(path)
+    key = shape_key(prob.I, prob.ny, prob.nx, prob.Q, prob.nnz)
+    # 16-bit values: their own entry, else the FP32 one
+    rec = cache.get(shape_key(prob.I, prob.ny, prob.nx, prob.Q, prob.nnz, storage)) or cache.get(key)
     return rec["schedule"] if rec else None
 
 
@@ -287,6 +293,7 @@ def _main():
     ap.add_argument("--workloads", default="paper,warmstart,batch")
     ap.add_argument("--out", default=CACHE_PATH)
     ap.add_argument("--candidates", type=int, default=8)
+    ap.add_argument("--storage", default="f32", help="value types to tune for, comma-separated (f32, bf16, f16)")
     ap.add_argument("--batch-scans", type=int, default=64)
     ap.add_argument("--tune-batch", action="store_true",
                     help="time the schedules of the whole batch workload (its scans, seeds 300 + k) instead")
@@ -313,8 +320,10 @@ def _main():
                     probs.append(datagen.make_batch_scan(ny, nx, Q, seed=900))
     for p in probs:
         t0 = time.time()
-        best, rep = tune(p, max_candidates=args.candidates, log=log, cache_path=args.out)
-        log("shape %dx%dx%d I=%d: best %s (%.1fs)" % (p.ny, p.nx, p.Q, p.I, json.dumps(best), time.time() - t0))
+        for st in args.storage.split(","):
+            best, rep = tune(p, max_candidates=args.candidates, log=log, cache_path=args.out, storage=st)
+            log("shape %dx%dx%d I=%d %s: best %s (%.1fs)" % (p.ny, p.nx, p.Q, p.I, st, json.dumps(best),
+                                                             time.time() - t0))
 
 
 if __name__ == "__main__":

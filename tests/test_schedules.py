@@ -56,3 +56,21 @@ def test_batch_tuner_candidates_and_cache_key(tmp_path):
         json.dump({autotune.batch_key(a): {"schedule": {"fwd_rows_per_wave": 512, "back_rows_per_wave": 512}}}, fh)
     assert autotune.cached_batch_schedule(a, path) == {"fwd_rows_per_wave": 512, "back_rows_per_wave": 512}
     assert autotune.cached_batch_schedule(b, path) is None
+
+
+def test_schedule_cache_keys_by_value_type(tmp_path):
+    """16-bit value types look up an entry of their own and fall back to the
+    FP32 entry of the same shape."""
+    import json
+    from types import SimpleNamespace as NS
+    from paper_1601_08201_amd import autotune
+    p = NS(I=1000, ny=4, nx=5, Q=6, nnz=777)
+    k32 = autotune.shape_key(p.I, p.ny, p.nx, p.Q, p.nnz)
+    kb = autotune.shape_key(p.I, p.ny, p.nx, p.Q, p.nnz, "bf16")
+    assert kb != k32 and kb.startswith(k32)
+    path = str(tmp_path / "cache.json")
+    with open(path, "w") as fh:
+        json.dump({k32: {"schedule": {"fwd_rows_per_wave": 2048}}, kb: {"schedule": {"fwd_rows_per_wave": 1024}}}, fh)
+    assert autotune.cached_schedule(p, path) == {"fwd_rows_per_wave": 2048}
+    assert autotune.cached_schedule(p, path, storage="bf16") == {"fwd_rows_per_wave": 1024}
+    assert autotune.cached_schedule(p, path, storage="f16") == {"fwd_rows_per_wave": 2048}
