@@ -139,6 +139,16 @@ def test_full_lds_tiles_of_2048_rows(sg, storage):
     R.close()
 
 
+def test_full_lds_tiles_standard_tv_weights_and_sweeps(sg):
+    """The full-LDS 2048-row tiles with standard TV, per-direction weights and
+    three surrogate sweeps per iteration on the 64^3 scanner."""
+    prob = datagen.make_problem("warmstart", 4)
+    sched = dict(format=0, waves=16, fwd_rows_per_wave=2048, fwd_block_cols=8188, fwd_slabs=4,
+                 back_rows_per_wave=2048, back_block_cols=8188, back_slabs=2)
+    w = np.array([1.0, 0.8, 1.25, 0.9], np.float32)
+    check_against_oracle(sg, prob, 12, w=w, grouping=1, sweeps=3, schedule=sched)
+
+
 def test_non_square_grid_and_ragged_tails(sg):
     prob = datagen.make_problem(dict(ny=3, nx=11, Q=5, I=301, nnz_per_col=7, rects=3, beta=0.1),
                                 seed=7)

@@ -43,6 +43,11 @@ CASES = {
     "sliced ELL": dict(cfg="small", seed=5, schedule=dict(format=1)),
     "sliced ELL bf16": dict(cfg="small", seed=6, storage="bf16", schedule=dict(format=1)),
     "fused update": dict(cfg="teflon", seed=7, fused=True),
+    # 13-bit columns: the tile map's column bits go through the file
+    "2048-row tiles": dict(cfg="small", seed=8, schedule=dict(format=0, waves=4, fwd_rows_per_wave=2048,
+                                                            fwd_block_cols=8188, fwd_slabs=1,
+                                                            back_rows_per_wave=1536, back_block_cols=1000,
+                                                            back_slabs=2)),
 }
 
 
