@@ -289,6 +289,34 @@ int main() {
     check_case("24-bit, 1500 rows per wave, dealt rows", f, TileParams{1500, 3, 4000, 3}, true, true);
     check_case("32-bit, 2048 rows per wave, 8192-column blocks", f, TileParams{2048, 2, 8192, 2}, false, false);
     check_threads("threads, 2048 rows per wave", f, TileParams{2048, 4, 8188, 2});
+    // seeded random schedules over both index formats and both column splits;
+    // the expected format and dealing follow the format's stated limits
+    uint64_t rs = 12345;
+    for (int k = 0; k < 24 && !failures; ++k) {
+        const int64_t n_rows = 1 + static_cast<int64_t>(lcg(rs) % 12000);
+        const int64_t n_cols = 1 + static_cast<int64_t>(lcg(rs) % 30000);
+        const Csr m = make_csr(n_rows, n_cols, 1 + static_cast<int>(lcg(rs) % 30), 100 + k, k % 3 == 0);
+        TileParams t;
+        const int rws[] = {64, 100, 512, 1024, 1025, 1536, 2048, 2100};
+        t.rw = rws[lcg(rs) % 8];
+        t.waves = 1 + static_cast<int>(lcg(rs) % 16);
+        const int cbs[] = {12, 1000, 4096, 8188, 8192, 16380, 16384};
+        t.cb = cbs[lcg(rs) % 7];
+        t.ns = 1 + static_cast<int>(lcg(rs) % 4);
+        const int cmax = t.rw <= 1024 ? 16380 : 8188;
+        const bool want24 = t.rw >= 64 && t.rw <= 2048 && t.cb % 4 == 0 && t.cb <= cmax;
+        const int64_t ncb = (n_cols + t.cb - 1) / t.cb;
+        if (t.ns > ncb) t.ns = static_cast<int>(ncb);   // as the schedule chooser caps it
+        int64_t cbs_max = 0;
+        for (int s2 = 0; s2 < t.ns; ++s2)
+            cbs_max = std::max<int64_t>(cbs_max, ((s2 + 1) * ncb) / t.ns - (s2 * ncb) / t.ns);
+        const int64_t RB = static_cast<int64_t>(t.waves) * t.rw;
+        const bool want_dealt = want24 && t.ns * RB * cbs_max <= (int64_t(1) << 24);
+        char name[160];
+        std::snprintf(name, sizeof name, "random %d: %lld x %lld, rw %d, waves %d, cb %d, ns %d", k,
+                      static_cast<long long>(n_rows), static_cast<long long>(n_cols), t.rw, t.waves, t.cb, t.ns);
+        check_case(name, m, t, want24, want_dealt);
+    }
     if (failures) return 1;
     std::printf("ok\n");
     return 0;

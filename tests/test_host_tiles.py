@@ -8,7 +8,8 @@ group in 32-bit lists, and a permutation per tile when rows are dealt to the
 waves; and the packed arrays built on one host thread and on eight are byte
 for byte the same.  Cases: dealt rows, 16 waves over 3 slabs, the 32-bit format, long row
 runs with duplicate entries, the contiguous order kept past 2^24 counts, and
-2048 rows per wave (11-bit rows, 13-bit columns)."""
+2048 rows per wave (11-bit rows, 13-bit columns), and 24 seeded random
+schedules across both formats."""
 import os
 import subprocess
 
@@ -34,3 +35,4 @@ def test_tiled_format_round_trips(tmp_path):
     assert out.stdout.count("dealt rows") >= 3 and "contiguous rows" in out.stdout
     assert out.stdout.count("identical with 1 and 8 host threads") == 5
     assert "2048 rows per wave, dealt rows" in out.stdout
+    assert out.stdout.count("random ") == 24
