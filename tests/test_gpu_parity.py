@@ -149,6 +149,41 @@ def test_full_lds_tiles_standard_tv_weights_and_sweeps(sg):
     check_against_oracle(sg, prob, 12, w=w, grouping=1, sweeps=3, schedule=sched)
 
 
+def random_schedule(rng):
+    """A tile schedule drawn at random within the limits of set_schedule and
+    of the 160 KiB of LDS (both index formats, all three inner loops)."""
+    from paper_1601_08201_amd import autotune
+    while True:
+        waves = int(rng.choice([1, 2, 4, 8, 16]))
+        variant = int(rng.choice([1, 1, 2, 3]))
+        side = []
+        for _ in range(2):
+            rw = int(rng.choice([64, 100, 256, 1024, 1536, 2048]))
+            cb = int(rng.choice([12, 256, 1000, 4096, 8188, 16380, 16384]))
+            side.append((rw, cb, int(rng.integers(1, 5))))
+        if variant == 3 and any(cb > 16 * waves * 64 for _, cb, _ in side):
+            continue   # the block prefetch of variant 3 holds at most 16 floats per thread
+        if all(autotune.lds_bytes(waves, rw, cb, variant) <= autotune.MAX_LDS for rw, cb, _ in side):
+            (fr, fc, fs), (br, bc, bs) = side
+            return dict(format=0, waves=waves, variant=variant, fwd_rows_per_wave=fr, fwd_block_cols=fc,
+                        fwd_slabs=fs, back_rows_per_wave=br, back_block_cols=bc, back_slabs=bs)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_schedules_agree_with_oracle(sg, seed):
+    """Seeded random problems (grid, spectral bins, measurements, density)
+    under seeded random tile schedules, against the oracle."""
+    rng = np.random.default_rng(900 + seed)
+    ny, nx, Q = int(rng.integers(3, 21)), int(rng.integers(3, 21)), int(rng.integers(1, 41))
+    J = ny * nx * Q
+    cfg = dict(ny=ny, nx=nx, Q=Q, I=int(rng.integers(64, max(65, 3 * J // 2))), nnz_per_col=int(rng.integers(2, 17)),
+               rects=int(rng.integers(1, 4)), beta=float(rng.choice([0.05, 0.2, 0.5])))
+    sched = random_schedule(rng)
+    print("seed", seed, "problem", cfg, "schedule", sched, flush=True)
+    prob = datagen.make_problem(cfg, seed=1000 + seed)
+    check_against_oracle(sg, prob, 15, schedule=sched)
+
+
 def test_non_square_grid_and_ragged_tails(sg):
     prob = datagen.make_problem(dict(ny=3, nx=11, Q=5, I=301, nnz_per_col=7, rects=3, beta=0.1),
                                 seed=7)
