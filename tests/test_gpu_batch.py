@@ -193,6 +193,53 @@ def test_batch_of_mixed_tile_formats(sg):
     B.close()
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_random_batches_equal_single_scans(sg, seed):
+    """Seeded random batches (3-6 scans of random shapes, groupings, betas
+    and densities) under one random tile schedule: the graph launch, and the
+    persistent launch where the schedule allows it (a multiple of 4 waves,
+    room for its own LDS), reproduce every scan's single run bit for bit."""
+    from paper_1601_08201_amd import autotune
+    rng = np.random.default_rng(700 + seed)
+    probs, setups = [], []
+    for k in range(int(rng.integers(3, 7))):
+        ny, nx, Q = int(rng.integers(3, 17)), int(rng.integers(3, 17)), int(rng.integers(1, 33))
+        J = ny * nx * Q
+        probs.append(datagen.make_problem(dict(ny=ny, nx=nx, Q=Q, I=int(rng.integers(64, max(65, J))),
+                                               nnz_per_col=int(rng.integers(2, 13)), rects=2, beta=0.1),
+                                          seed=1500 + 10 * seed + k))
+        setups.append((int(rng.integers(0, 2)), float(rng.choice([0.05, 0.2, 1.0]))))
+    while True:
+        waves = int(rng.choice([4, 8, 16]))
+        rw = int(rng.choice([64, 256, 1024, 2048]))
+        cb = int(rng.choice([256, 4096, 8188, 16380]))
+        if autotune.lds_bytes(waves, rw, cb) <= autotune.MAX_LDS:
+            break
+    sched = dict(waves=waves, fwd_rows_per_wave=rw, back_rows_per_wave=rw, fwd_block_cols=cb, back_block_cols=cb)
+    persistent_ok = autotune.lds_bytes(waves, rw, cb) <= autotune.MAX_LDS - 16
+    print("seed", seed, "scans", len(probs), "schedule", sched, "persistent", persistent_ok, flush=True)
+    launches = ["graph"] + (["persistent"] if persistent_ok else [])
+    for launch in launches:
+        B = sg.Batch()
+        for p, (g, b) in zip(probs, setups):
+            B.add_scan(p, schedule=sched, grouping=g, beta=b)
+        B.set_launch(launch)
+        B.iterate(9)
+        B.iterate(8)
+        for i, (p, (g, b)) in enumerate(zip(probs, setups)):
+            R = sg.Reconstructor()
+            R.set_schedule(**sched)
+            R.set_problem(p)
+            if g:
+                R.set_grouping(g)
+            R.set_data(p.y, p.r, b, p.rho, p.sweeps)
+            R.iterate(17)
+            np.testing.assert_array_equal(B.image(i), R.image())
+            assert B.objective(i) == R.objective()
+            R.close()
+        B.close()
+
+
 def test_launch_mode_is_checked(sg):
     B = sg.Batch()
     assert B.launch() == ("graph", 0)
