@@ -184,6 +184,30 @@ def test_random_schedules_agree_with_oracle(sg, seed):
     check_against_oracle(sg, prob, 15, schedule=sched)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_schedules_16_bit_values(sg, seed):
+    """Seeded random problems and schedules with BF16 or FP16 values: the GPU
+    against the oracle given the same dequantised matrix."""
+    import copy
+    rng = np.random.default_rng(950 + seed)
+    storage = ("bf16", "f16")[seed % 2]
+    ny, nx, Q = int(rng.integers(3, 17)), int(rng.integers(3, 17)), int(rng.integers(1, 33))
+    J = ny * nx * Q
+    cfg = dict(ny=ny, nx=nx, Q=Q, I=int(rng.integers(64, max(65, J))), nnz_per_col=int(rng.integers(2, 13)),
+               rects=2, beta=0.1)
+    sched = random_schedule(rng)
+    print("seed", seed, storage, "problem", cfg, "schedule", sched, flush=True)
+    prob = datagen.make_problem(cfg, seed=1200 + seed)
+    q = copy.copy(prob)
+    q.val = oracle.quantise(prob.col, prob.val, prob.J, storage)[2]
+    R = run_gpu(sg, prob, 15, storage=storage, schedule=sched)
+    f_o = oracle.admm(q, 15, report=False)[0]
+    err = rel_l2(R.image(), f_o)
+    print("rel_l2 vs oracle on the quantised matrix", err, flush=True)
+    assert err <= IMG_TOL
+    R.close()
+
+
 def test_non_square_grid_and_ragged_tails(sg):
     prob = datagen.make_problem(dict(ny=3, nx=11, Q=5, I=301, nnz_per_col=7, rects=3, beta=0.1),
                                 seed=7)
