@@ -571,7 +571,7 @@ def warmstart_main(args):
         train_info[name] = {"seconds": time.time() - t1, "loss_first_last": [hist[0], hist[-1]],
                             "loss_of_constant_prediction": const,
                             "input": "plain image after %d iterations" % k if k else "normalised backprojection",
-                            "output": mode}
+                            "output": mode, "start_floor": model.floor}
         log("%s: trained %d epochs in %.1fs, loss %.5f -> %.5f (constant prediction %.5f)"
             % (name, args.epochs, train_info[name]["seconds"], hist[0], hist[-1], const))
     del xin, tgt

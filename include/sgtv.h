@@ -501,10 +501,14 @@ int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int me
  * m = mean(f) (FP64 sum; 1 where not positive) and s = network(f / m):
  *   WSNET_START_RATIO:  x0 = c_out * s * f   (per-voxel correction factor)
  *   WSNET_START_DIRECT: x0 = c_out * s * m   (the image itself)
- * c_out is the scale the targets were divided by in training (> 0). */
+ * c_out is the scale the targets were divided by in training (> 0).  With
+ * floor > 0 every voxel is raised to at least floor * c_out * m (a fraction
+ * of the predicted mean level): the image update is multiplicative, so a
+ * voxel started near zero takes many iterations to grow; floor = 0 leaves x0
+ * as above.  floor must be finite and >= 0. */
 #define WSNET_START_RATIO 0
 #define WSNET_START_DIRECT 1
-int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out, float *x0,
+int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out, double floor, float *x0,
                 int mem_kind);
 /* Loss and gradient of the mean squared error of network(x_in) against
  * target; the gradient stays in the network for wsnet_adam_step and is

@@ -3385,12 +3385,13 @@ int wsnet_forward(wsnet net, const float *x_in, int32_t batch, float *x0, int me
     return SGTV_OK;
 }
 
-int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out, float *x0,
+int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out, double floor, float *x0,
                 int mem_kind) {
     if (int e = net_check(net, batch, mem_kind)) return e;
     if (!f || !x0) return fail(SGTV_EINVAL, "null argument");
     if (mode != WSNET_START_RATIO && mode != WSNET_START_DIRECT) return fail(SGTV_EINVAL, "unknown start mode");
     if (!(c_out > 0.0) || !std::isfinite(c_out)) return fail(SGTV_EINVAL, "c_out must be finite and > 0");
+    if (!(floor >= 0.0) || !std::isfinite(floor)) return fail(SGTV_EINVAL, "floor must be finite and >= 0");
     DeviceGuard g(net->device);
     const int64_t cnt = batch * net->img;
     if (int e = net_stage(net, net->xin, f, cnt, mem_kind)) return e;
@@ -3402,7 +3403,7 @@ int wsnet_start(wsnet net, const float *f, int32_t batch, int mode, double c_out
     if (int e = net_layers(net, batch)) return e;
     HIP_TRY(sgtv::wsn::start_image(net->xin.as<float>(), net->out.as<float>(), net->isum.as<double>(), net->img,
                                    cnt, static_cast<float>(c_out), mode == WSNET_START_RATIO,
-                                   net->tgt.as<float>(), net->stream));
+                                   static_cast<float>(floor), net->tgt.as<float>(), net->stream));
     HIP_TRY(hipMemcpyAsync(x0, net->tgt.p, sizeof(float) * cnt, to_caller(mem_kind), net->stream));
     HIP_TRY(hipStreamSynchronize(net->stream));
     return SGTV_OK;

@@ -36,9 +36,9 @@ hipError_t image_partials(const float *x, int64_t img, int n_images, int n_block
 // y = bf16(x / m_b), m_b = sums[b] / img (1 where not positive), b = i / img
 hipError_t scale_to_bf16(const float *x, const double *sums, int64_t img, int64_t n, __bf16 *y,
                          hipStream_t st);
-// x0 = c_out * s * (ratio ? f : m_b)
+// x0 = c_out * s * (ratio ? f : m_b), raised to at least floor * c_out * m_b when floor > 0
 hipError_t start_image(const float *f, const float *s, const double *sums, int64_t img, int64_t n,
-                       float c_out, int ratio, float *x0, hipStream_t st);
+                       float c_out, int ratio, float floor, float *x0, hipStream_t st);
 hipError_t mse_grad(const float *out, const float *target, const float *z, int64_t n, __bf16 *dz,
                     double *partials, int n_blocks, hipStream_t st);
 // acc[0] += l[0] / cnt, acc[1] += 1 (FP64, one thread)

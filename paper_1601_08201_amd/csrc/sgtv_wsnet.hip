@@ -462,11 +462,13 @@ __global__ void k_scale_to_bf16(const float *__restrict__ x, const double *__res
 // start image from the network output s: c_out * s * f (ratio) or c_out * s * mean(f) (direct)
 __global__ void k_start_image(const float *__restrict__ f, const float *__restrict__ s,
                               const double *__restrict__ sums, int64_t img, int64_t n, float c_out,
-                              int ratio, float *__restrict__ x0) {
+                              int ratio, float floor, float *__restrict__ x0) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const float base = ratio ? f[i] : static_cast<float>(image_mean(sums, i / img, img));
-        x0[i] = c_out * s[i] * base;
+        const float m = static_cast<float>(image_mean(sums, i / img, img));
+        const float base = ratio ? f[i] : m;
+        const float v = c_out * s[i] * base;
+        x0[i] = floor > 0.0f ? fmaxf(v, floor * c_out * m) : v;
     }
 }
 
@@ -618,10 +620,10 @@ hipError_t scale_to_bf16(const float *x, const double *sums, int64_t img, int64_
 }
 
 hipError_t start_image(const float *f, const float *s, const double *sums, int64_t img, int64_t n,
-                       float c_out, int ratio, float *x0, hipStream_t st) {
+                       float c_out, int ratio, float floor, float *x0, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_start_image, dim3(static_cast<unsigned>(std::min<int64_t>(4096, (n + 255) / 256))),
-                       dim3(256), 0, st, f, s, sums, img, n, c_out, ratio, x0);
+                       dim3(256), 0, st, f, s, sums, img, n, c_out, ratio, floor, x0);
     return hipGetLastError();
 }
 

@@ -135,7 +135,7 @@ def lib():
             "wsnet_set_params": (_I, [_P, _P, _I64, _I]),
             "wsnet_get_params": (_I, [_P, _P, _I64, _I]),
             "wsnet_forward": (_I, [_P, _P, _I32, _P, _I]),
-            "wsnet_start": (_I, [_P, _P, _I32, _I, _D, _P, _I]),
+            "wsnet_start": (_I, [_P, _P, _I32, _I, _D, _D, _P, _I]),
             "wsnet_backward": (_I, [_P, _P, _P, _I32, ctypes.POINTER(_D), _P, _I]),
             "wsnet_adam_step": (_I, [_P, _D, _D, _D, _D]),
             "wsnet_train_step": (_I, [_P, _P, _P, _I32, _D, _D, _D, _D, _I]),
@@ -794,12 +794,12 @@ def wsnet_forward(net, x_in, batch, out):
     return out
 
 
-def wsnet_start(net, f, batch, mode, c_out, out):
+def wsnet_start(net, f, batch, mode, c_out, out, floor=0.0):
     a = _arg(f, np.float32)
     p, mk = _out_arg(out)
     if mk != _kind(a):
         raise ValueError("f and out must both be host arrays or both device tensors")
-    _check(lib().wsnet_start(net, a[0], int(batch), int(mode), float(c_out), p, mk))
+    _check(lib().wsnet_start(net, a[0], int(batch), int(mode), float(c_out), float(floor), p, mk))
     return out
 
 
@@ -878,14 +878,15 @@ class WarmStartNet:
         _check(lib().wsnet_load(self._n, os.fsencode(path)))
         return self
 
-    def start(self, f, mode="ratio", c_out=1.0, out=None):
+    def start(self, f, mode="ratio", c_out=1.0, out=None, floor=0.0):
         """Start images x0 from images f (see wsnet_start): mode "ratio" gives
-        c_out * net(f / mean f) * f, "direct" c_out * net(f / mean f) * mean f."""
+        c_out * net(f / mean f) * f, "direct" c_out * net(f / mean f) * mean f;
+        floor > 0 raises every voxel to at least floor * c_out * mean f."""
         b = f.shape[0]
         if out is None:
             out = np.empty((b,) + self.shape, np.float32) if not _is_torch_cuda(f) else f.new_empty(f.shape)
         m = {"ratio": WSNET_START_RATIO, "direct": WSNET_START_DIRECT}[mode]
-        return wsnet_start(self._n, f, b, m, c_out, out)
+        return wsnet_start(self._n, f, b, m, c_out, out, floor)
 
     def backward(self, x_in, target, grad=None):
         return wsnet_backward(self._n, x_in, target, x_in.shape[0], grad)

@@ -137,12 +137,14 @@ class Model:
     number of plain iterations whose image the network sees.  The network sees
     each input image divided by its own mean m (counts, backprojection and
     image all scale with the object's intensity, so only the shape is learned);
-    mode "ratio": x0 = c_out * net * f_k, mode "direct": x0 = c_out * net * m."""
+    mode "ratio": x0 = c_out * net * f_k, mode "direct": x0 = c_out * net * m;
+    every voxel of x0 at least floor * c_out * m (wsnet_start)."""
     params: np.ndarray
     c_out: float
     mode: str = "ratio"
     input_iters: int = 10
     layers: int = 6
+    floor: float = 0.0
 
 
 def image_means(x):
@@ -165,8 +167,12 @@ def training_targets(xin, tgt, mode):
 
 
 def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, lr_min=1e-5, seed=0,
-          log=None, device=0, layers=6):
-    """Adam on the mean squared error of the scaled targets; cosine learning rate."""
+          log=None, device=0, layers=6, floor=None):
+    """Adam on the mean squared error of the scaled targets; cosine learning
+    rate.  floor (default: 0.2 for mode "direct", 0 for "ratio"): the start
+    images' floor as a fraction of the predicted mean level.  A direct
+    prediction from the backprojection leaves voxels near zero that the
+    multiplicative image update is slow to raise."""
     import torch
     dev = torch.device("cuda", device)
     m = image_means(xin)[:, None, None, None]
@@ -197,7 +203,9 @@ def train(xin, tgt, mode="ratio", input_iters=10, epochs=40, batch=32, lr=1e-3, 
         history.append(tot / max(N // batch, 1))
         if log and (ep + 1) % 5 == 0:
             log("train: epoch %d / %d, loss %.5f (%.1fs)" % (ep + 1, epochs, history[-1], time.time() - t0))
-    model = Model(net.params(), c_out, mode, int(input_iters), int(layers))
+    if floor is None:
+        floor = 0.2 if mode == "direct" else 0.0
+    model = Model(net.params(), c_out, mode, int(input_iters), int(layers), float(floor))
     return model, net, history
 
 
@@ -205,7 +213,7 @@ def predict(net, model, f):
     """Start images for a batch of network inputs f (float32 NHWC, host array
     or device tensor): the plain images after model.input_iters iterations, or
     normalised backprojections."""
-    return net.start(f, model.mode, model.c_out)
+    return net.start(f, model.mode, model.c_out, floor=model.floor)
 
 
 def warm_start(R, net, model, shape):

@@ -182,10 +182,12 @@ def test_invalid_network_arguments(sg):
         N.adam_step()             # no gradient yet
 
 
+@pytest.mark.parametrize("floor", [0.0, 0.3])
 @pytest.mark.parametrize("mode", ["ratio", "direct"])
-def test_start_images_against_fp64(sg, mode):
+def test_start_images_against_fp64(sg, mode, floor):
     """wsnet_start: the network sees f / mean(f) and the start image is
-    c_out * s * f (ratio) or c_out * s * mean(f) (direct)."""
+    c_out * s * f (ratio) or c_out * s * mean(f) (direct), raised to at least
+    floor * c_out * mean(f) when floor > 0."""
     rng = np.random.default_rng(11)
     f = rng.gamma(2.0, 1.5, size=(3, 8, 64, 64)).astype(np.float32)
     f[1] *= np.float32(40.0)
@@ -193,18 +195,23 @@ def test_start_images_against_fp64(sg, mode):
     p = layer_params(sg, 1, 5)
     N = sg.WarmStartNet(layers=1, height=8, max_batch=4).set_params(p)
     c_out = 1.75
-    x0 = N.start(f, mode, c_out)
+    x0 = N.start(f, mode, c_out, floor=floor)
     m = f.reshape(3, -1).astype(np.float64).mean(axis=1)[:, None, None, None]
     xin = bf16((f.astype(np.float64) / m).astype(np.float32))
     s = oracle.wn_forward(rounded_params(p, 1), xin, L=1)
     ref = c_out * s * (f.astype(np.float64) if mode == "ratio" else m)
+    if floor > 0:
+        lo = floor * c_out * m * np.ones_like(ref)
+        assert np.mean(ref < lo) > 0.01     # the floor acts on this input
+        ref = np.maximum(ref, lo)
+        assert np.all(x0 >= np.float32(0.999) * lo.astype(np.float32))
     err = rel(x0, ref)
-    print("start", mode, "rel L2", err, flush=True)
+    print("start", mode, "floor", floor, "rel L2", err, flush=True)
     assert err <= 1e-5
     assert np.all(x0 >= 0)
     # power-of-two scaling of an image is exact through the mean and the
     # network input, so the start image scales bit for bit
-    x4 = N.start(np.float32(4.0) * f, mode, c_out)
+    x4 = N.start(np.float32(4.0) * f, mode, c_out, floor=floor)
     np.testing.assert_array_equal(x4, np.float32(4.0) * x0)
 
 
@@ -225,6 +232,10 @@ def test_start_rejects_bad_arguments(sg):
         sg.wsnet_start(N._n, f, 1, 7, 1.0, np.empty_like(f))
     with pytest.raises(sg.SgtvError):
         N.start(f, "ratio", 0.0)
+    with pytest.raises(sg.SgtvError):
+        N.start(f, "direct", 1.0, floor=-0.1)
+    with pytest.raises(sg.SgtvError):
+        N.start(f, "direct", 1.0, floor=float("inf"))
     with pytest.raises(sg.SgtvError):
         N.start(f, "ratio", float("nan"))
     with pytest.raises(sg.SgtvError):
