@@ -169,8 +169,8 @@ __device__ __forceinline__ void tiled_body(const TileMap &M, int64_t tile,
     // (so its latency overlaps the wait there): MODE 2, and the simple loop on
     // 24-bit lists when the block fits the prefetch registers.  All kXPrefetch
     // loads are issued unconditionally (a chunk past a narrow block rereads
-    // the block's first float4): loads under a branch would be waited for
-    // where the branches join, before the barrier
+    // the block's first float4; skipping such chunks with a uniform branch
+    // made the products 11 % slower)
     const bool pre = PREFETCH && (MODE == 2 || (MODE == 0 && M.idx24 && M.cb <= kXPrefetch * 4 * nthr));
     // The offsets of a block's list (group offset, length, and where its
     // 24-bit indices start) are read one block ahead, while the previous
