@@ -481,15 +481,16 @@ def test_workspace_estimate_and_device_bytes(sg, cfg, storage):
 
 def test_tiles_with_and_without_row_balancing(sg):
     """24-bit lists deal each tile's rows to the waves by their entry counts
-    unless the per-row-block counts (slabs x rows x column blocks) pass 2^22;
+    unless the per-row-block counts (slabs x rows x column blocks) pass 2^24;
     then the rows keep their contiguous order.  With 16 x 64 rows per row block
-    and 12-column blocks the forward product (65536 columns, 5462 blocks) takes
-    the contiguous order and the back product (32768 columns, 2731 blocks) the
-    dealt one; both must match the oracle."""
-    for rows, blocks in ((16 * 64, 5462), (16 * 64, 2731)):
-        assert (rows * blocks > 1 << 22) == (blocks == 5462)
-    prob = datagen.make_problem(dict(ny=32, nx=32, Q=64, I=32768, nnz_per_col=8, rects=3, beta=0.1),
+    and 12-column blocks the forward product (262144 columns, 21846 blocks)
+    takes the contiguous order and the back product (32768 columns, 2731
+    blocks) the dealt one; both must match the oracle."""
+    for rows, blocks in ((16 * 64, 21846), (16 * 64, 2731)):
+        assert (rows * blocks > 1 << 24) == (blocks == 21846)
+    prob = datagen.make_problem(dict(ny=32, nx=32, Q=256, I=32768, nnz_per_col=8, rects=3, beta=0.1),
                                 seed=31)
+    assert prob.J == 262144 and -(-prob.J // 12) == 21846
     sched = dict(format=0, waves=16, fwd_rows_per_wave=64, fwd_block_cols=12, fwd_slabs=1,
                  back_rows_per_wave=64, back_block_cols=12, back_slabs=1)
     check_against_oracle(sg, prob, 20, schedule=sched)
