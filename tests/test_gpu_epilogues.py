@@ -93,12 +93,14 @@ def test_epilogues_equal_separate_launches(sg, name):
 
 
 def test_epilogues_on_the_paper_scale_scan(sg):
-    """The 128 x 128 x 128 scan with its tuned schedule (4 forward and 2 back
-    slabs): 20 iterations with and without the epilogues, bit for bit."""
+    """The 128 x 128 x 128 scan with its tuned schedule (2048 rows per wave,
+    full-LDS tiles, 8 forward and 4 back slabs): 20 iterations with and
+    without the epilogues, bit for bit."""
     prob = datagen.make_problem("paper", 1)
     from paper_1601_08201_amd import autotune
     tuned = autotune.cached_schedule(prob)
-    c = dict(sched=tuned) if tuned else {}
+    assert tuned and tuned["fwd_rows_per_wave"] == 2048
+    c = dict(sched=tuned)
     on = run(sg, prob, c, True, 20)
     off = run(sg, prob, c, False, 20)
     np.testing.assert_array_equal(on["image"], off["image"])
