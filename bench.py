@@ -820,6 +820,22 @@ def main():
         del src, dst
     iter_bytes = sum(alg.values())
 
+    # the same iterations handed over through host memory: counts and
+    # background from host arrays, the image back to a host array (set_data
+    # drops the captured graphs, so the iterations' graph is captured again
+    # inside this region, as it would be for a caller doing the same)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter()
+    R.set_data(prob.y, prob.r, prob.beta, prob.rho, prob.sweeps)
+    R.iterate(args.steps)
+    R.image()
+    host_s = time.perf_counter() - t_h
+    host_leg = {"value": args.steps / host_s, "unit": "iters/s", "seconds": host_s,
+                "note": "set_data from host arrays (y, r: %.1f MB), %d iterations, the image to a host array "
+                        "(%.1f MB), wall clock; the iteration graph is captured again after set_data"
+                        % (8e-6 * prob.I, args.steps, 4e-6 * prob.J)}
+    log("host-memory handover: %.1f iters/s (%.3f s for %d iterations)" % (host_leg["value"], host_s, args.steps))
+
     cpu = None
     err = None
     if not args.no_cpu_baseline:
@@ -871,6 +887,7 @@ def main():
                                        + ", valid for the current kernels, builder and schedule"},
         "cpu_baseline": cpu,
         "oracle_error": err,
+        "host_memory_handover": host_leg,
         "setup": dict(setup, note="set_system_s: packing on the host and upload; load_system_s: the same "
                                   "packed system read back from a file into a new context"),
     }
