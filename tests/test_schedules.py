@@ -74,3 +74,45 @@ def test_schedule_cache_keys_by_value_type(tmp_path):
     assert autotune.cached_schedule(p, path) == {"fwd_rows_per_wave": 2048}
     assert autotune.cached_schedule(p, path, storage="bf16") == {"fwd_rows_per_wave": 1024}
     assert autotune.cached_schedule(p, path, storage="f16") == {"fwd_rows_per_wave": 2048}
+
+
+def test_tuner_picks_the_fastest_iteration_among_finalists(tmp_path, monkeypatch):
+    """The tuner times every candidate's products, pairs the two fastest
+    forward and the two fastest back parameters, and keeps the pairing whose
+    whole iteration is fastest (which need not be the fastest products); the
+    result is cached under the shape and value type."""
+    import json
+    import sys
+    import types
+    from types import SimpleNamespace as NS
+    from paper_1601_08201_amd import autotune
+    prob = NS(I=1 << 20, J=1 << 21, ny=128, nx=128, Q=128, nnz=1 << 27)
+    fwd_us = {}   # forward product time by (rows, block, slabs): prefer many rows
+    back_us = {}
+
+    def fake_products(p, sched, reps, warmup=10, storage="f32"):
+        f = (sched["fwd_rows_per_wave"], sched["fwd_block_cols"], sched["fwd_slabs"])
+        b = (sched["back_rows_per_wave"], sched["back_block_cols"], sched["back_slabs"])
+        fwd_us[f] = 300.0 - f[0] / 16.0 - f[1] / 1000.0
+        back_us[b] = 300.0 - b[0] / 16.0 - b[1] / 1000.0
+        return fwd_us[f], back_us[b]
+
+    def fake_iteration(p, sched, reps, warmup=10, storage="f32"):
+        # the iteration also pays per slab (ratio and image update partial sums)
+        return (fwd_us[(sched["fwd_rows_per_wave"], sched["fwd_block_cols"], sched["fwd_slabs"])]
+                + back_us[(sched["back_rows_per_wave"], sched["back_block_cols"], sched["back_slabs"])]
+                + 5.0 * (sched["fwd_slabs"] + sched["back_slabs"])) / 1e3
+
+    monkeypatch.setattr(autotune, "_time_schedule", fake_products)
+    monkeypatch.setattr(autotune, "_time_iteration", fake_iteration)
+    monkeypatch.setitem(sys.modules, "torch", types.SimpleNamespace(cuda=types.SimpleNamespace(init=lambda: None)))
+    path = str(tmp_path / "cache.json")
+    best, report = autotune.tune(prob, max_candidates=8, cache_path=path, storage="bf16")
+    timed = [r for r in report if "iteration_ms" in r]
+    assert len(timed) == 4                     # two forward x two back finalists
+    fastest = min(timed, key=lambda r: r["iteration_ms"])
+    assert best == fastest["schedule"]
+    top_f = sorted(fwd_us.values())[:2]
+    assert fwd_us[(best["fwd_rows_per_wave"], best["fwd_block_cols"], best["fwd_slabs"])] in top_f
+    rec = json.load(open(path))[autotune.shape_key(prob.I, prob.ny, prob.nx, prob.Q, prob.nnz, "bf16")]
+    assert rec["schedule"] == best and rec["iteration_ms"] == fastest["iteration_ms"]
