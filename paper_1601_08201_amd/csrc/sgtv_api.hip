@@ -3179,7 +3179,7 @@ struct wsnet_s {
 
 namespace {
 
-constexpr int kLossBlocks = 1024;
+constexpr int kLossBlocks = 4096;   // loss-gradient blocks (FP64 partial sums of the squared error)
 constexpr int kImageBlocks = 64;    // partial sums per image (start images)
 
 __bf16 *bf(const DBuf &b, int64_t off = 0) { return b.as<__bf16>() + off; }
@@ -3212,8 +3212,10 @@ int net_layers(wsnet_s *n, int B, bool training = false) {
                                          training ? bf(n->xt, (l + 1) * 3 * n->max_batch * n->img) : nullptr,
                                          n->stream));
         else
+            // training: only z (the loss kernel forms softplus(z) itself)
             HIP_TRY(sgtv::wsn::conv_softplus(X, bf(n->wf, l * CK), bias, B, n->H, n->W,
-                                             n->z_last.as<float>(), n->out.as<float>(), n->stream));
+                                             n->z_last.as<float>(), training ? nullptr : n->out.as<float>(),
+                                             n->stream));
     }
     return SGTV_OK;
 }
@@ -3421,8 +3423,8 @@ int net_backward(wsnet_s *net, int32_t batch) {
     const int64_t CK = static_cast<int64_t>(net->C) * 9 * net->C;
     if (int e = net_forward(net, batch, true)) return e;
     int cur = 0;
-    HIP_TRY(sgtv::wsn::mse_grad(net->out.as<float>(), net->tgt.as<float>(), net->z_last.as<float>(), cnt,
-                                bf(net->dz[cur]), net->lpart.as<double>(), kLossBlocks, net->stream));
+    HIP_TRY(sgtv::wsn::mse_grad(net->tgt.as<float>(), net->z_last.as<float>(), cnt, bf(net->dz[cur]),
+                                net->lpart.as<double>(), kLossBlocks, net->stream));
     HIP_TRY(sgtv::launch_reduce(net->lpart.as<double>(), kLossBlocks, 1, net->lred.as<double>(), net->stream));
     for (int l = net->L - 1; l >= 0; --l) {
         const __bf16 *X = bf(net->acts, l * net->max_batch * net->img);

@@ -15,6 +15,7 @@ size_t conv_lds_bytes(int W);
 // copies (3*B*H*W*C bf16), ready for the next layer's conv_wgrad
 hipError_t conv_relu(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H, int W,
                      __bf16 *out, __bf16 *xt, hipStream_t st);
+// z = conv(X) + bias (FP32); sp (or nullptr): softplus(z)
 hipError_t conv_softplus(const __bf16 *X, const __bf16 *Wk, const float *bias, int B, int H,
                          int W, float *z, float *sp, hipStream_t st);
 // out = conv(X) masked by mask > 0; dt (or nullptr): the same values channel-major
@@ -39,8 +40,9 @@ hipError_t scale_to_bf16(const float *x, const double *sums, int64_t img, int64_
 // x0 = c_out * s * (ratio ? f : m_b), raised to at least floor * c_out * m_b when floor > 0
 hipError_t start_image(const float *f, const float *s, const double *sums, int64_t img, int64_t n,
                        float c_out, int ratio, float floor, float *x0, hipStream_t st);
-hipError_t mse_grad(const float *out, const float *target, const float *z, int64_t n, __bf16 *dz,
-                    double *partials, int n_blocks, hipStream_t st);
+// dz = bf16(2 (softplus(z) - target) / n * sigmoid(z)), FP64 squared-error partials
+hipError_t mse_grad(const float *target, const float *z, int64_t n, __bf16 *dz, double *partials,
+                    int n_blocks, hipStream_t st);
 // acc[0] += l[0] / cnt, acc[1] += 1 (FP64, one thread)
 hipError_t loss_accumulate(const double *l, double cnt, double *acc, hipStream_t st);
 hipError_t adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,

@@ -260,13 +260,15 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(const __bf16 *__restri
 #pragma unroll 4
                     for (int c = lane; c < 32 * kC / 4; c += 64) {
                         const f32x4 z = *reinterpret_cast<const f32x4 *>(tile + c * 4);
-                        f32x4 sp;
-                        sp[0] = softplusf(z[0]);
-                        sp[1] = softplusf(z[1]);
-                        sp[2] = softplusf(z[2]);
-                        sp[3] = softplusf(z[3]);
                         *reinterpret_cast<f32x4 *>(out_z + hb + c * 4) = z;
-                        *reinterpret_cast<f32x4 *>(out_sp + hb + c * 4) = sp;
+                        if (out_sp) {   // uniform: training leaves softplus(z) to the loss kernel
+                            f32x4 sp;
+                            sp[0] = softplusf(z[0]);
+                            sp[1] = softplusf(z[1]);
+                            sp[2] = softplusf(z[2]);
+                            sp[3] = softplusf(z[3]);
+                            *reinterpret_cast<f32x4 *>(out_sp + hb + c * 4) = sp;
+                        }
                     }
                 }
                 __syncthreads();
@@ -472,9 +474,9 @@ __global__ void k_start_image(const float *__restrict__ f, const float *__restri
     }
 }
 
-// dZ of the last layer: 2 (out - target) / n * softplus'(z); FP64 loss partials
-__global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ out,
-                                                  const float *__restrict__ target,
+// dZ of the last layer: 2 (out - target) / n * softplus'(z) with out =
+// softplus(z) (the same function as the layer's epilogue); FP64 loss partials
+__global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ target,
                                                   const float *__restrict__ z, int64_t n,
                                                   __bf16 *__restrict__ dz,
                                                   double *__restrict__ partials) {
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ out,
     const float inv = 2.0f / static_cast<float>(n);
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * 256) {
-        const float d = out[i] - target[i];
+        const float d = softplusf(z[i]) - target[i];
         acc += static_cast<double>(d) * d;
         dz[i] = static_cast<__bf16>(inv * d * sigmoidf(z[i]));
     }
@@ -627,10 +629,10 @@ hipError_t start_image(const float *f, const float *s, const double *sums, int64
     return hipGetLastError();
 }
 
-hipError_t mse_grad(const float *out, const float *target, const float *z, int64_t n, __bf16 *dz,
-                    double *partials, int n_blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_mse_grad, dim3(static_cast<unsigned>(n_blocks)), dim3(256), 0, st, out,
-                       target, z, n, dz, partials);
+hipError_t mse_grad(const float *target, const float *z, int64_t n, __bf16 *dz, double *partials,
+                    int n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_mse_grad, dim3(static_cast<unsigned>(n_blocks)), dim3(256), 0, st, target, z, n, dz,
+                       partials);
     return hipGetLastError();
 }
 
