@@ -484,9 +484,15 @@ __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ targ
     const float inv = 2.0f / static_cast<float>(n);
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * 256) {
-        const float d = softplusf(z[i]) - target[i];
+        // softplusf(z) and sigmoidf(z) from one exp(-|z|): exp(-z) for z >= 0
+        // and exp(z) below, bit for bit the values of the two functions
+        const float zi = z[i];
+        const float e = expf(-fabsf(zi));
+        const float sp = fmaxf(zi, 0.0f) + log1pf(e);
+        const float sg = zi >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+        const float d = sp - target[i];
         acc += static_cast<double>(d) * d;
-        dz[i] = static_cast<__bf16>(inv * d * sigmoidf(z[i]));
+        dz[i] = static_cast<__bf16>(inv * d * sg);
     }
     block_sum_store(acc, partials + blockIdx.x);
 }
